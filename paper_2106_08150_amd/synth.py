@@ -1,0 +1,295 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+This module only produces bytes: reference genomes as ASCII, taxonomies as
+parent arrays, and read records as ASCII plus offsets. It holds none of the
+classifier's arithmetic (no base codes, k-mers, hashes or sketches), so both
+the HIP path and the CPU oracle can take their inputs from it.
+
+Generator rules (numpy ``Generator(PCG64(seed))`` everywhere):
+
+* bases are i.i.d. uniform over ``ACGT``;
+* a mutated copy substitutes every base independently with probability ``d``
+  by one of the three other letters, chosen uniformly (substitution sites are
+  drawn as geometric gaps, which is the same Bernoulli process);
+* a read picks a genome uniformly, a start uniformly in ``[0, L - len]`` and
+  the reverse strand with probability 1/2 (reverse strand = reverse
+  complement of the ASCII text), then gets substitutions at its error rate;
+* foreign reads are i.i.d. random text that is not drawn from any genome.
+
+The reference sets of the paper (RefSeq 202, AFS 31) and its read sets (HiSeq,
+MiSeq, KAL_D) are not available; these generators stand in for them with the
+shapes given in the evaluation section (read lengths around 100 to 250 bp,
+paired reads of 2 x 101 to 2 x 150 bp, thousands of bacterial-sized genomes).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_LETTERS = np.frombuffer(b"ACGT", dtype=np.uint8)
+# For every letter, the three other letters (substitution targets).
+_OTHER = np.zeros((256, 3), dtype=np.uint8)
+for _c, _o in ((b"A", b"CGT"), (b"C", b"AGT"), (b"G", b"ACT"), (b"T", b"ACG")):
+    _OTHER[_c[0]] = np.frombuffer(_o, dtype=np.uint8)
+# ASCII complement table for the reverse strand of generated text.
+_COMP = np.arange(256, dtype=np.uint8)
+for _a, _b in ((b"A", b"T"), (b"C", b"G"), (b"G", b"C"), (b"T", b"A")):
+    _COMP[_a[0]] = _b[0]
+
+
+def rng_for(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def random_text(rng: np.random.Generator, n: int) -> np.ndarray:
+    """``n`` i.i.d. uniform letters from ACGT as uint8 ASCII."""
+    return _LETTERS[rng.integers(0, 4, size=int(n), dtype=np.uint8)]
+
+
+def substitute(rng: np.random.Generator, text: np.ndarray, d: float) -> np.ndarray:
+    """Copy of ``text`` with each letter replaced w.p. ``d`` by another letter."""
+    out = np.array(text, dtype=np.uint8, copy=True)
+    n = out.size
+    if d <= 0.0 or n == 0:
+        return out
+    # Bernoulli(d) sites as cumulative geometric gaps.
+    est = int(n * d + 10 * np.sqrt(n * d + 1) + 16)
+    pos = np.cumsum(rng.geometric(d, size=est)) - 1
+    while pos.size and pos[-1] < n:  # extend in the (rare) short case
+        more = np.cumsum(rng.geometric(d, size=est)) + pos[-1]
+        pos = np.concatenate([pos, more])
+    pos = pos[pos < n]
+    pick = rng.integers(0, 3, size=pos.size)
+    out[pos] = _OTHER[out[pos], pick]
+    return out
+
+
+def reverse_complement_text(text: np.ndarray) -> np.ndarray:
+    return _COMP[np.asarray(text, dtype=np.uint8)[::-1]]
+
+
+@dataclass
+class Genomes:
+    """Concatenated reference text plus per-genome lengths and taxa."""
+    text: np.ndarray          # uint8 ASCII, all genomes back to back
+    lengths: np.ndarray       # uint64 [n]
+    taxa: np.ndarray          # uint32 [n]
+    parents: np.ndarray       # uint32 [n_nodes], parents[root] == root
+
+    @property
+    def offsets(self) -> np.ndarray:
+        o = np.zeros(self.lengths.size + 1, dtype=np.uint64)
+        np.cumsum(self.lengths, out=o[1:])
+        return o
+
+    def genome(self, i: int) -> np.ndarray:
+        o = self.offsets
+        return self.text[int(o[i]):int(o[i + 1])]
+
+
+@dataclass
+class Reads:
+    """Read records: ASCII text plus u64 offsets.
+
+    Single-end (``paired=False``): record i is ``text[off[i]:off[i+1]]``.
+    Paired (``paired=True``): record i has mate 1 ``text[off[2i]:off[2i+1]]``
+    and mate 2 ``text[off[2i+1]:off[2i+2]]``; an empty mate 2 marks a
+    single-end record inside a paired batch.
+    """
+    text: np.ndarray
+    offsets: np.ndarray
+    paired: bool = False
+    origin: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int64))
+
+    @property
+    def n_records(self) -> int:
+        return (self.offsets.size - 1) // (2 if self.paired else 1)
+
+
+def _pack(chunks: list[np.ndarray]) -> tuple[np.ndarray, np.ndarray]:
+    lens = np.fromiter((c.size for c in chunks), dtype=np.uint64, count=len(chunks))
+    off = np.zeros(len(chunks) + 1, dtype=np.uint64)
+    np.cumsum(lens, out=off[1:])
+    text = np.concatenate(chunks) if chunks else np.zeros(0, np.uint8)
+    return text.astype(np.uint8, copy=False), off
+
+
+# --------------------------------------------------------------------------
+# Tiny configuration: 8 genomes of 100 kbp, root -> 2 genera -> 4 species each.
+# --------------------------------------------------------------------------
+TINY_DIVERGENCE = (0.0, 0.01, 0.025, 0.04, 0.055, 0.07, 0.085, 0.10)
+TINY_PARENTS = np.array([0, 0, 0, 1, 1, 1, 1, 2, 2, 2, 2], dtype=np.uint32)
+
+
+def tiny_genomes(seed: int = 101, length: int = 100_000) -> Genomes:
+    rng = rng_for(seed)
+    g0 = random_text(rng, length)
+    chunks = [g0] + [substitute(rng, g0, d) for d in TINY_DIVERGENCE[1:]]
+    text, off = _pack(chunks)
+    lengths = np.diff(off).astype(np.uint64)
+    taxa = np.arange(3, 3 + len(chunks), dtype=np.uint32)   # genome i -> species 3+i
+    return Genomes(text, lengths, taxa, TINY_PARENTS.copy())
+
+
+def sample_reads(genomes: Genomes, n: int, length: int, seed: int,
+                 error: float = 0.01, foreign: float = 0.0,
+                 chunk: int = 200_000) -> Reads:
+    """``n`` single-end reads of a fixed ``length`` (see the module rules)."""
+    rng = rng_for(seed)
+    off_g = genomes.offsets
+    lens = genomes.lengths.astype(np.int64)
+    ok = np.nonzero(lens >= length)[0]
+    text = np.empty(n * length, dtype=np.uint8)
+    origin = np.empty(n, dtype=np.int64)
+    ar = np.arange(length, dtype=np.int64)
+    for c0 in range(0, n, chunk):
+        m = min(chunk, n - c0)
+        gi = ok[rng.integers(0, ok.size, size=m)]
+        is_foreign = rng.random(m) < foreign
+        start = (rng.random(m) * (lens[gi] - length + 1)).astype(np.int64)
+        rev = rng.random(m) < 0.5
+        idx = (off_g[gi].astype(np.int64) + start)[:, None] + ar[None, :]
+        block = genomes.text[idx]
+        block[rev] = _COMP[block[rev][:, ::-1]]
+        nf = int(is_foreign.sum())
+        if nf:
+            block[is_foreign] = random_text(rng, nf * length).reshape(nf, length)
+        flat = substitute(rng, block.reshape(-1), error)
+        text[c0 * length:(c0 + m) * length] = flat
+        origin[c0:c0 + m] = np.where(is_foreign, -1, gi)
+    offsets = np.arange(n + 1, dtype=np.uint64) * np.uint64(length)
+    return Reads(text, offsets, False, origin)
+
+
+def tiny_reads(genomes: Genomes, n: int = 10_000, seed: int = 102) -> Reads:
+    return sample_reads(genomes, n, 100, seed, error=0.01)
+
+
+# --------------------------------------------------------------------------
+# Clustered reference sets (the "at scale" shape): clusters of mutated copies.
+# --------------------------------------------------------------------------
+def clustered_genomes(n_clusters: int, per_cluster: int, total_bp: float,
+                      seed: int, div_lo: float = 0.02, div_hi: float = 0.15,
+                      median_bp: float = 4e6, sigma: float = 0.4,
+                      clip: tuple[float, float] = (1e6, 1e7),
+                      level1: int | None = None) -> Genomes:
+    """Clusters of mutated copies with log-normal lengths.
+
+    Lengths are log-normal around ``median_bp`` (shape ``sigma``), clipped to
+    ``clip`` and rescaled together so that they sum to about ``total_bp``.
+    Each cluster has a random root as long as its longest member; member ``i``
+    is the root's prefix of its own length with divergence ``U[div_lo,
+    div_hi]``. Taxonomy: root -> ``level1`` nodes -> one node per cluster ->
+    three sub-groups per cluster (members split as evenly as possible) -> one
+    leaf per genome.
+    """
+    rng = rng_for(seed)
+    n = n_clusters * per_cluster
+    raw = np.exp(rng.normal(np.log(median_bp), sigma, size=n))
+    raw = np.clip(raw, clip[0], clip[1])
+    lengths = np.maximum(np.round(raw * (total_bp / raw.sum())), 1).astype(np.int64)
+    level1 = level1 or max(1, n_clusters // 5)
+    # node ids: 0 root | level1 | clusters | 3 per cluster | leaves
+    l1_base = 1
+    cl_base = l1_base + level1
+    sub_base = cl_base + n_clusters
+    leaf_base = sub_base + 3 * n_clusters
+    n_nodes = leaf_base + n
+    parents = np.zeros(n_nodes, dtype=np.uint32)
+    parents[l1_base:cl_base] = 0
+    for c in range(n_clusters):
+        parents[cl_base + c] = l1_base + (c * level1) // n_clusters
+        for j in range(3):
+            parents[sub_base + 3 * c + j] = cl_base + c
+    chunks, taxa = [], np.zeros(n, dtype=np.uint32)
+    for c in range(n_clusters):
+        ids = np.arange(c * per_cluster, (c + 1) * per_cluster)
+        root = random_text(rng, int(lengths[ids].max()))
+        divs = rng.uniform(div_lo, div_hi, size=per_cluster)
+        groups = np.array_split(np.arange(per_cluster), 3)
+        for gidx, grp in enumerate(groups):
+            for m in grp:
+                gid = int(ids[m])
+                chunks.append(substitute(rng, root[:lengths[gid]], float(divs[m])))
+                parents[leaf_base + gid] = sub_base + 3 * c + gidx
+                taxa[gid] = leaf_base + gid
+    text, off = _pack(chunks)
+    return Genomes(text, np.diff(off).astype(np.uint64), taxa, parents)
+
+
+def scale_genomes(seed: int = 201, total_bp: float = 4.0e9) -> Genomes:
+    """1,000 genomes = 100 clusters x 10 (about 4 Gbp), 5-level taxonomy."""
+    return clustered_genomes(100, 10, total_bp, seed, level1=20)
+
+
+def scale_reads(genomes: Genomes, n: int = 10_000_000, seed: int = 202) -> Reads:
+    """150 bp reads, 1% substitutions, 5% foreign."""
+    return sample_reads(genomes, n, 150, seed, error=0.01, foreign=0.05)
+
+
+def mixed_records(genomes: Genomes, n: int, seed: int = 301, error: float = 0.01,
+                  foreign: float = 0.05, chunk: int = 100_000) -> Reads:
+    """Uneven batch in the paired layout.
+
+    Half the records are single-end with length U{50..250} (empty mate 2);
+    half are pairs 2 x 150 from a fragment of length round(N(400, 50))
+    clipped to [150, 700]: mate 1 is the fragment start, mate 2 the reverse
+    complement of the fragment end, on a random fragment strand.
+    """
+    rng = rng_for(seed)
+    off_g = genomes.offsets.astype(np.int64)
+    lens = genomes.lengths.astype(np.int64)
+    pieces: list[np.ndarray] = []
+    origin = np.empty(n, dtype=np.int64)
+    for c0 in range(0, n, chunk):
+        m = min(chunk, n - c0)
+        is_pair = rng.random(m) < 0.5
+        is_foreign = rng.random(m) < foreign
+        se_len = rng.integers(50, 251, size=m)
+        frag = np.clip(np.round(rng.normal(400, 50, size=m)), 150, 700).astype(np.int64)
+        span = np.where(is_pair, frag, se_len)
+        gi = rng.integers(0, lens.size, size=m)
+        gi = np.where(lens[gi] >= span, gi, int(np.argmax(lens)))
+        start = (rng.random(m) * (lens[gi] - span + 1)).astype(np.int64)
+        rev = rng.random(m) < 0.5
+        for r in range(m):
+            L = int(span[r])
+            if is_foreign[r]:
+                frag_txt = random_text(rng, L)
+            else:
+                s0 = int(off_g[gi[r]] + start[r])
+                frag_txt = genomes.text[s0:s0 + L]
+                if rev[r]:
+                    frag_txt = reverse_complement_text(frag_txt)
+            if is_pair[r]:
+                m1 = frag_txt[:150]
+                m2 = reverse_complement_text(frag_txt[L - 150:])
+            else:
+                m1 = frag_txt
+                m2 = frag_txt[:0]
+            pieces.append(substitute(rng, m1, error))
+            pieces.append(substitute(rng, m2, error) if m2.size else m2)
+            origin[c0 + r] = -1 if is_foreign[r] else gi[r]
+    text, off = _pack(pieces)
+    return Reads(text, off, True, origin)
+
+
+def repeated_genome(n_copies: int, length: int, seed: int) -> Genomes:
+    """``n_copies`` identical genomes (stress input for the per-feature cap)."""
+    rng = rng_for(seed)
+    g = random_text(rng, length)
+    text = np.tile(g, n_copies)
+    lengths = np.full(n_copies, length, dtype=np.uint64)
+    parents = np.zeros(1 + n_copies, dtype=np.uint32)
+    taxa = np.arange(1, 1 + n_copies, dtype=np.uint32)
+    return Genomes(text, lengths, taxa, parents)
+
+
+def arrival_trace(n_batches: int, seed: int, lo: float = 1e3, hi: float = 1e6,
+                  rate_hz: float = 100.0) -> tuple[np.ndarray, np.ndarray]:
+    """Poisson arrival times (s) and log-uniform batch sizes (reads)."""
+    rng = rng_for(seed)
+    gaps = rng.exponential(1.0 / rate_hz, size=n_batches)
+    sizes = np.exp(rng.uniform(np.log(lo), np.log(hi), size=n_batches)).astype(np.int64)
+    return np.cumsum(gaps), sizes
