@@ -1,0 +1,185 @@
+/*
+ * mc.h — C ABI of the MI355X minhash metagenomic classifier.
+ *
+ * Method: "MetaCache-GPU: Ultra-Fast Metagenomic Classification" (Kobus,
+ * Mueller, Juenger, Hundt, Schmidt; ICPP'21). Build (Sec. 4.1, Sec. 5.2):
+ * reference sequences are cut into windows of `window` bases overlapping by
+ * k-1; every window is represented by its minhash sketch, the `sketch_size`
+ * smallest distinct hashes h1 of its canonical k-mers (Sec. 2), and every
+ * sketch element is stored in a multi-value hash table as
+ * feature -> location (target id, window id), at most `max_locations` per
+ * feature (Sec. 4.1). Query (Sec. 4.2, Sec. 5.2-5.6): every window of a read
+ * (or read pair) is sketched the same way, the location lists of all sketch
+ * elements are merged and counted per reference window, the best contiguous
+ * window range per target is found with a sliding window, and the read is
+ * labelled from its top hits, by lowest common ancestor when they are close.
+ *
+ * Every compute step runs in the library's HIP kernels on the current device
+ * (gfx950). Functions return MC_OK (0) or a negative MC_ERR_* code; the text
+ * of the last error of the calling thread is available from mc_last_error().
+ * A db handle is not thread-safe: calls on one handle must not overlap.
+ *
+ * Fixed formats:
+ *   base codes     A/a=0, C/c=1, G/g=2, T/t=3; any other byte is invalid and
+ *                  no valid k-mer covers it.
+ *   feature        h1(canonical k-mer), 32 bits; h1 is MurmurHash3's 32-bit
+ *                  finalizer; canonical = min(forward, reverse complement)
+ *                  with the first base most significant.
+ *   location       (target << 18) | window; target < 16383, window < 2^18.
+ *   labels         taxon ids from mc_db_set_taxonomy, or MC_UNCLASSIFIED.
+ */
+#ifndef MC_H
+#define MC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MC_OK               0
+#define MC_ERR_INVALID_ARG (-1)  /* bad pointer, size or parameter           */
+#define MC_ERR_CAPACITY    (-2)  /* target or window id does not fit         */
+#define MC_ERR_OOM         (-3)  /* device or pinned host allocation failed  */
+#define MC_ERR_TABLE_FULL  (-4)  /* probe sequence exhausted (should not occur
+                                    at the library's load factors)           */
+#define MC_ERR_STATE       (-5)  /* call not valid in the handle's state     */
+#define MC_ERR_HIP         (-6)  /* a HIP runtime call failed                */
+#define MC_ERR_LIST        (-7)  /* a record's candidate list exceeded the
+                                    largest supported size (see mc_classify_ex) */
+
+#define MC_UNCLASSIFIED 0xFFFFFFFFu
+#define MC_MAX_TARGETS  16383u
+#define MC_MAX_WINDOWS  262144u
+
+typedef struct mc_db mc_db;
+
+/* Query options (Sec. 4.2, Sec. 5.6, Sec. 6.5).
+ *   top_m       number of top hits kept per record (1..8); the paper uses 2..4.
+ *   min_hits    hit threshold: a record whose best score is below it is
+ *               unclassified.
+ *   hit_diff    if best - second > hit_diff the label is the best target's
+ *               taxon; otherwise the LCA of the taxa of all top hits whose
+ *               score is at least best - hit_diff.
+ *   insert_size fragment length used for pairs: the sliding window spans
+ *               ceil((F-k)/S)+1 reference windows with F = max(l1+l2,
+ *               insert_size) for a pair, F = read length otherwise.
+ *   paired      0: record i is reads[offsets[i], offsets[i+1]).
+ *               1: record i is mate 1 reads[offsets[2i], offsets[2i+1]) and
+ *                  mate 2 reads[offsets[2i+1], offsets[2i+2]); an empty mate
+ *                  marks a single-end record.
+ * Defaults (mc_classify): {4, 4, 0, 0, 0}. */
+typedef struct mc_query_opts {
+    uint32_t top_m;
+    uint32_t min_hits;
+    uint32_t hit_diff;
+    uint32_t insert_size;
+    uint32_t paired;
+} mc_query_opts;
+
+/* One top hit: target id, score (hits summed over the best window range of
+ * that target) and the first window of the range that holds a hit.
+ * Unused entries are {MC_UNCLASSIFIED, 0, 0}. */
+typedef struct mc_tophit {
+    uint32_t target;
+    uint32_t score;
+    uint32_t window_begin;
+} mc_tophit;
+
+typedef struct mc_db_stats {
+    uint64_t n_targets;
+    uint64_t n_windows;        /* windows of all targets added so far       */
+    uint64_t n_pairs_inserted; /* sketch elements inserted, before the cap  */
+    uint64_t n_pairs_stored;   /* valid (feature, location) pairs stored    */
+    uint64_t n_buckets;        /* 16 slots of 8 bytes per bucket            */
+    uint64_t table_bytes;
+    uint64_t n_cap_candidates; /* features re-checked against the cap       */
+    uint64_t probe_sum;        /* sum over inserts of buckets probed - 1    */
+    uint64_t n_rehash;         /* table growths                             */
+} mc_db_stats;
+
+/* Text of the calling thread's last error ("" if none). Never NULL. */
+const char* mc_last_error(void);
+
+/* Create an empty database on the current HIP device.
+ * 1 <= k <= 16; k <= window; S = window - k + 1 <= 256;
+ * 1 <= sketch_size <= min(S, 64); 1 <= max_locations <= 65535.
+ * Returns NULL (and sets mc_last_error) on invalid arguments or failure. */
+mc_db* mc_db_create(uint32_t k, uint32_t window, uint32_t sketch_size,
+                    uint32_t max_locations);
+
+/* Free every device and host resource of the handle. NULL is accepted. */
+int mc_db_destroy(mc_db* db);
+
+/* Size the table for at least n_pairs stored pairs (optional; tables also
+ * grow by themselves). load_factor in (0, 0.9]; 0 selects the default 0.5. */
+int mc_db_reserve(mc_db* db, uint64_t n_pairs, double load_factor);
+
+/* Add n reference sequences (Sec. 4.1). genomes: host bytes, all sequences
+ * back to back (sum of lengths bytes); lengths, taxon_ids: host arrays of n.
+ * Targets get consecutive ids starting at the current target count, in array
+ * order. The caller keeps ownership; the call is synchronous. May be called
+ * again after mc_classify (on-demand addition); new targets always get larger
+ * ids, so the per-feature cap keeps its meaning. On error nothing is added.
+ * MC_ERR_CAPACITY: more than MC_MAX_TARGETS targets in total, or a sequence
+ * with more than MC_MAX_WINDOWS windows. */
+int mc_db_add_targets(mc_db* db, const char* genomes, const uint64_t* lengths,
+                      const uint32_t* taxon_ids, uint32_t n);
+
+/* Same as mc_db_add_targets, but genomes is a device pointer (already
+ * resident in HBM); lengths and taxon_ids stay host arrays. Work is queued on
+ * `stream` (a hipStream_t, NULL = default stream); the call returns after the
+ * stream has finished it. */
+int mc_db_add_targets_device(mc_db* db, const char* genomes_dev, const uint64_t* lengths,
+                             const uint32_t* taxon_ids, uint32_t n, void* stream);
+
+/* Set (or replace with a superset) the taxonomy (Sec. 4.1): parents[i] is the
+ * parent of node i, host array of n_nodes. Exactly one root r with
+ * parents[r] == r; every other chain must reach it (no cycles). */
+int mc_db_set_taxonomy(mc_db* db, const uint32_t* parents, uint32_t n_nodes);
+
+/* Classify n_reads single-end reads with the default options. reads, offsets
+ * (n_reads+1 entries, u64) and out_labels (n_reads) are device pointers owned
+ * by the caller. Asynchronous on `stream` (hipStream_t): labels are valid once
+ * the stream has reached this point. Argument errors are returned at once;
+ * MC_ERR_STATE if a target's taxon is not in the taxonomy. */
+int mc_classify(mc_db* db, const char* reads, const uint64_t* offsets, uint32_t n_reads,
+                uint32_t* out_labels, void* stream);
+
+/* Classify with options (see mc_query_opts). out_top: device array of
+ * n_records * top_m entries, or NULL. Records whose merged candidate list
+ * exceeds 16384 locations (about four windows of 16 features each at the
+ * 254 cap) are labelled MC_UNCLASSIFIED and counted; mc_db_query_status
+ * reports them. */
+int mc_classify_ex(mc_db* db, const char* reads, const uint64_t* offsets, uint32_t n_records,
+                   const mc_query_opts* opts, uint32_t* out_labels, mc_tophit* out_top,
+                   void* stream);
+
+/* Waits for `stream`, then reports (and clears) the number of records since
+ * the last call whose candidate list was too long (MC_ERR_LIST if > 0). */
+int mc_db_query_status(mc_db* db, void* stream, uint64_t* n_too_long);
+
+/* Counters of the handle (synchronous). */
+int mc_db_get_stats(mc_db* db, mc_db_stats* out);
+
+/* Test/inspection export, not part of the hot path: every stored pair whose
+ * feature lies in [feature_lo, feature_hi], sorted by feature then location,
+ * into host arrays of `capacity` entries. *n_out receives the number of pairs
+ * (even when larger than capacity, in which case nothing is written). */
+int mc_db_dump(mc_db* db, uint32_t feature_lo, uint32_t feature_hi, uint32_t* features,
+               uint32_t* locations, uint64_t capacity, uint64_t* n_out);
+
+/* Per-window sketches of n sequences with the handle's k, window and
+ * sketch_size, computed by the same kernel code as the build (device inputs
+ * and outputs; test/inspection export). seqs: device bytes back to back;
+ * lengths: host array of n; out_counts: device u32 per window; out_features:
+ * device u32, sketch_size per window; windows are numbered per sequence in
+ * order, sequence after sequence. Synchronous. */
+int mc_db_sketch(mc_db* db, const char* seqs_dev, const uint64_t* lengths, uint32_t n,
+                 uint32_t* out_counts, uint32_t* out_features, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MC_H */

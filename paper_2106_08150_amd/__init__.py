@@ -1,0 +1,263 @@
+"""MI355X-native minhash metagenomic classifier (MetaCache-GPU method).
+
+Thin Python binding of the C ABI in ``include/mc.h``: argument marshalling
+only; every compute step runs in the HIP kernels of ``libmc.so``. PyTorch is
+used by callers for device memory and streams (``tensor.data_ptr()``,
+``torch.cuda.current_stream().cuda_stream``).
+
+The library is loaded on first use and an error is raised if it has not been
+built (``python -m paper_2106_08150_amd.build`` or ``__graft_entry__.build()``);
+there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmc.so")
+
+MC_OK = 0
+MC_ERR_INVALID_ARG = -1
+MC_ERR_CAPACITY = -2
+MC_ERR_OOM = -3
+MC_ERR_TABLE_FULL = -4
+MC_ERR_STATE = -5
+MC_ERR_HIP = -6
+MC_ERR_LIST = -7
+MC_UNCLASSIFIED = 0xFFFFFFFF
+MC_MAX_TARGETS = 16383
+MC_MAX_WINDOWS = 1 << 18
+
+EXPORTS = [
+    "mc_last_error", "mc_db_create", "mc_db_destroy", "mc_db_reserve", "mc_db_add_targets",
+    "mc_db_add_targets_device", "mc_db_set_taxonomy", "mc_classify", "mc_classify_ex",
+    "mc_db_query_status", "mc_db_get_stats", "mc_db_dump", "mc_db_sketch",
+]
+
+
+class MCError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+class QueryOpts(C.Structure):
+    _fields_ = [("top_m", C.c_uint32), ("min_hits", C.c_uint32), ("hit_diff", C.c_uint32),
+                ("insert_size", C.c_uint32), ("paired", C.c_uint32)]
+
+
+class DbStats(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in (
+        "n_targets", "n_windows", "n_pairs_inserted", "n_pairs_stored", "n_buckets",
+        "table_bytes", "n_cap_candidates", "probe_sum", "n_rehash")]
+
+    def as_dict(self) -> dict:
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libmc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
+                              "(python -m paper_2106_08150_amd.build)")
+        L = C.CDLL(LIB_PATH)
+        u32, u64, vp, i32 = C.c_uint32, C.c_uint64, C.c_void_p, C.c_int
+        L.mc_last_error.restype = C.c_char_p
+        L.mc_last_error.argtypes = []
+        L.mc_db_create.restype = vp
+        L.mc_db_create.argtypes = [u32, u32, u32, u32]
+        L.mc_db_destroy.restype, L.mc_db_destroy.argtypes = i32, [vp]
+        L.mc_db_reserve.restype, L.mc_db_reserve.argtypes = i32, [vp, u64, C.c_double]
+        L.mc_db_add_targets.restype = i32
+        L.mc_db_add_targets.argtypes = [vp, vp, vp, vp, u32]
+        L.mc_db_add_targets_device.restype = i32
+        L.mc_db_add_targets_device.argtypes = [vp, vp, vp, vp, u32, vp]
+        L.mc_db_set_taxonomy.restype, L.mc_db_set_taxonomy.argtypes = i32, [vp, vp, u32]
+        L.mc_classify.restype = i32
+        L.mc_classify.argtypes = [vp, vp, vp, u32, vp, vp]
+        L.mc_classify_ex.restype = i32
+        L.mc_classify_ex.argtypes = [vp, vp, vp, u32, C.POINTER(QueryOpts), vp, vp, vp]
+        L.mc_db_query_status.restype = i32
+        L.mc_db_query_status.argtypes = [vp, vp, C.POINTER(u64)]
+        L.mc_db_get_stats.restype = i32
+        L.mc_db_get_stats.argtypes = [vp, C.POINTER(DbStats)]
+        L.mc_db_dump.restype = i32
+        L.mc_db_dump.argtypes = [vp, u32, u32, vp, vp, u64, C.POINTER(u64)]
+        L.mc_db_sketch.restype = i32
+        L.mc_db_sketch.argtypes = [vp, vp, vp, u32, vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int) -> int:
+    if rc != MC_OK:
+        raise MCError(rc, lib().mc_last_error().decode(errors="replace"))
+    return rc
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _dev_ptr(t) -> int:
+    """Device address of a torch tensor (must live on a HIP device)."""
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+# ---------------------------------------------------------------- C ABI ----
+def mc_db_create(k: int = 16, window: int = 128, sketch_size: int = 16,
+                 max_locations: int = 254) -> int:
+    h = lib().mc_db_create(k, window, sketch_size, max_locations)
+    if not h:
+        raise MCError(MC_ERR_INVALID_ARG, lib().mc_last_error().decode(errors="replace"))
+    return h
+
+
+def mc_db_destroy(db: int) -> None:
+    _check(lib().mc_db_destroy(db))
+
+
+def mc_db_reserve(db: int, n_pairs: int, load_factor: float = 0.0) -> None:
+    _check(lib().mc_db_reserve(db, n_pairs, load_factor))
+
+
+def mc_db_add_targets(db: int, genomes, lengths, taxon_ids) -> None:
+    g = np.ascontiguousarray(genomes, dtype=np.uint8)
+    L = np.ascontiguousarray(lengths, dtype=np.uint64)
+    t = np.ascontiguousarray(taxon_ids, dtype=np.uint32)
+    if L.size != t.size or int(L.sum()) > g.size:
+        raise ValueError("lengths/taxon_ids/genomes sizes disagree")
+    _check(lib().mc_db_add_targets(db, _np_ptr(g), _np_ptr(L), _np_ptr(t), L.size))
+
+
+def mc_db_add_targets_device(db: int, genomes_dev, lengths, taxon_ids, stream=None) -> None:
+    L = np.ascontiguousarray(lengths, dtype=np.uint64)
+    t = np.ascontiguousarray(taxon_ids, dtype=np.uint32)
+    if L.size != t.size or int(L.sum()) > genomes_dev.numel():
+        raise ValueError("lengths/taxon_ids/genomes sizes disagree")
+    _check(lib().mc_db_add_targets_device(db, _dev_ptr(genomes_dev), _np_ptr(L), _np_ptr(t),
+                                          L.size, _stream(stream)))
+
+
+def mc_db_set_taxonomy(db: int, parents) -> None:
+    p = np.ascontiguousarray(parents, dtype=np.uint32)
+    _check(lib().mc_db_set_taxonomy(db, _np_ptr(p), p.size))
+
+
+def mc_classify(db: int, reads, offsets, n_reads: int, out_labels, stream=None) -> None:
+    _check(lib().mc_classify(db, _dev_ptr(reads), _dev_ptr(offsets), n_reads,
+                             _dev_ptr(out_labels), _stream(stream)))
+
+
+def mc_classify_ex(db: int, reads, offsets, n_records: int, opts: QueryOpts, out_labels,
+                   out_top=None, stream=None) -> None:
+    top = _dev_ptr(out_top) if out_top is not None else None
+    _check(lib().mc_classify_ex(db, _dev_ptr(reads), _dev_ptr(offsets), n_records,
+                                C.byref(opts), _dev_ptr(out_labels), top, _stream(stream)))
+
+
+def mc_db_query_status(db: int, stream=None) -> int:
+    n = C.c_uint64(0)
+    rc = lib().mc_db_query_status(db, _stream(stream), C.byref(n))
+    if rc not in (MC_OK, MC_ERR_LIST):
+        _check(rc)
+    return int(n.value)
+
+
+def mc_db_get_stats(db: int) -> dict:
+    s = DbStats()
+    _check(lib().mc_db_get_stats(db, C.byref(s)))
+    return s.as_dict()
+
+
+def mc_db_dump(db: int, lo: int = 0, hi: int = 0xFFFFFFFF) -> tuple[np.ndarray, np.ndarray]:
+    n = C.c_uint64(0)
+    _check(lib().mc_db_dump(db, lo, hi, None, None, 0, C.byref(n)))
+    cap = int(n.value)
+    f = np.zeros(max(cap, 1), np.uint32)
+    l = np.zeros(max(cap, 1), np.uint32)
+    _check(lib().mc_db_dump(db, lo, hi, _np_ptr(f), _np_ptr(l), cap, C.byref(n)))
+    return f[:int(n.value)], l[:int(n.value)]
+
+
+def mc_db_sketch(db: int, seqs_dev, lengths, out_counts, out_features, stream=None) -> None:
+    L = np.ascontiguousarray(lengths, dtype=np.uint64)
+    _check(lib().mc_db_sketch(db, _dev_ptr(seqs_dev), _np_ptr(L), L.size, _dev_ptr(out_counts),
+                              _dev_ptr(out_features), _stream(stream)))
+
+
+# ------------------------------------------------------------ wrapper ----
+class Database:
+    """Owning wrapper of an ``mc_db`` handle with torch-friendly helpers."""
+
+    def __init__(self, k: int = 16, window: int = 128, sketch_size: int = 16,
+                 max_locations: int = 254):
+        self.k, self.window, self.sketch_size, self.max_locations = (
+            k, window, sketch_size, max_locations)
+        self.h = mc_db_create(k, window, sketch_size, max_locations)
+
+    def close(self):
+        if getattr(self, "h", None):
+            mc_db_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def reserve(self, n_pairs: int, load_factor: float = 0.0):
+        mc_db_reserve(self.h, n_pairs, load_factor)
+
+    def add_targets(self, genomes, lengths, taxon_ids):
+        """Host arrays (numpy) or a device uint8 tensor for ``genomes``."""
+        if hasattr(genomes, "is_cuda") and genomes.is_cuda:
+            mc_db_add_targets_device(self.h, genomes, lengths, taxon_ids)
+        else:
+            mc_db_add_targets(self.h, genomes, lengths, taxon_ids)
+
+    def set_taxonomy(self, parents):
+        mc_db_set_taxonomy(self.h, parents)
+
+    def stats(self) -> dict:
+        return mc_db_get_stats(self.h)
+
+    def dump(self, lo: int = 0, hi: int = 0xFFFFFFFF):
+        return mc_db_dump(self.h, lo, hi)
+
+    def classify(self, reads, offsets, n_records: int | None = None, top_m: int = 4,
+                 min_hits: int = 4, hit_diff: int = 0, insert_size: int = 0,
+                 paired: bool = False, with_top: bool = False, stream=None):
+        """Device tensors in, device tensors out (labels int32 viewed as u32)."""
+        import torch
+        if n_records is None:
+            n_records = (offsets.numel() - 1) // (2 if paired else 1)
+        dev = reads.device
+        labels = torch.empty(max(n_records, 1), dtype=torch.int32, device=dev)
+        top = (torch.empty((max(n_records, 1), top_m, 3), dtype=torch.int32, device=dev)
+               if with_top else None)
+        opts = QueryOpts(top_m, min_hits, hit_diff, insert_size, int(paired))
+        mc_classify_ex(self.h, reads, offsets, n_records, opts, labels, top, stream)
+        return (labels[:n_records], top[:n_records] if top is not None else None)

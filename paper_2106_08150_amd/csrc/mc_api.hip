@@ -1,0 +1,589 @@
+// Host side of the C ABI declared in include/mc.h: argument checks, the db
+// handle (device table, targets, taxonomy, per-stream workspaces), table
+// sizing and growth, and the launch sequence of every call.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/mc.h"
+#include "mc_internal.hpp"
+
+using namespace mc;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(e_ == hipErrorOutOfMemory ? MC_ERR_OOM : MC_ERR_HIP, "%s: %s (%s:%d)", \
+                        #expr, hipGetErrorString(e_), __FILE__, __LINE__);               \
+    } while (0)
+
+constexpr double kDefaultLoad = 0.5;
+constexpr uint64_t kMinBuckets = 64;
+constexpr uint64_t kCandCapMax = 1ull << 24;
+
+struct Workspace {
+    uint32_t* queue = nullptr;
+    uint64_t queue_cap = 0;
+    uint32_t* counters = nullptr;   // kNumQueryCounters
+};
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+        else prev = -1;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+struct mc_db {
+    int device = 0;
+    uint32_t k = 16, w = 128, s = 16, cap = 254, S = 113;
+    uint32_t cap_dist = 15;
+    double load = kDefaultLoad;
+    // table
+    unsigned long long* table = nullptr;
+    uint64_t nb = 0;
+    uint64_t slots_used = 0;          // occupied slots (stored + tombstones) since the last rehash
+    unsigned long long* counters = nullptr;   // kNumBuildCounters
+    uint32_t* cand = nullptr;
+    uint64_t cand_cap = 0;
+    // targets
+    std::vector<uint32_t> taxa;
+    uint32_t* d_taxa = nullptr;
+    uint64_t d_taxa_cap = 0;
+    uint64_t n_windows = 0;
+    // taxonomy
+    std::vector<uint32_t> parents;
+    uint32_t* d_parents = nullptr;
+    uint32_t* d_depth = nullptr;
+    // stats
+    mc_db_stats st{};
+    // per-stream query workspaces
+    std::map<hipStream_t, Workspace> ws;
+};
+
+namespace {
+
+uint64_t num_windows(uint64_t len, uint32_t k, uint32_t S) {
+    if (len < k) return 0;
+    return (len - k + 1 + S - 1) / S;
+}
+
+template <typename T>
+int dev_alloc(T** p, uint64_t n) {
+    *p = nullptr;
+    if (n == 0) n = 1;
+    HIP_TRY(hipMalloc((void**)p, n * sizeof(T)));
+    return MC_OK;
+}
+
+// Make room for `extra` more occupied slots at the handle's load factor,
+// re-inserting the current entries into a larger table when needed.
+int ensure_capacity(mc_db* db, uint64_t extra, hipStream_t st) {
+    const double slots_per_bucket = (double)kSlots;
+    uint64_t need = db->slots_used + extra;
+    if (db->table && (double)need <= db->load * slots_per_bucket * (double)db->nb) return MC_OK;
+    uint64_t nb = (uint64_t)std::ceil((double)need / (db->load * slots_per_bucket));
+    if (db->table) nb = std::max<uint64_t>(nb, db->nb + db->nb / 2);   // grow by >= 1.5x
+    nb = std::max<uint64_t>(nb, kMinBuckets);
+    unsigned long long* t = nullptr;
+    int rc = dev_alloc(&t, nb * kSlots);
+    if (rc) return rc;
+    HIP_TRY(launch_fill_u64(t, nb * kSlots, ~0ull, st));
+    if (db->table) {
+        HIP_TRY(launch_fill_u64(db->counters, kNumBuildCounters, 0ull, st));
+        HIP_TRY(launch_rehash(db->table, db->nb, t, nb, db->counters, st));
+        unsigned long long c[kNumBuildCounters];
+        HIP_TRY(hipMemcpyAsync(c, db->counters, sizeof c, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (c[kCntFull]) {
+            (void)hipFree(t);
+            return fail(MC_ERR_TABLE_FULL, "rehash found no free slot for %llu entries",
+                        (unsigned long long)c[kCntFull]);
+        }
+        HIP_TRY(hipFree(db->table));
+        db->slots_used = c[kCntMoved];
+        db->st.n_rehash += 1;
+    }
+    db->table = t;
+    db->nb = nb;
+    return MC_OK;
+}
+
+int upload_taxa(mc_db* db, hipStream_t st) {
+    uint64_t n = db->taxa.size();
+    if (n > db->d_taxa_cap) {
+        uint32_t* p = nullptr;
+        uint64_t c = std::max<uint64_t>(n, db->d_taxa_cap * 2);
+        int rc = dev_alloc(&p, c);
+        if (rc) return rc;
+        if (db->d_taxa) HIP_TRY(hipFree(db->d_taxa));
+        db->d_taxa = p;
+        db->d_taxa_cap = c;
+    }
+    if (n) HIP_TRY(hipMemcpyAsync(db->d_taxa, db->taxa.data(), n * 4, hipMemcpyHostToDevice, st));
+    return MC_OK;
+}
+
+// Shared by the host and device entry points: genomes is a device pointer.
+int add_targets_dev(mc_db* db, const uint8_t* genomes, const uint64_t* lengths,
+                    const uint32_t* taxa, uint32_t n, hipStream_t st) {
+    if (n == 0) return MC_OK;
+    if ((uint64_t)db->taxa.size() + n > MC_MAX_TARGETS)
+        return fail(MC_ERR_CAPACITY, "at most %u targets (have %zu, adding %u)", MC_MAX_TARGETS,
+                    db->taxa.size(), n);
+    std::vector<TargetDesc> td(n);
+    std::vector<uint64_t> tile_first(n + 1, 0);
+    uint64_t off = 0, wins = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        uint64_t nw = num_windows(lengths[i], db->k, db->S);
+        if (nw > MC_MAX_WINDOWS)
+            return fail(MC_ERR_CAPACITY, "sequence %u has %llu windows (max %u)", i,
+                        (unsigned long long)nw, MC_MAX_WINDOWS);
+        td[i] = TargetDesc{off, lengths[i], wins, (uint32_t)db->taxa.size() + i, (uint32_t)nw};
+        tile_first[i + 1] = tile_first[i] + (nw + kTileWindows - 1) / kTileWindows;
+        off += lengths[i];
+        wins += nw;
+    }
+    const uint64_t upper = wins * db->s;
+    int rc = ensure_capacity(db, upper, st);
+    if (rc) return rc;
+    uint64_t cand_need = std::min<uint64_t>(std::max<uint64_t>(upper, 1), kCandCapMax);
+    if (cand_need > db->cand_cap) {
+        if (db->cand) HIP_TRY(hipFree(db->cand));
+        db->cand = nullptr;
+        db->cand_cap = 0;
+        rc = dev_alloc(&db->cand, cand_need);
+        if (rc) return rc;
+        db->cand_cap = cand_need;
+    }
+    TargetDesc* d_td = nullptr;
+    uint64_t* d_tf = nullptr;
+    rc = dev_alloc(&d_td, n);
+    if (rc) return rc;
+    rc = dev_alloc(&d_tf, n + 1);
+    if (rc) { (void)hipFree(d_td); return rc; }
+    struct Free {
+        void* a; void* b;
+        ~Free() { (void)hipFree(a); (void)hipFree(b); }
+    } guard{d_td, d_tf};
+    HIP_TRY(hipMemcpyAsync(d_td, td.data(), n * sizeof(TargetDesc), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(d_tf, tile_first.data(), (n + 1) * 8, hipMemcpyHostToDevice, st));
+    HIP_TRY(launch_fill_u64(db->counters, kNumBuildCounters, 0ull, st));
+
+    BuildArgs a{};
+    a.text = genomes;
+    a.text_len = off;
+    a.targets = d_td;
+    a.n_targets = n;
+    a.tile_first = d_tf;
+    a.n_tiles = tile_first[n];
+    a.k = db->k; a.w = db->w; a.S = db->S; a.s = db->s;
+    a.table = db->table;
+    a.nb = db->nb;
+    a.cap_dist = db->cap_dist;
+    a.cand = db->cand;
+    a.cand_cap = db->cand_cap;
+    a.counters = db->counters;
+    HIP_TRY(launch_build(a, true, st));
+    unsigned long long c[kNumBuildCounters];
+    HIP_TRY(hipMemcpyAsync(c, db->counters, sizeof c, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (c[kCntFull]) return fail(MC_ERR_TABLE_FULL, "%llu inserts found no free slot",
+                                 (unsigned long long)c[kCntFull]);
+    if (c[kCntCand] <= db->cand_cap) {
+        HIP_TRY(launch_cap_finalize(db->table, db->nb, db->cap, db->cand, c[kCntCand], st));
+    } else {
+        HIP_TRY(launch_cap_scan(db->table, db->nb, db->cap, db->cap_dist, st));
+    }
+    for (uint32_t i = 0; i < n; ++i) db->taxa.push_back(taxa[i]);
+    rc = upload_taxa(db, st);
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(st));
+    db->slots_used += c[kCntInserted];
+    db->n_windows += wins;
+    db->st.n_pairs_inserted += c[kCntInserted];
+    db->st.probe_sum += c[kCntProbe];
+    db->st.n_cap_candidates += c[kCntCand];
+    return MC_OK;
+}
+
+int check_db(mc_db* db) {
+    if (!db) return fail(MC_ERR_INVALID_ARG, "db is NULL");
+    return MC_OK;
+}
+
+Workspace* workspace(mc_db* db, hipStream_t st, uint64_t n_records, int* rc) {
+    Workspace& w = db->ws[st];
+    *rc = MC_OK;
+    if (!w.counters) {
+        if ((*rc = dev_alloc(&w.counters, kNumQueryCounters))) return nullptr;
+        if (launch_fill_u32(w.counters, kNumQueryCounters, 0u, st) != hipSuccess) {
+            *rc = fail(MC_ERR_HIP, "workspace init failed");
+            return nullptr;
+        }
+    }
+    if (n_records > w.queue_cap) {
+        if (w.queue) (void)hipFree(w.queue);
+        w.queue = nullptr;
+        w.queue_cap = 0;
+        uint64_t c = std::max<uint64_t>(n_records, 1024);
+        if ((*rc = dev_alloc(&w.queue, c))) return nullptr;
+        w.queue_cap = c;
+    }
+    return &w;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mc_last_error(void) { return g_err.c_str(); }
+
+mc_db* mc_db_create(uint32_t k, uint32_t window, uint32_t sketch_size, uint32_t max_locations) {
+    if (k < 1 || k > 16 || window < k || window - k + 1 > 256 || sketch_size < 1 ||
+        sketch_size > 64 || sketch_size > window - k + 1 || max_locations < 1 ||
+        max_locations > 65535) {
+        fail(MC_ERR_INVALID_ARG,
+             "invalid parameters k=%u window=%u sketch_size=%u max_locations=%u", k, window,
+             sketch_size, max_locations);
+        return nullptr;
+    }
+    mc_db* db = new mc_db();
+    if (hipGetDevice(&db->device) != hipSuccess) {
+        fail(MC_ERR_HIP, "no HIP device");
+        delete db;
+        return nullptr;
+    }
+    db->k = k; db->w = window; db->s = sketch_size; db->cap = max_locations;
+    db->S = window - k + 1;
+    // a feature with more than `cap` entries spans at least ceil((cap+1)/16)
+    // buckets of its chain, so one of its inserts lands this far or farther
+    db->cap_dist = (max_locations + 1 + kSlots - 1) / kSlots - 1;
+    if (dev_alloc(&db->counters, kNumBuildCounters) || ensure_capacity(db, 0, nullptr) ||
+        hipDeviceSynchronize() != hipSuccess) {
+        std::string e = g_err;
+        mc_db_destroy(db);
+        g_err = e.empty() ? "allocation failed" : e;
+        return nullptr;
+    }
+    return db;
+}
+
+int mc_db_destroy(mc_db* db) {
+    if (!db) return MC_OK;
+    DeviceGuard dg(db->device);
+    (void)hipDeviceSynchronize();
+    for (auto& kv : db->ws) {
+        (void)hipFree(kv.second.queue);
+        (void)hipFree(kv.second.counters);
+    }
+    (void)hipFree(db->table);
+    (void)hipFree(db->counters);
+    (void)hipFree(db->cand);
+    (void)hipFree(db->d_taxa);
+    (void)hipFree(db->d_parents);
+    (void)hipFree(db->d_depth);
+    delete db;
+    return MC_OK;
+}
+
+int mc_db_reserve(mc_db* db, uint64_t n_pairs, double load_factor) {
+    if (int rc = check_db(db)) return rc;
+    if (load_factor < 0.0 || load_factor > 0.9 || std::isnan(load_factor))
+        return fail(MC_ERR_INVALID_ARG, "load_factor %g not in (0, 0.9]", load_factor);
+    DeviceGuard dg(db->device);
+    if (load_factor > 0.0) db->load = load_factor;
+    uint64_t have = db->slots_used;
+    uint64_t extra = n_pairs > have ? n_pairs - have : 0;
+    int rc = ensure_capacity(db, extra, nullptr);
+    if (rc) return rc;
+    HIP_TRY(hipDeviceSynchronize());
+    return MC_OK;
+}
+
+int mc_db_add_targets(mc_db* db, const char* genomes, const uint64_t* lengths,
+                      const uint32_t* taxon_ids, uint32_t n) {
+    if (int rc = check_db(db)) return rc;
+    if (n && (!lengths || !taxon_ids)) return fail(MC_ERR_INVALID_ARG, "NULL array");
+    uint64_t total = 0;
+    for (uint32_t i = 0; i < n; ++i) total += lengths[i];
+    if (total && !genomes) return fail(MC_ERR_INVALID_ARG, "genomes is NULL");
+    DeviceGuard dg(db->device);
+    uint8_t* d = nullptr;
+    int rc = dev_alloc(&d, total + 16);
+    if (rc) return rc;
+    hipError_t e = total ? hipMemcpy(d, genomes, total, hipMemcpyHostToDevice) : hipSuccess;
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return fail(MC_ERR_HIP, "copy of genomes failed: %s", hipGetErrorString(e));
+    }
+    rc = add_targets_dev(db, d, lengths, taxon_ids, n, nullptr);
+    (void)hipFree(d);
+    return rc;
+}
+
+int mc_db_add_targets_device(mc_db* db, const char* genomes_dev, const uint64_t* lengths,
+                             const uint32_t* taxon_ids, uint32_t n, void* stream) {
+    if (int rc = check_db(db)) return rc;
+    if (n && (!lengths || !taxon_ids)) return fail(MC_ERR_INVALID_ARG, "NULL array");
+    uint64_t total = 0;
+    for (uint32_t i = 0; i < n; ++i) total += lengths[i];
+    if (total && !genomes_dev) return fail(MC_ERR_INVALID_ARG, "genomes_dev is NULL");
+    DeviceGuard dg(db->device);
+    return add_targets_dev(db, reinterpret_cast<const uint8_t*>(genomes_dev), lengths, taxon_ids,
+                           n, static_cast<hipStream_t>(stream));
+}
+
+int mc_db_set_taxonomy(mc_db* db, const uint32_t* parents, uint32_t n_nodes) {
+    if (int rc = check_db(db)) return rc;
+    if (!parents || n_nodes == 0) return fail(MC_ERR_INVALID_ARG, "empty taxonomy");
+    uint32_t roots = 0;
+    for (uint32_t i = 0; i < n_nodes; ++i) {
+        if (parents[i] >= n_nodes)
+            return fail(MC_ERR_INVALID_ARG, "parent of node %u out of range", i);
+        roots += parents[i] == i;
+    }
+    if (roots != 1) return fail(MC_ERR_INVALID_ARG, "taxonomy has %u roots (need 1)", roots);
+    // depth by walking up with memoisation; a walk longer than n_nodes is a cycle
+    std::vector<uint32_t> depth(n_nodes, 0xFFFFFFFFu);
+    std::vector<uint32_t> path;
+    for (uint32_t i = 0; i < n_nodes; ++i) {
+        uint32_t x = i;
+        path.clear();
+        while (depth[x] == 0xFFFFFFFFu && parents[x] != x) {
+            path.push_back(x);
+            if (path.size() > n_nodes) return fail(MC_ERR_INVALID_ARG, "taxonomy has a cycle");
+            x = parents[x];
+        }
+        uint32_t d = parents[x] == x && depth[x] == 0xFFFFFFFFu ? 0 : depth[x];
+        depth[x] = d;
+        for (size_t p = path.size(); p-- > 0;) depth[path[p]] = ++d;
+    }
+    DeviceGuard dg(db->device);
+    uint32_t *dp = nullptr, *dd = nullptr;
+    int rc = dev_alloc(&dp, n_nodes);
+    if (rc) return rc;
+    rc = dev_alloc(&dd, n_nodes);
+    if (rc) { (void)hipFree(dp); return rc; }
+    hipError_t e1 = hipMemcpy(dp, parents, n_nodes * 4ull, hipMemcpyHostToDevice);
+    hipError_t e2 = hipMemcpy(dd, depth.data(), n_nodes * 4ull, hipMemcpyHostToDevice);
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+        (void)hipFree(dp);
+        (void)hipFree(dd);
+        return fail(MC_ERR_HIP, "taxonomy upload failed");
+    }
+    HIP_TRY(hipDeviceSynchronize());   // no classify may still read the old arrays
+    (void)hipFree(db->d_parents);
+    (void)hipFree(db->d_depth);
+    db->d_parents = dp;
+    db->d_depth = dd;
+    db->parents.assign(parents, parents + n_nodes);
+    return MC_OK;
+}
+
+int mc_classify_ex(mc_db* db, const char* reads, const uint64_t* offsets, uint32_t n_records,
+                   const mc_query_opts* opts, uint32_t* out_labels, mc_tophit* out_top,
+                   void* stream) {
+    if (int rc = check_db(db)) return rc;
+    if (!opts) return fail(MC_ERR_INVALID_ARG, "opts is NULL");
+    if (opts->top_m < 1 || opts->top_m > kMaxTopM)
+        return fail(MC_ERR_INVALID_ARG, "top_m %u not in [1, %u]", opts->top_m, kMaxTopM);
+    if (opts->paired > 1) return fail(MC_ERR_INVALID_ARG, "paired must be 0 or 1");
+    if (n_records == 0) return MC_OK;
+    if (!reads || !offsets || !out_labels) return fail(MC_ERR_INVALID_ARG, "NULL pointer");
+    if (!db->taxa.empty()) {
+        if (db->parents.empty()) return fail(MC_ERR_STATE, "taxonomy not set");
+        for (size_t t = 0; t < db->taxa.size(); ++t)
+            if (db->taxa[t] >= db->parents.size())
+                return fail(MC_ERR_STATE, "target %zu has taxon %u outside the taxonomy", t,
+                            db->taxa[t]);
+    }
+    DeviceGuard dg(db->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int rc = 0;
+    Workspace* w = workspace(db, st, n_records, &rc);
+    if (!w) return rc;
+    HIP_TRY(launch_fill_u32(w->counters + kQOverflow, 1, 0u, st));
+    QueryArgs a{};
+    a.table = db->table;
+    a.nb = db->nb;
+    a.reads = reinterpret_cast<const uint8_t*>(reads);
+    a.offsets = offsets;
+    a.n_records = n_records;
+    a.paired = opts->paired;
+    a.k = db->k; a.w = db->w; a.S = db->S; a.s = db->s;
+    a.top_m = opts->top_m;
+    a.min_hits = opts->min_hits;
+    a.hit_diff = opts->hit_diff;
+    a.insert_size = opts->insert_size;
+    a.target_taxon = db->d_taxa;
+    a.parents = db->d_parents;
+    a.depth = db->d_depth;
+    a.out_labels = out_labels;
+    a.out_top = reinterpret_cast<uint32_t*>(out_top);
+    a.queue = w->queue;
+    a.counters = w->counters;
+    HIP_TRY(launch_classify(a, st));
+    return MC_OK;
+}
+
+int mc_classify(mc_db* db, const char* reads, const uint64_t* offsets, uint32_t n_reads,
+                uint32_t* out_labels, void* stream) {
+    mc_query_opts o{4, 4, 0, 0, 0};
+    return mc_classify_ex(db, reads, offsets, n_reads, &o, out_labels, nullptr, stream);
+}
+
+int mc_db_query_status(mc_db* db, void* stream, uint64_t* n_too_long) {
+    if (int rc = check_db(db)) return rc;
+    DeviceGuard dg(db->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipStreamSynchronize(st));
+    uint64_t n = 0;
+    auto it = db->ws.find(st);
+    if (it != db->ws.end() && it->second.counters) {
+        uint32_t c = 0;
+        HIP_TRY(hipMemcpy(&c, it->second.counters + kQTooLong, 4, hipMemcpyDeviceToHost));
+        HIP_TRY(launch_fill_u32(it->second.counters + kQTooLong, 1, 0u, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        n = c;
+    }
+    if (n_too_long) *n_too_long = n;
+    if (n) return fail(MC_ERR_LIST, "%llu records had too many candidate locations",
+                       (unsigned long long)n);
+    return MC_OK;
+}
+
+int mc_db_get_stats(mc_db* db, mc_db_stats* out) {
+    if (int rc = check_db(db)) return rc;
+    if (!out) return fail(MC_ERR_INVALID_ARG, "out is NULL");
+    DeviceGuard dg(db->device);
+    unsigned long long* cnt = nullptr;
+    int rc = dev_alloc(&cnt, 1);
+    if (rc) return rc;
+    unsigned long long stored = 0;
+    hipError_t e = launch_fill_u64(cnt, 1, 0ull, nullptr);
+    if (e == hipSuccess) e = launch_count_valid(db->table, db->nb, cnt, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(&stored, cnt, 8, hipMemcpyDeviceToHost);
+    (void)hipFree(cnt);
+    if (e != hipSuccess) return fail(MC_ERR_HIP, "stats: %s", hipGetErrorString(e));
+    *out = db->st;
+    out->n_targets = db->taxa.size();
+    out->n_windows = db->n_windows;
+    out->n_pairs_stored = stored;
+    out->n_buckets = db->nb;
+    out->table_bytes = db->nb * kSlots * 8;
+    return MC_OK;
+}
+
+int mc_db_dump(mc_db* db, uint32_t feature_lo, uint32_t feature_hi, uint32_t* features,
+               uint32_t* locations, uint64_t capacity, uint64_t* n_out) {
+    if (int rc = check_db(db)) return rc;
+    if (!n_out || (capacity && (!features || !locations)))
+        return fail(MC_ERR_INVALID_ARG, "NULL output");
+    DeviceGuard dg(db->device);
+    unsigned long long *cnt = nullptr, *buf = nullptr;
+    int rc = dev_alloc(&cnt, 1);
+    if (rc) return rc;
+    rc = dev_alloc(&buf, std::max<uint64_t>(capacity, 1));
+    if (rc) { (void)hipFree(cnt); return rc; }
+    unsigned long long n = 0;
+    std::vector<unsigned long long> host;
+    hipError_t e = launch_fill_u64(cnt, 1, 0ull, nullptr);
+    if (e == hipSuccess) e = launch_dump(db->table, db->nb, feature_lo, feature_hi, buf, capacity,
+                                         cnt, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(&n, cnt, 8, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && n <= capacity && n) {
+        host.resize(n);
+        e = hipMemcpy(host.data(), buf, n * 8, hipMemcpyDeviceToHost);
+    }
+    (void)hipFree(cnt);
+    (void)hipFree(buf);
+    if (e != hipSuccess) return fail(MC_ERR_HIP, "dump: %s", hipGetErrorString(e));
+    *n_out = n;
+    if (n <= capacity) {
+        std::sort(host.begin(), host.end());   // export order: feature, then location
+        for (uint64_t i = 0; i < n; ++i) {
+            features[i] = (uint32_t)(host[i] >> 32);
+            locations[i] = (uint32_t)host[i];
+        }
+    }
+    return MC_OK;
+}
+
+int mc_db_sketch(mc_db* db, const char* seqs_dev, const uint64_t* lengths, uint32_t n,
+                 uint32_t* out_counts, uint32_t* out_features, void* stream) {
+    if (int rc = check_db(db)) return rc;
+    if (n == 0) return MC_OK;
+    if (!seqs_dev || !lengths || !out_counts || !out_features)
+        return fail(MC_ERR_INVALID_ARG, "NULL pointer");
+    DeviceGuard dg(db->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    std::vector<TargetDesc> td(n);
+    std::vector<uint64_t> tile_first(n + 1, 0);
+    uint64_t off = 0, wins = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        uint64_t nw = num_windows(lengths[i], db->k, db->S);
+        if (nw > 0xFFFFFFFFull) return fail(MC_ERR_CAPACITY, "sequence too long");
+        td[i] = TargetDesc{off, lengths[i], wins, i, (uint32_t)nw};
+        tile_first[i + 1] = tile_first[i] + (nw + kTileWindows - 1) / kTileWindows;
+        off += lengths[i];
+        wins += nw;
+    }
+    TargetDesc* d_td = nullptr;
+    uint64_t* d_tf = nullptr;
+    int rc = dev_alloc(&d_td, n);
+    if (rc) return rc;
+    rc = dev_alloc(&d_tf, n + 1);
+    if (rc) { (void)hipFree(d_td); return rc; }
+    BuildArgs a{};
+    a.text = reinterpret_cast<const uint8_t*>(seqs_dev);
+    a.text_len = off;
+    a.targets = d_td;
+    a.n_targets = n;
+    a.tile_first = d_tf;
+    a.n_tiles = tile_first[n];
+    a.k = db->k; a.w = db->w; a.S = db->S; a.s = db->s;
+    a.out_counts = out_counts;
+    a.out_feats = out_features;
+    hipError_t e = hipMemcpyAsync(d_td, td.data(), n * sizeof(TargetDesc), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_tf, tile_first.data(), (n + 1) * 8, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = launch_build(a, false, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(d_td);
+    (void)hipFree(d_tf);
+    if (e != hipSuccess) return fail(MC_ERR_HIP, "sketch: %s", hipGetErrorString(e));
+    return MC_OK;
+}
+
+}  // extern "C"

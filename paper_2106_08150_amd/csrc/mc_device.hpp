@@ -1,0 +1,289 @@
+// Device building blocks of the minhash classifier (gfx950, wave64).
+//
+// Everything here runs inside the library's kernels: 2-bit encoding of ASCII
+// text staged in LDS, canonical k-mer extraction by funnel shifts, h1, a
+// register bitonic sort across the 64 lanes of a wave, bottom-s selection with
+// ballots, and the bucketed open-addressing table (16 x 64-bit slots = one
+// 128-byte line per bucket).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mc_internal.hpp"
+
+namespace mc {
+
+constexpr uint32_t kWindowBits = 18;
+constexpr uint32_t kWindowMask = (1u << kWindowBits) - 1;
+constexpr uint32_t kNone = 0xFFFFFFFFu;        // unclassified label / unused hit
+constexpr uint32_t kBadLoc = 0xFFFFFFFFu;      // never a real location
+constexpr uint64_t kEmpty = ~0ull;             // empty table slot
+
+constexpr int kWave = 64;
+
+// ------------------------------------------------------------------ lanes --
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return (uint64_t)__ballot(p); }
+
+// Number of set bits of `mask` in lanes below the calling lane.
+__device__ __forceinline__ uint32_t rank_below(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ uint32_t popc64(uint64_t m) { return (uint32_t)__popcll(m); }
+
+__device__ __forceinline__ uint32_t shfl_idx(uint32_t v, int src) {
+    return (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)v);
+}
+
+__device__ __forceinline__ uint32_t shfl_xor(uint32_t v, int m) {
+    return shfl_idx(v, lane_id() ^ m);
+}
+
+__device__ __forceinline__ uint32_t uniform(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+    uint32_t lo = uniform((uint32_t)v), hi = uniform((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+#pragma unroll
+    for (int m = 1; m < kWave; m <<= 1) {
+        uint32_t lo = shfl_xor((uint32_t)v, m), hi = shfl_xor((uint32_t)(v >> 32), m);
+        uint64_t o = ((uint64_t)hi << 32) | lo;
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// Orders LDS accesses of different lanes of one wave (LDS executes a wave's
+// operations in order; this keeps the compiler from moving them across).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---------------------------------------------------------------- mixers --
+// h1: MurmurHash3's 32-bit finalizer, a bijection on 32-bit words.
+__device__ __forceinline__ uint32_t h1(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x85ebca6bu;
+    x ^= x >> 13;
+    x *= 0xc2b2ae35u;
+    x ^= x >> 16;
+    return x;
+}
+
+// Slot hash h2 (Sec. 4.1 uses a second hash so that the skewed sketch values
+// spread over the table): SplitMix64's finalizer of the feature.
+__device__ __forceinline__ uint64_t h2(uint32_t f) {
+    uint64_t z = (uint64_t)f + 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint64_t home_bucket(uint32_t f, uint64_t nb) {
+    return __umul64hi(h2(f), nb);
+}
+
+__device__ __forceinline__ uint64_t next_bucket(uint64_t b, uint64_t nb) {
+    return b + 1 == nb ? 0 : b + 1;
+}
+
+// ------------------------------------------------------------- encoding --
+// 16 bases packed as 2-bit codes (first base in bits 31..30) plus a 16-bit
+// invalid mask (first base in bit 15). A=0 C=1 G=2 T=3, case-insensitive;
+// every other byte is invalid.
+struct Word {
+    uint32_t code;
+    uint32_t mask;
+};
+
+__device__ __forceinline__ uint32_t zero_bytes(uint32_t y) {   // 0x80 where byte == 0
+    uint32_t t = (y & 0x7F7F7F7Fu) + 0x7F7F7F7Fu;
+    return ~(t | y | 0x7F7F7F7Fu);
+}
+
+// Encode 4 ASCII bytes (byte 0 = first base): 8 code bits and 4 mask bits.
+__device__ __forceinline__ void encode4(uint32_t x, uint32_t& c8, uint32_t& m4) {
+    uint32_t l = x | 0x20202020u;
+    uint32_t ok = zero_bytes(l ^ 0x61616161u) | zero_bytes(l ^ 0x63636363u) |
+                  zero_bytes(l ^ 0x67676767u) | zero_bytes(l ^ 0x74747474u);
+    uint32_t g = (l >> 1) & 0x03030303u;          // a0 c1 g3 t2
+    uint32_t cd = g ^ ((g >> 1) & 0x01010101u);    // a0 c1 g2 t3
+    cd &= (ok >> 7) * 3u;
+    c8 = ((cd & 0xFFu) << 6) | (((cd >> 8) & 0xFFu) << 4) | (((cd >> 16) & 0xFFu) << 2) |
+         (cd >> 24);
+    uint32_t bad = ~ok & 0x80808080u;
+    m4 = (((bad >> 7) & 1u) << 3) | (((bad >> 15) & 1u) << 2) | (((bad >> 23) & 1u) << 1) |
+         (bad >> 31);
+}
+
+__device__ __forceinline__ Word encode16(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3) {
+    uint32_t c0, c1, c2, c3, m0, m1, m2, m3;
+    encode4(x0, c0, m0);
+    encode4(x1, c1, m1);
+    encode4(x2, c2, m2);
+    encode4(x3, c3, m3);
+    Word w;
+    w.code = (c0 << 24) | (c1 << 16) | (c2 << 8) | c3;
+    w.mask = (m0 << 12) | (m1 << 8) | (m2 << 4) | m3;
+    return w;
+}
+
+// Word covering absolute bytes [a, a+16), a 16-byte aligned. Bytes outside
+// [vlo, vhi) are not read and count as invalid.
+__device__ __forceinline__ Word load_word(uintptr_t a, uintptr_t vlo, uintptr_t vhi) {
+    if (a >= vlo && a + 16 <= vhi) {
+        uint4 v = *reinterpret_cast<const uint4*>(a);
+        return encode16(v.x, v.y, v.z, v.w);
+    }
+    uint32_t x[4] = {0x4E4E4E4Eu, 0x4E4E4E4Eu, 0x4E4E4E4Eu, 0x4E4E4E4Eu};   // "NNNN"
+    for (int i = 0; i < 16; ++i) {
+        uintptr_t p = a + (uintptr_t)i;
+        if (p >= vlo && p < vhi) {
+            uint32_t b = *reinterpret_cast<const uint8_t*>(p);
+            x[i >> 2] = (x[i >> 2] & ~(0xFFu << (8 * (i & 3)))) | (b << (8 * (i & 3)));
+        }
+    }
+    return encode16(x[0], x[1], x[2], x[3]);
+}
+
+// Canonical k-mer starting x bases after the first staged word (k <= 16).
+// Returns false if any of its bases is invalid.
+__device__ __forceinline__ bool kmer_at(const Word* W, uint32_t x, uint32_t k, uint32_t& canon) {
+    uint32_t q = x >> 4, o = x & 15u;
+    Word a = W[q], b = W[q + 1];
+    uint64_t v = ((uint64_t)a.code << 32) | b.code;
+    uint32_t fwd = (uint32_t)((v << (2 * o)) >> (64 - 2 * k));
+    uint32_t m = (a.mask << 16) | b.mask;
+    bool bad = ((m << o) >> (32 - k)) != 0u;
+    // reverse complement: complement, align to the top, reverse 2-bit groups
+    uint32_t r = __builtin_bitreverse32((~fwd) << (32 - 2 * k));
+    r = ((r >> 1) & 0x55555555u) | ((r & 0x55555555u) << 1);
+    canon = fwd < r ? fwd : r;
+    return !bad;
+}
+
+// ------------------------------------------------------- bitonic in regs --
+// Ascending sort of 64*KPL keys held KPL per lane; element index r*64 + lane.
+template <int KPL>
+__device__ __forceinline__ void wave_sort(uint32_t (&v)[KPL]) {
+    constexpr int N = kWave * KPL;
+    const int lane = lane_id();
+#pragma unroll
+    for (int size = 2; size <= N; size <<= 1) {
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            if (stride >= kWave) {
+                const int rs = stride / kWave;
+#pragma unroll
+                for (int r = 0; r < KPL; ++r) {
+                    const int p = r ^ rs;
+                    if (p > r) {
+                        const bool asc = ((r * kWave) & size) == 0;
+                        uint32_t a = v[r], b = v[p];
+                        uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
+                        v[r] = asc ? lo : hi;
+                        v[p] = asc ? hi : lo;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < KPL; ++r) {
+                    const int e = r * kWave + lane;
+                    uint32_t o = shfl_xor(v[r], stride);
+                    const bool asc = (e & size) == 0;
+                    const bool lower = (lane & stride) == 0;
+                    uint32_t lo = v[r] < o ? v[r] : o, hi = v[r] < o ? o : v[r];
+                    v[r] = (asc == lower) ? lo : hi;
+                }
+            }
+        }
+    }
+}
+
+// After wave_sort: write the s smallest distinct keys (kBadLoc excluded) to
+// sk[0..] in ascending order and return their number. If a valid k-mer hashed
+// to 0xFFFFFFFF (has_top) and fewer than s smaller distinct values exist, that
+// value is appended as the last element.
+template <int KPL>
+__device__ __forceinline__ uint32_t select_distinct(const uint32_t (&v)[KPL], bool has_top,
+                                                    uint32_t s, uint32_t* sk) {
+    const int lane = lane_id();
+    uint32_t base = 0, prev_last = 0;
+#pragma unroll
+    for (int r = 0; r < KPL; ++r) {
+        uint32_t up = shfl_idx(v[r], lane > 0 ? lane - 1 : 0);
+        bool has_prev = lane > 0 || r > 0;
+        uint32_t prev = lane > 0 ? up : prev_last;
+        bool first = v[r] != 0xFFFFFFFFu && (!has_prev || v[r] != prev);
+        uint64_t bal = ballot(first);
+        uint32_t rank = base + rank_below(bal);
+        if (first && rank < s) sk[rank] = v[r];
+        base += popc64(bal);
+        prev_last = (uint32_t)__builtin_amdgcn_readlane((int)v[r], kWave - 1);
+    }
+    uint32_t n = base < s ? base : s;
+    if (has_top && base < s) {
+        if (lane == 0) sk[base] = 0xFFFFFFFFu;
+        n = base + 1;
+    }
+    return n;
+}
+
+// Sketch of one window whose nk k-mer starts begin x0 bases after the first
+// staged word: h1 of each valid canonical k-mer, then the s smallest distinct.
+template <int KPL>
+__device__ __forceinline__ uint32_t sketch_window(const Word* W, uint32_t x0, uint32_t nk,
+                                                  uint32_t k, uint32_t s, uint32_t* sk) {
+    const int lane = lane_id();
+    uint32_t key[KPL];
+    bool top = false;
+#pragma unroll
+    for (int r = 0; r < KPL; ++r) {
+        uint32_t i = (uint32_t)(r * kWave + lane);
+        key[r] = 0xFFFFFFFFu;
+        if (i < nk) {
+            uint32_t c;
+            if (kmer_at(W, x0 + i, k, c)) {
+                uint32_t h = h1(c);
+                key[r] = h;
+                top |= (h == 0xFFFFFFFFu);
+            }
+        }
+    }
+    bool has_top = ballot(top) != 0;
+    wave_sort<KPL>(key);
+    return select_distinct<KPL>(key, has_top, s, sk);
+}
+
+// Stage the bytes [lo, hi) into words relative to A0 = lo & ~15, one word per
+// participating thread (tid in [0, nthreads)); bytes outside [vlo, vhi) are
+// invalid. Returns nothing; callers synchronise before reading W.
+__device__ __forceinline__ void stage_words(Word* W, uintptr_t lo, uintptr_t hi, uintptr_t vlo,
+                                            uintptr_t vhi, int tid, int nthreads) {
+    uintptr_t A0 = lo & ~(uintptr_t)15;
+    int nw = (int)((hi - A0 + 15) / 16) + 1;
+    for (int q = tid; q < nw; q += nthreads) W[q] = load_word(A0 + 16 * (uintptr_t)q, vlo, vhi);
+}
+
+// ------------------------------------------------------------ LCA / taxa --
+__device__ __forceinline__ uint32_t lca(uint32_t a, uint32_t b, const uint32_t* parent,
+                                        const uint32_t* depth) {
+    uint32_t da = depth[a], db = depth[b];
+    while (da > db) { a = parent[a]; --da; }
+    while (db > da) { b = parent[b]; --db; }
+    while (a != b) { a = parent[a]; b = parent[b]; }
+    return a;
+}
+
+}  // namespace mc

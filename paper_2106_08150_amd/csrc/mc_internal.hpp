@@ -1,0 +1,102 @@
+// Launch interfaces between the host-side C ABI (mc_api.hip) and the kernel
+// translation units (mc_build.hip, mc_query.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mc {
+
+constexpr int kSlots = 16;   // 64-bit slots per table bucket (one 128-byte line)
+
+// One reference sequence of an add call.
+struct TargetDesc {
+    uint64_t off;        // byte offset of the sequence in the call's text buffer
+    uint64_t len;        // bases
+    uint64_t win_base;   // index of its window 0 among all windows of the call
+    uint32_t id;         // global target id
+    uint32_t nw;         // windows
+};
+
+// Build-side counters (device, u64).
+enum BuildCounter {
+    kCntInserted = 0,    // pairs inserted
+    kCntProbe = 1,       // sum over inserts of (buckets probed - 1)
+    kCntCand = 2,        // cap candidates pushed (may exceed the list capacity)
+    kCntFull = 3,        // inserts that found no free slot
+    kCntMoved = 4,       // entries re-inserted by a rehash
+    kNumBuildCounters = 8
+};
+
+struct BuildArgs {
+    const uint8_t* text;
+    uint64_t text_len;
+    const TargetDesc* targets;
+    uint32_t n_targets;
+    const uint64_t* tile_first;   // n_targets + 1 prefix of tiles per target
+    uint64_t n_tiles;
+    uint32_t k, w, S, s;
+    // insert mode
+    unsigned long long* table;
+    uint64_t nb;                  // buckets
+    uint32_t cap_dist;            // inserts at this probe distance or more are cap candidates
+    uint32_t* cand;
+    uint64_t cand_cap;
+    unsigned long long* counters;
+    // sketch-export mode
+    uint32_t* out_counts;
+    uint32_t* out_feats;
+};
+
+constexpr int kTileWindows = 32;  // windows per build workgroup tile
+constexpr int kBuildThreads = 256;
+
+// Query-side counters (device, u32).
+enum QueryCounter {
+    kQOverflow = 0,      // records queued for the large-list pass
+    kQTooLong = 1,       // records whose list exceeded the large-list capacity
+    kNumQueryCounters = 4
+};
+
+struct QueryArgs {
+    const unsigned long long* table;
+    uint64_t nb;
+    const uint8_t* reads;
+    const uint64_t* offsets;
+    uint32_t n_records;
+    uint32_t paired;
+    uint32_t k, w, S, s;
+    uint32_t top_m, min_hits, hit_diff, insert_size;
+    const uint32_t* target_taxon;
+    const uint32_t* parents;
+    const uint32_t* depth;
+    uint32_t* out_labels;
+    uint32_t* out_top;            // n_records * top_m * 3 u32, or null
+    uint32_t* queue;              // overflow record ids (capacity n_records)
+    uint32_t* counters;
+};
+
+constexpr uint32_t kListSmall = 512;     // candidate locations per record, fast path
+constexpr uint32_t kListLarge = 16384;   // large-list pass (one wave per workgroup)
+constexpr uint32_t kMaxTopM = 8;
+
+// Launchers (return hipError_t of the launch).
+hipError_t launch_build(const BuildArgs& a, bool insert, hipStream_t st);
+hipError_t launch_cap_finalize(unsigned long long* table, uint64_t nb, uint32_t cap,
+                               const uint32_t* cand, uint64_t n_cand, hipStream_t st);
+hipError_t launch_cap_scan(unsigned long long* table, uint64_t nb, uint32_t cap,
+                           uint32_t cap_dist, hipStream_t st);
+hipError_t launch_rehash(const unsigned long long* old_table, uint64_t old_nb,
+                         unsigned long long* table, uint64_t nb, unsigned long long* counters,
+                         hipStream_t st);
+hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v,
+                           hipStream_t st);
+hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st);
+hipError_t launch_dump(const unsigned long long* table, uint64_t nb, uint32_t lo, uint32_t hi,
+                       unsigned long long* out, uint64_t cap, unsigned long long* count,
+                       hipStream_t st);
+hipError_t launch_count_valid(const unsigned long long* table, uint64_t nb,
+                              unsigned long long* count, hipStream_t st);
+hipError_t launch_classify(const QueryArgs& a, hipStream_t st);
+
+}  // namespace mc

@@ -1,0 +1,313 @@
+// Classification kernels (Sec. 4.2, Sec. 5.2-5.6). One wave classifies one
+// record: it sketches every window of both mates (same code as the build),
+// gathers the location lists of all sketch elements into LDS, sorts them,
+// counts equal locations (window count statistic), scores the best range of
+// `sws` consecutive windows per target, keeps the top m targets and labels the
+// record, by LCA when the top scores are close. Records whose list does not
+// fit the fast path's LDS are queued for a second pass with a larger list.
+#include "mc_device.hpp"
+#include "mc_internal.hpp"
+
+namespace mc {
+
+namespace {
+
+constexpr int kStageWords = 20;    // one window of at most 271 bases
+constexpr uint32_t kMaxFeat = 128; // sketch elements buffered before lookups
+
+template <uint32_t LCAP>
+struct QueryLds {
+    Word stage[kStageWords];
+    uint32_t feats[kMaxFeat];
+    uint32_t list[LCAP];
+    uint16_t uidx[LCAP + 2];
+};
+
+// Append the locations of features F[0..nf) to list (LDS). 16-lane groups
+// read one bucket line each; a feature's chain ends at the first bucket that
+// has an empty slot. Returns false once the list outgrew LCAP.
+template <uint32_t LCAP>
+__device__ bool lookup(const QueryArgs& a, const uint32_t* F, uint32_t nf, uint32_t* list,
+                       uint32_t& nlist) {
+    constexpr int NB = 8;
+    const int lane = lane_id();
+    const int g = lane >> 4, gl = lane & 15;
+    for (uint32_t base = 0; base < nf; base += 4 * NB) {
+        uint32_t f[NB], d[NB];
+        uint64_t b[NB];
+        bool pend[NB];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            uint32_t i = base + (uint32_t)g + 4u * (uint32_t)q;
+            pend[q] = i < nf;
+            f[q] = pend[q] ? F[i] : 0u;
+            b[q] = home_bucket(f[q], a.nb);
+            d[q] = 0;
+        }
+        while (true) {
+            bool any = false;
+#pragma unroll
+            for (int q = 0; q < NB; ++q) any |= pend[q];
+            if (ballot(any) == 0) break;
+            uint64_t sl[NB];
+#pragma unroll
+            for (int q = 0; q < NB; ++q)
+                sl[q] = pend[q] ? (uint64_t)a.table[b[q] * kSlots + gl] : kEmpty;
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                bool m = pend[q] && sl[q] != kEmpty && (uint32_t)(sl[q] >> 32) == f[q] &&
+                         (uint32_t)sl[q] != kBadLoc;
+                uint64_t mb = ballot(m);
+                uint32_t pos = nlist + rank_below(mb);
+                if (m && pos < LCAP) list[pos] = (uint32_t)sl[q];
+                nlist += popc64(mb);
+                uint64_t emp = ballot(pend[q] && sl[q] == kEmpty);
+                bool done = ((emp >> (16 * g)) & 0xFFFFull) != 0;
+                if (pend[q]) {
+                    if (done) {
+                        pend[q] = false;
+                    } else {
+                        b[q] = next_bucket(b[q], a.nb);
+                        d[q] += 1;
+                        if ((uint64_t)d[q] > a.nb) pend[q] = false;
+                    }
+                }
+            }
+            if (nlist > LCAP) return false;
+        }
+    }
+    return true;
+}
+
+template <int K>
+__device__ __forceinline__ void sort_regs(uint32_t* list, uint32_t n) {
+    const int lane = lane_id();
+    uint32_t v[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        uint32_t e = (uint32_t)(r * kWave + lane);
+        v[r] = e < n ? list[e] : 0xFFFFFFFFu;
+    }
+    wave_sort<K>(v);
+    wave_lds_sync();
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        uint32_t e = (uint32_t)(r * kWave + lane);
+        if (e < n) list[e] = v[r];
+    }
+    wave_lds_sync();
+}
+
+// Bitonic sort of list[0..P) in LDS by one wave (P a power of two, entries
+// n..P-1 padded with the largest key).
+__device__ void sort_lds(uint32_t* list, uint32_t n, uint32_t P) {
+    const uint32_t lane = (uint32_t)lane_id();
+    for (uint32_t e = n + lane; e < P; e += kWave) list[e] = 0xFFFFFFFFu;
+    wave_lds_sync();
+    for (uint32_t size = 2; size <= P; size <<= 1) {
+        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+            for (uint32_t idx = lane; idx < P / 2; idx += kWave) {
+                uint32_t i = (idx / stride) * 2 * stride + (idx % stride);
+                uint32_t j = i + stride;
+                bool asc = (i & size) == 0;
+                uint32_t x = list[i], y = list[j];
+                if ((x > y) == asc) {
+                    list[i] = y;
+                    list[j] = x;
+                }
+            }
+            wave_lds_sync();
+        }
+    }
+}
+
+template <uint32_t LCAP>
+__device__ void sort_list(uint32_t* list, uint32_t n) {
+    uint32_t P = 64;
+    while (P < n) P <<= 1;
+    switch (P) {
+        case 64: sort_regs<1>(list, n); break;
+        case 128: sort_regs<2>(list, n); break;
+        case 256: sort_regs<4>(list, n); break;
+        case 512: sort_regs<8>(list, n); break;
+        case 1024: if (LCAP >= 1024) sort_regs<16>(list, n); break;
+        default: sort_lds(list, n, P); break;
+    }
+}
+
+__device__ __forceinline__ void write_result(const QueryArgs& a, uint32_t rec, uint32_t label,
+                                             const uint32_t* st, const uint32_t* ss,
+                                             const uint32_t* sb, uint32_t nsel) {
+    const uint32_t lane = (uint32_t)lane_id();
+    if (lane == 0) a.out_labels[rec] = label;
+    if (a.out_top && lane < a.top_m) {
+        uint32_t t = kNone, s = 0, bgn = 0;
+#pragma unroll
+        for (uint32_t x = 0; x < kMaxTopM; ++x)
+            if (x == lane && x < nsel) { t = st[x]; s = ss[x]; bgn = sb[x]; }
+        uint32_t* o = a.out_top + ((uint64_t)rec * a.top_m + lane) * 3;
+        o[0] = t;
+        o[1] = s;
+        o[2] = bgn;
+    }
+}
+
+template <uint32_t LCAP, int KPL>
+__device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>& L, bool big) {
+    const int lane = lane_id();
+    uint64_t o0, o1, o2;
+    if (a.paired) {
+        o0 = a.offsets[2ull * rec]; o1 = a.offsets[2ull * rec + 1]; o2 = a.offsets[2ull * rec + 2];
+    } else {
+        o0 = a.offsets[rec]; o1 = a.offsets[rec + 1ull]; o2 = o1;
+    }
+    o0 = uniform64(o0); o1 = uniform64(o1); o2 = uniform64(o2);
+    uint32_t st[kMaxTopM], ss[kMaxTopM], sb[kMaxTopM];
+    if (o1 < o0 || o2 < o1) {           // malformed record: nothing to classify
+        write_result(a, rec, kNone, st, ss, sb, 0);
+        return;
+    }
+    const uint64_t len[2] = {o1 - o0, o2 - o1};
+    uint64_t F = len[0] + len[1];
+    if (len[0] > 0 && len[1] > 0 && a.insert_size > F) F = a.insert_size;
+    const uint32_t sws = F < a.k ? 1u : (uint32_t)((F - a.k + a.S - 1) / a.S + 1);
+
+    uint32_t nlist = 0, nf = 0;
+    bool fits = true;
+    for (int sg = 0; sg < 2 && fits; ++sg) {
+        const uint64_t L0 = len[sg];
+        if (L0 < a.k) continue;
+        const uintptr_t p0 = (uintptr_t)(a.reads + (sg ? o1 : o0));
+        const uintptr_t p1 = p0 + L0;
+        const uint64_t n_starts = L0 - a.k + 1;
+        const uint64_t nw = (n_starts + a.S - 1) / a.S;
+        for (uint64_t j = 0; j < nw && fits; ++j) {
+            const uintptr_t lo = p0 + j * a.S;
+            uintptr_t hi = lo + a.w;
+            if (hi > p1) hi = p1;
+            wave_lds_sync();
+            stage_words(L.stage, lo, hi, p0, p1, lane, kWave);
+            wave_lds_sync();
+            const uint32_t nk = (uint32_t)min((uint64_t)a.S, n_starts - j * a.S);
+            const uint32_t x0 = (uint32_t)(lo & 15u);
+            nf += sketch_window<KPL>(L.stage, x0, nk, a.k, a.s, L.feats + nf);
+            wave_lds_sync();
+            if (nf + a.s > kMaxFeat) {
+                fits = lookup<LCAP>(a, L.feats, nf, L.list, nlist);
+                nf = 0;
+            }
+        }
+    }
+    if (fits && nf) fits = lookup<LCAP>(a, L.feats, nf, L.list, nlist);
+    if (!fits) {
+        if (!big) {
+            if (lane == 0) {
+                uint32_t qi = atomicAdd(&a.counters[kQOverflow], 1u);
+                a.queue[qi] = rec;
+            }
+        } else {
+            if (lane == 0) atomicAdd(&a.counters[kQTooLong], 1u);
+            write_result(a, rec, kNone, st, ss, sb, 0);
+        }
+        return;
+    }
+    wave_lds_sync();
+    const uint32_t n = nlist;
+    sort_list<LCAP>(L.list, n);
+
+    // run-length encoding: uidx[u] = first index of the u-th distinct location
+    uint32_t U = 0;
+    for (uint32_t c = 0; c < n; c += kWave) {
+        uint32_t i = c + (uint32_t)lane;
+        bool first = false;
+        if (i < n) first = (i == 0) || (L.list[i] != L.list[i - 1]);
+        uint64_t mb = ballot(first);
+        if (first) L.uidx[U + rank_below(mb)] = (uint16_t)i;
+        U += popc64(mb);
+    }
+    if (lane == 0) L.uidx[U] = (uint16_t)n;
+    wave_lds_sync();
+
+    // top-m targets by (score desc, target asc); per target the range with the
+    // highest score, ties to the smallest start window
+    uint32_t nsel = 0;
+#pragma unroll
+    for (uint32_t m = 0; m < kMaxTopM; ++m) {
+        if (m >= a.top_m) break;
+        uint64_t best = 0;
+        for (uint32_t u = (uint32_t)lane; u < U; u += kWave) {
+            const uint32_t loc = L.list[L.uidx[u]];
+            const uint32_t t = loc >> kWindowBits;
+            bool excluded = false;
+#pragma unroll
+            for (uint32_t x = 0; x < kMaxTopM; ++x)
+                if (x < m) excluded |= (st[x] == t);
+            if (excluded) continue;
+            const uint32_t w_end = (loc & kWindowMask) + sws;
+            uint32_t score = 0;
+            for (uint32_t v = u; v < U; ++v) {
+                const uint32_t l2 = L.list[L.uidx[v]];
+                if ((l2 >> kWindowBits) != t || (l2 & kWindowMask) >= w_end) break;
+                score += (uint32_t)L.uidx[v + 1] - (uint32_t)L.uidx[v];
+            }
+            const uint64_t key = ((uint64_t)score << 32) | (uint64_t)(~loc);
+            best = key > best ? key : best;
+        }
+        best = uniform64(wave_max_u64(best));
+        if (best == 0) break;
+        const uint32_t loc = ~(uint32_t)best;
+        st[m] = loc >> kWindowBits;
+        ss[m] = (uint32_t)(best >> 32);
+        sb[m] = loc & kWindowMask;
+        nsel = m + 1;
+    }
+
+    uint32_t label = kNone;
+    if (nsel > 0 && ss[0] >= a.min_hits) {
+        const uint32_t c1 = ss[0], c2 = nsel > 1 ? ss[1] : 0u;
+        label = a.target_taxon[st[0]];
+        if (c1 - c2 <= a.hit_diff) {
+#pragma unroll
+            for (uint32_t x = 1; x < kMaxTopM; ++x)
+                if (x < nsel && (uint64_t)ss[x] + a.hit_diff >= c1)
+                    label = lca(label, a.target_taxon[st[x]], a.parents, a.depth);
+        }
+    }
+    write_result(a, rec, uniform(label), st, ss, sb, nsel);
+}
+
+template <uint32_t LCAP, int WPB, int KPL>
+__global__ __launch_bounds__(WPB * 64) void k_classify(QueryArgs a, int big) {
+    __shared__ QueryLds<LCAP> L[WPB];
+    const int wave = (int)uniform(threadIdx.x >> 6);
+    const uint32_t n_iter = big ? uniform(a.counters[kQOverflow]) : a.n_records;
+    for (uint32_t it = blockIdx.x * WPB + wave; it < n_iter; it += gridDim.x * WPB) {
+        const uint32_t rec = big ? uniform(a.queue[it]) : it;
+        classify_record<LCAP, KPL>(a, rec, L[wave], big != 0);
+    }
+}
+
+template <int KPL>
+hipError_t launch_kpl(const QueryArgs& a, hipStream_t st) {
+    constexpr int WPB = 4;
+    uint64_t blocks = ((uint64_t)a.n_records + WPB - 1) / WPB;
+    if (blocks > 16384) blocks = 16384;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL((k_classify<kListSmall, WPB, KPL>), dim3((unsigned)blocks), dim3(WPB * 64),
+                       0, st, a, 0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_classify<kListLarge, 1, KPL>), dim3(512), dim3(64), 0, st, a, 1);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_classify(const QueryArgs& a, hipStream_t st) {
+    if (a.n_records == 0) return hipSuccess;
+    if (a.S <= 64) return launch_kpl<1>(a, st);
+    if (a.S <= 128) return launch_kpl<2>(a, st);
+    return launch_kpl<4>(a, st);
+}
+
+}  // namespace mc

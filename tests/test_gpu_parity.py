@@ -1,0 +1,311 @@
+"""HIP path vs the CPU oracle, element by element, through the C ABI.
+
+Integer work throughout, so the bar is bit-exact: per-window sketches, the
+stored (feature, location) pairs, per-record top hits and labels.
+"""
+import numpy as np
+import pytest
+
+import oracle as orc
+import paper_2106_08150_amd as mc
+from paper_2106_08150_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+UNCL = 0xFFFFFFFF
+SENTINEL_KMER = "ATATACTCGGAAGAAT"   # canonical 16-mer whose h1 is 0xFFFFFFFF
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    if not T.cuda.is_available():
+        pytest.skip("no GPU")
+    return T
+
+
+def dev_u8(torch, arr):
+    a = np.ascontiguousarray(arr, dtype=np.uint8)
+    return torch.from_numpy(a.copy()).cuda() if a.size else torch.zeros(1, dtype=torch.uint8,
+                                                                           device="cuda")
+
+
+def dev_off(torch, off):
+    return torch.from_numpy(np.ascontiguousarray(off, dtype=np.uint64).view(np.int64)).cuda()
+
+
+def build_both(torch, g, k=16, w=128, s=16, cap=254, splits=None):
+    gdb = mc.Database(k, w, s, cap)
+    odb = orc.OracleDB(k, w, s, cap)
+    off = g.offsets
+    for a, b in (splits or [(0, g.lengths.size)]):
+        txt = g.text[int(off[a]):int(off[b])]
+        gdb.add_targets(dev_u8(torch, txt), g.lengths[a:b], g.taxa[a:b])
+        odb.add_targets(txt, g.lengths[a:b], g.taxa[a:b], threads=8)
+    gdb.set_taxonomy(g.parents)
+    odb.set_taxonomy(g.parents)
+    return gdb, odb
+
+
+def assert_same_table(gdb, odb):
+    gf, gl = gdb.dump()
+    of, ol = odb.dump()
+    assert gf.size == of.size
+    assert np.array_equal(gf, of)
+    assert np.array_equal(gl, ol)
+
+
+def classify_both(torch, gdb, odb, reads, paired=False, **opts):
+    r = dev_u8(torch, reads.text)
+    o = dev_off(torch, reads.offsets)
+    n = reads.n_records
+    labels, top = gdb.classify(r, o, n, paired=paired, with_top=True, **opts)
+    torch.cuda.synchronize()
+    gl = labels.cpu().numpy().view(np.uint32)
+    gt = top.cpu().numpy().view(np.uint32)
+    ol, ot = odb.classify(reads.text, reads.offsets, paired=paired, threads=8, **opts)
+    return gl, gt, ol, ot
+
+
+def assert_same_results(gl, gt, ol, ot):
+    bad = np.nonzero((gl != ol) | (gt != ot).any(axis=(1, 2)))[0]
+    assert bad.size == 0, (f"{bad.size} records differ, first {bad[:5]}: "
+                           f"gpu {gl[bad[:3]]} {gt[bad[:3]]} oracle {ol[bad[:3]]} {ot[bad[:3]]}")
+
+
+# ------------------------------------------------------------ sketches ----
+@pytest.mark.parametrize("k,w,s", [(16, 128, 16), (16, 127, 16), (4, 20, 3), (5, 5, 1),
+                                   (16, 40, 25), (12, 75, 64), (16, 271, 16), (1, 64, 2)])
+def test_window_sketches(torch, k, w, s):
+    rng = np.random.default_rng(k * 1000 + w)
+    seqs = []
+    for L in [0, 1, k - 1, k, k + 1, w, w + 1, 3 * w - 7, 5000]:
+        t = rng.choice(np.frombuffer(b"ACGTacgtN", np.uint8), size=L,
+                       p=[0.24, 0.24, 0.24, 0.24, 0.01, 0.01, 0.01, 0.005, 0.005])
+        seqs.append(t.astype(np.uint8))
+    seqs.append(np.frombuffer(b"A" * 700, np.uint8))
+    seqs.append(np.frombuffer(("NN" + SENTINEL_KMER + "NN").encode(), np.uint8))
+    lengths = np.array([x.size for x in seqs], np.uint64)
+    text = np.concatenate(seqs)
+    db = mc.Database(k, w, s, 254)
+    nw = [orc.num_windows(int(L), k, w) for L in lengths]
+    tot = max(1, sum(nw))
+    counts = torch.zeros(tot, dtype=torch.int32, device="cuda")
+    feats = torch.zeros(tot * s, dtype=torch.int32, device="cuda")
+    mc.mc_db_sketch(db.h, dev_u8(torch, text), lengths, counts, feats)
+    torch.cuda.synchronize()
+    counts = counts.cpu().numpy().view(np.uint32)
+    feats = feats.cpu().numpy().view(np.uint32)
+    gw = 0
+    for x, n_w in zip(seqs, nw):
+        want = orc.sketch_windows(x, k, w, s)
+        assert len(want) == n_w
+        for j in range(n_w):
+            got = feats[(gw + j) * s:(gw + j) * s + counts[gw + j]].tolist()
+            assert got == want[j], (k, w, s, x.size, j)
+        gw += n_w
+
+
+# ---------------------------------------------------------- tiny config ----
+@pytest.fixture(scope="module")
+def tiny(torch):
+    g = synth.tiny_genomes()
+    gdb, odb = build_both(torch, g)
+    reads = synth.tiny_reads(g)
+    return g, gdb, odb, reads
+
+
+def test_tiny_table(tiny):
+    _, gdb, odb, _ = tiny
+    assert_same_table(gdb, odb)
+    st = gdb.stats()
+    assert st["n_pairs_stored"] == odb.num_pairs
+    assert st["n_windows"] == 8 * 885
+
+
+def test_tiny_classification(torch, tiny):
+    _, gdb, odb, reads = tiny
+    gl, gt, ol, ot = classify_both(torch, gdb, odb, reads)
+    assert_same_results(gl, gt, ol, ot)
+    # sanity: most reads are labelled with a species or genus
+    assert (gl != UNCL).mean() > 0.5
+
+
+@pytest.mark.parametrize("top_m,min_hits,hit_diff",
+                         [(1, 1, 0), (2, 1, 1), (4, 1, 3), (4, 4, 0), (2, 4, 3), (1, 4, 1),
+                          (8, 2, 2)])
+def test_parameter_grid(torch, tiny, top_m, min_hits, hit_diff):
+    g, gdb, odb, _ = tiny
+    reads = synth.sample_reads(g, 1500, 100, seed=top_m * 100 + min_hits * 10 + hit_diff)
+    gl, gt, ol, ot = classify_both(torch, gdb, odb, reads, top_m=top_m, min_hits=min_hits,
+                                   hit_diff=hit_diff)
+    assert_same_results(gl, gt, ol, ot)
+
+
+def test_batch_split_and_stream_determinism(torch, tiny):
+    _, gdb, _, reads = tiny
+    r = dev_u8(torch, reads.text)
+    o = dev_off(torch, reads.offsets)
+    full, _ = gdb.classify(r, o, reads.n_records)
+    parts = []
+    s = torch.cuda.Stream()
+    for a, b in [(0, 1), (1, 4000), (4000, 10000)]:
+        with torch.cuda.stream(s):
+            lab, _ = gdb.classify(r, o[a:b + 1].contiguous(), b - a, stream=s)
+        parts.append(lab)
+    s.synchronize()
+    torch.cuda.synchronize()
+    assert torch.equal(full, torch.cat(parts))
+
+
+# -------------------------------------------------------- cap handling ----
+def test_cap_stress_repeated_genomes(torch):
+    g = synth.repeated_genome(300, 20_000, seed=21)
+    gdb, odb = build_both(torch, g)
+    assert_same_table(gdb, odb)
+    f, _ = gdb.dump()
+    _, counts = np.unique(f, return_counts=True)
+    assert counts.max() == 254
+    # reads from the repeats: 16 features x 254 locations -> large-list pass
+    reads = synth.sample_reads(g, 300, 100, seed=5, error=0.0)
+    gl, gt, ol, ot = classify_both(torch, gdb, odb, reads, top_m=8, min_hits=1)
+    assert_same_results(gl, gt, ol, ot)
+    assert mc.mc_db_query_status(gdb.h) == 0
+
+
+@pytest.mark.parametrize("cap", [1, 3, 17])
+def test_small_caps_and_incremental_adds(torch, cap):
+    g = synth.tiny_genomes(length=30_000)
+    gdb, odb = build_both(torch, g, cap=cap, splits=[(0, 3), (3, 4), (4, 8)])
+    assert_same_table(gdb, odb)
+    reads = synth.sample_reads(g, 2000, 100, seed=cap)
+    gl, gt, ol, ot = classify_both(torch, gdb, odb, reads, min_hits=1)
+    assert_same_results(gl, gt, ol, ot)
+
+
+def test_table_growth_keeps_entries(torch):
+    """Many small adds force several rehashes of the table."""
+    g = synth.clustered_genomes(4, 5, 2e6, seed=31, median_bp=1e5, clip=(2e4, 3e5))
+    gdb, odb = build_both(torch, g, splits=[(i, i + 1) for i in range(20)])
+    assert gdb.stats()["n_rehash"] >= 1
+    assert_same_table(gdb, odb)
+
+
+# ------------------------------------------------------------ edge cases --
+def test_edge_case_reads(torch, tiny):
+    g, gdb, odb, _ = tiny
+    g0 = g.genome(0)
+    S = 113
+    pieces = [
+        b"", b"ACGT", g0[500:515].tobytes(), g0[500:516].tobytes(), g0[500:628].tobytes(),
+        g0[5 * S:5 * S + 128].tobytes(), g0[1000:1129].tobytes(),
+        g0[2000:2100].tobytes().lower(), (g0[3000:3050].tobytes() + b"N" + g0[3051:3100].tobytes()),
+        b"N" * 100, g0[4000:4250].tobytes(), g0[7000:8000].tobytes(),
+        synth.reverse_complement_text(g0[9000:9150]).tobytes(),
+    ]
+    off = np.zeros(len(pieces) + 1, np.uint64)
+    off[1:] = np.cumsum([len(p) for p in pieces])
+    reads = synth.Reads(np.frombuffer(b"".join(pieces), np.uint8), off)
+    for opts in [dict(min_hits=1), dict(), dict(top_m=1, hit_diff=2)]:
+        gl, gt, ol, ot = classify_both(torch, gdb, odb, reads, **opts)
+        assert_same_results(gl, gt, ol, ot)
+    assert gl[0] == UNCL and gl[1] == UNCL and gl[9] == UNCL
+
+
+def test_paired_records(torch, tiny):
+    g, gdb, odb, _ = tiny
+    recs = synth.mixed_records(g, 600, seed=9)
+    # add a few records with an empty mate 1 or both mates empty
+    extra = [(b"", g.genome(2)[100:250].tobytes()), (b"", b""), (g.genome(3)[0:20].tobytes(), b"")]
+    text = recs.text.tobytes()
+    off = list(recs.offsets.tolist())
+    for m1, m2 in extra:
+        text += m1
+        off.append(len(text))
+        text += m2
+        off.append(len(text))
+    reads = synth.Reads(np.frombuffer(text, np.uint8), np.array(off, np.uint64), paired=True)
+    for ins in [0, 400, 1000]:
+        gl, gt, ol, ot = classify_both(torch, gdb, odb, reads, paired=True, insert_size=ins,
+                                       min_hits=2)
+        assert_same_results(gl, gt, ol, ot)
+
+
+def test_homopolymer_and_sentinel_feature(torch):
+    seqs = [b"A" * 5000, ("N" * 40 + SENTINEL_KMER + "N" * 40).encode(), SENTINEL_KMER.encode(),
+            b"ACGT" * 700]
+    lengths = np.array([len(x) for x in seqs], np.uint64)
+    text = np.frombuffer(b"".join(seqs), np.uint8)
+    g = synth.Genomes(text, lengths, np.array([1, 2, 2, 1], np.uint32),
+                      np.array([0, 0, 0], np.uint32))
+    gdb, odb = build_both(torch, g)
+    assert_same_table(gdb, odb)
+    f, _ = gdb.dump(0xFFFFFFFF, 0xFFFFFFFF)
+    assert f.size == 2            # the all-ones feature is stored, twice
+    rd = [SENTINEL_KMER.encode(), b"A" * 100, b"ACGT" * 30, b"T" * 60]
+    off = np.zeros(len(rd) + 1, np.uint64)
+    off[1:] = np.cumsum([len(x) for x in rd])
+    reads = synth.Reads(np.frombuffer(b"".join(rd), np.uint8), off)
+    gl, gt, ol, ot = classify_both(torch, gdb, odb, reads, min_hits=1, top_m=4)
+    assert_same_results(gl, gt, ol, ot)
+    assert gl[0] == 2
+
+
+def test_record_over_large_list_capacity_is_reported(torch):
+    """A record whose candidate list exceeds 16384 locations is reported and
+    left unclassified (both other records still match the oracle)."""
+    g = synth.repeated_genome(300, 20_000, seed=21)
+    gdb, odb = build_both(torch, g)
+    g0 = g.genome(0)
+    # 2 x 600 bp mates: 12 windows x 16 features x 254 locations > 16384
+    pieces = [g0[0:100].tobytes(), b"", g0[1000:1600].tobytes(), g0[5000:5600].tobytes(),
+              g0[100:250].tobytes(), g0[300:450].tobytes()]
+    off = np.zeros(len(pieces) + 1, np.uint64)
+    off[1:] = np.cumsum([len(p) for p in pieces])
+    reads = synth.Reads(np.frombuffer(b"".join(pieces), np.uint8), off, paired=True)
+    gl, gt, ol, ot = classify_both(torch, gdb, odb, reads, paired=True, min_hits=1)
+    assert mc.mc_db_query_status(gdb.h) == 1
+    assert gl[1] == UNCL and (gt[1, :, 0] == UNCL).all()
+    keep = np.array([0, 2])
+    assert_same_results(gl[keep], gt[keep], ol[keep], ot[keep])
+
+
+# ------------------------------------------------- several tiles, ragged --
+def test_clustered_midsize(torch):
+    g = synth.clustered_genomes(5, 6, 3e6, seed=41, median_bp=1e5, clip=(3e3, 4e5))
+    gdb, odb = build_both(torch, g)
+    assert_same_table(gdb, odb)
+    reads = synth.sample_reads(g, 5000, 150, seed=42, foreign=0.05)
+    gl, gt, ol, ot = classify_both(torch, gdb, odb, reads)
+    assert_same_results(gl, gt, ol, ot)
+    recs = synth.mixed_records(g, 1000, seed=43)
+    gl, gt, ol, ot = classify_both(torch, gdb, odb, recs, paired=True, insert_size=400)
+    assert_same_results(gl, gt, ol, ot)
+
+
+def test_invalid_taxonomy_and_state(torch):
+    db = mc.Database()
+    with pytest.raises(mc.MCError):
+        db.set_taxonomy(np.array([1, 0], np.uint32))          # no root (cycle)
+    with pytest.raises(mc.MCError):
+        db.set_taxonomy(np.array([0, 1], np.uint32))          # two roots
+    with pytest.raises(mc.MCError):
+        db.set_taxonomy(np.array([0, 5], np.uint32))          # out of range
+    with pytest.raises(mc.MCError):
+        db.set_taxonomy(np.array([0, 2, 1], np.uint32))       # cycle off the root
+    g = synth.tiny_genomes(length=2000)
+    db.add_targets(dev_u8(torch, g.text), g.lengths, g.taxa)
+    r = dev_u8(torch, g.text[:100])
+    o = dev_off(torch, np.array([0, 100], np.uint64))
+    with pytest.raises(mc.MCError):       # taxonomy not set
+        db.classify(r, o, 1)
+    db.set_taxonomy(np.array([0, 0, 0], np.uint32))   # taxa 3..10 outside
+    with pytest.raises(mc.MCError):
+        db.classify(r, o, 1)
+    # a sequence with 2^18 + 1 windows: rejected before any byte is read
+    lengths = np.array([(1 << 18) * 113 + 16], np.uint64)
+    taxa = np.zeros(1, np.uint32)
+    buf = dev_u8(torch, np.zeros(16, np.uint8))
+    rc = mc.lib().mc_db_add_targets_device(db.h, buf.data_ptr(), mc._np_ptr(lengths),
+                                           mc._np_ptr(taxa), 1, None)
+    assert rc == mc.MC_ERR_CAPACITY
