@@ -96,6 +96,9 @@ typedef struct mc_db_stats {
     uint64_t n_cap_candidates; /* features re-checked against the cap       */
     uint64_t probe_sum;        /* sum over inserts of buckets probed - 1    */
     uint64_t n_rehash;         /* table growths                             */
+    uint64_t q_features;       /* sketch elements looked up by classify     */
+    uint64_t q_locations;      /* locations gathered by classify            */
+    uint64_t q_probes;         /* bucket lines read by classify lookups     */
 } mc_db_stats;
 
 /* Text of the calling thread's last error ("" if none). Never NULL. */
@@ -158,6 +161,15 @@ int mc_classify_ex(mc_db* db, const char* reads, const uint64_t* offsets, uint32
 /* Waits for `stream`, then reports (and clears) the number of records since
  * the last call whose candidate list was too long (MC_ERR_LIST if > 0). */
 int mc_db_query_status(mc_db* db, void* stream, uint64_t* n_too_long);
+
+/* Inspection: when profiling is enabled, the library brackets its two
+ * dominant launches with HIP events on the launch stream: the build kernel of
+ * mc_db_add_targets* and the fast-path classify kernel of mc_classify*.
+ * mc_db_kernel_times waits for those events, returns the summed milliseconds
+ * and launch counts since the previous call, and resets them. */
+int mc_db_set_profiling(mc_db* db, int enable);
+int mc_db_kernel_times(mc_db* db, double* build_ms, uint64_t* n_build, double* classify_ms,
+                       uint64_t* n_classify);
 
 /* Counters of the handle (synchronous). */
 int mc_db_get_stats(mc_db* db, mc_db_stats* out);

@@ -35,6 +35,7 @@ EXPORTS = [
     "mc_last_error", "mc_db_create", "mc_db_destroy", "mc_db_reserve", "mc_db_add_targets",
     "mc_db_add_targets_device", "mc_db_set_taxonomy", "mc_classify", "mc_classify_ex",
     "mc_db_query_status", "mc_db_get_stats", "mc_db_dump", "mc_db_sketch",
+    "mc_db_set_profiling", "mc_db_kernel_times",
 ]
 
 
@@ -52,7 +53,8 @@ class QueryOpts(C.Structure):
 class DbStats(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in (
         "n_targets", "n_windows", "n_pairs_inserted", "n_pairs_stored", "n_buckets",
-        "table_bytes", "n_cap_candidates", "probe_sum", "n_rehash")]
+        "table_bytes", "n_cap_candidates", "probe_sum", "n_rehash", "q_features",
+        "q_locations", "q_probes")]
 
     def as_dict(self) -> dict:
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
@@ -93,6 +95,10 @@ def lib():
         L.mc_db_dump.argtypes = [vp, u32, u32, vp, vp, u64, C.POINTER(u64)]
         L.mc_db_sketch.restype = i32
         L.mc_db_sketch.argtypes = [vp, vp, vp, u32, vp, vp, vp]
+        L.mc_db_set_profiling.restype, L.mc_db_set_profiling.argtypes = i32, [vp, i32]
+        L.mc_db_kernel_times.restype = i32
+        L.mc_db_kernel_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(u64),
+                                         C.POINTER(C.c_double), C.POINTER(u64)]
         _lib = L
     return _lib
 
@@ -205,6 +211,19 @@ def mc_db_sketch(db: int, seqs_dev, lengths, out_counts, out_features, stream=No
     L = np.ascontiguousarray(lengths, dtype=np.uint64)
     _check(lib().mc_db_sketch(db, _dev_ptr(seqs_dev), _np_ptr(L), L.size, _dev_ptr(out_counts),
                               _dev_ptr(out_features), _stream(stream)))
+
+
+def mc_db_set_profiling(db: int, enable: bool) -> None:
+    _check(lib().mc_db_set_profiling(db, int(enable)))
+
+
+def mc_db_kernel_times(db: int) -> dict:
+    """Summed ms and launch counts of the profiled build / classify kernels."""
+    bm, cm = C.c_double(0), C.c_double(0)
+    nb, nc = C.c_uint64(0), C.c_uint64(0)
+    _check(lib().mc_db_kernel_times(db, C.byref(bm), C.byref(nb), C.byref(cm), C.byref(nc)))
+    return {"build_ms": bm.value, "n_build": int(nb.value), "classify_ms": cm.value,
+            "n_classify": int(nc.value)}
 
 
 # ------------------------------------------------------------ wrapper ----

@@ -1,4 +1,8 @@
-"""Compiles the HIP library (gfx950) in-tree: paper_2106_08150_amd/libmc.so."""
+"""Compiles the HIP libraries (gfx950) in-tree.
+
+libmc.so        the classifier (C ABI of include/mc.h)
+libmc_peaks.so  memory-system probes used as roofline denominators
+"""
 from __future__ import annotations
 
 import os
@@ -10,6 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmc.so")
 SOURCES = ["mc_api.hip", "mc_build.hip", "mc_query.hip"]
+PEAKS_LIB = os.path.join(HERE, "libmc_peaks.so")
+PEAKS_SOURCES = ["mc_peaks.hip"]
 ARCH = os.environ.get("MC_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
@@ -40,14 +46,15 @@ def build(verbose: bool = False) -> str:
             print(r.stdout, r.stderr, file=sys.stderr)
         return obj
 
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(compile_one, SOURCES))
-    tmp = LIB + ".tmp"
-    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    with ThreadPoolExecutor(max_workers=len(SOURCES) + len(PEAKS_SOURCES)) as ex:
+        objs = list(ex.map(compile_one, SOURCES + PEAKS_SOURCES))
+    for lib, n0, n1 in ((LIB, 0, len(SOURCES)), (PEAKS_LIB, len(SOURCES), len(objs))):
+        tmp = lib + ".tmp"
+        cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs[n0:n1], "-o", tmp]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
+        os.replace(tmp, lib)
     return LIB
 
 

@@ -47,7 +47,13 @@ constexpr uint64_t kCandCapMax = 1ull << 24;
 struct Workspace {
     uint32_t* queue = nullptr;
     uint64_t queue_cap = 0;
-    uint32_t* counters = nullptr;   // kNumQueryCounters
+    uint32_t* counters = nullptr;            // kNumQueryCounters
+    unsigned long long* qstats = nullptr;    // kNumQueryStats
+};
+
+// Event pairs bracketing profiled launches.
+struct Timed {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
 };
 
 // Restores the caller's current device on scope exit.
@@ -89,6 +95,9 @@ struct mc_db {
     mc_db_stats st{};
     // per-stream query workspaces
     std::map<hipStream_t, Workspace> ws;
+    // profiling
+    bool profiling = false;
+    Timed t_build, t_query;
 };
 
 namespace {
@@ -154,6 +163,43 @@ int upload_taxa(mc_db* db, hipStream_t st) {
     return MC_OK;
 }
 
+// Record an event pair around `launch` when profiling is on.
+template <typename F>
+hipError_t timed_launch(mc_db* db, Timed& t, hipStream_t st, F launch) {
+    if (!db->profiling) return launch();
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e == hipSuccess) e = hipEventRecord(a, st);
+    if (e == hipSuccess) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(b, st);
+    if (e == hipSuccess) {
+        t.ev.emplace_back(a, b);
+    } else {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+    return e;
+}
+
+hipError_t drain(Timed& t, double* ms, uint64_t* n) {
+    double total = 0.0;
+    hipError_t err = hipSuccess;
+    for (auto& p : t.ev) {
+        float x = 0.f;
+        hipError_t e = hipEventSynchronize(p.second);
+        if (e == hipSuccess) e = hipEventElapsedTime(&x, p.first, p.second);
+        if (e != hipSuccess) err = e;
+        total += x;
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+    }
+    if (ms) *ms = total;
+    if (n) *n = t.ev.size();
+    t.ev.clear();
+    return err;
+}
+
 // Shared by the host and device entry points: genomes is a device pointer.
 int add_targets_dev(mc_db* db, const uint8_t* genomes, const uint64_t* lengths,
                     const uint32_t* taxa, uint32_t n, hipStream_t st) {
@@ -214,7 +260,7 @@ int add_targets_dev(mc_db* db, const uint8_t* genomes, const uint64_t* lengths,
     a.cand = db->cand;
     a.cand_cap = db->cand_cap;
     a.counters = db->counters;
-    HIP_TRY(launch_build(a, true, st));
+    HIP_TRY(timed_launch(db, db->t_build, st, [&] { return launch_build(a, true, st); }));
     unsigned long long c[kNumBuildCounters];
     HIP_TRY(hipMemcpyAsync(c, db->counters, sizeof c, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -247,7 +293,9 @@ Workspace* workspace(mc_db* db, hipStream_t st, uint64_t n_records, int* rc) {
     *rc = MC_OK;
     if (!w.counters) {
         if ((*rc = dev_alloc(&w.counters, kNumQueryCounters))) return nullptr;
-        if (launch_fill_u32(w.counters, kNumQueryCounters, 0u, st) != hipSuccess) {
+        if ((*rc = dev_alloc(&w.qstats, kNumQueryStats))) return nullptr;
+        if (launch_fill_u32(w.counters, kNumQueryCounters, 0u, st) != hipSuccess ||
+            launch_fill_u64(w.qstats, kNumQueryStats, 0ull, st) != hipSuccess) {
             *rc = fail(MC_ERR_HIP, "workspace init failed");
             return nullptr;
         }
@@ -306,7 +354,10 @@ int mc_db_destroy(mc_db* db) {
     for (auto& kv : db->ws) {
         (void)hipFree(kv.second.queue);
         (void)hipFree(kv.second.counters);
+        (void)hipFree(kv.second.qstats);
     }
+    (void)drain(db->t_build, nullptr, nullptr);
+    (void)drain(db->t_query, nullptr, nullptr);
     (void)hipFree(db->table);
     (void)hipFree(db->counters);
     (void)hipFree(db->cand);
@@ -453,7 +504,9 @@ int mc_classify_ex(mc_db* db, const char* reads, const uint64_t* offsets, uint32
     a.out_top = reinterpret_cast<uint32_t*>(out_top);
     a.queue = w->queue;
     a.counters = w->counters;
-    HIP_TRY(launch_classify(a, st));
+    a.qstats = w->qstats;
+    HIP_TRY(timed_launch(db, db->t_query, st, [&] { return launch_classify_fast(a, st); }));
+    HIP_TRY(launch_classify_large(a, st));
     return MC_OK;
 }
 
@@ -497,11 +550,38 @@ int mc_db_get_stats(mc_db* db, mc_db_stats* out) {
     (void)hipFree(cnt);
     if (e != hipSuccess) return fail(MC_ERR_HIP, "stats: %s", hipGetErrorString(e));
     *out = db->st;
+    for (auto& kv : db->ws) {
+        if (!kv.second.qstats) continue;
+        unsigned long long q[kNumQueryStats];
+        HIP_TRY(hipStreamSynchronize(kv.first));
+        HIP_TRY(hipMemcpy(q, kv.second.qstats, sizeof q, hipMemcpyDeviceToHost));
+        out->q_features += q[kQsFeatures];
+        out->q_locations += q[kQsLocations];
+        out->q_probes += q[kQsProbes];
+    }
     out->n_targets = db->taxa.size();
     out->n_windows = db->n_windows;
     out->n_pairs_stored = stored;
     out->n_buckets = db->nb;
     out->table_bytes = db->nb * kSlots * 8;
+    return MC_OK;
+}
+
+int mc_db_set_profiling(mc_db* db, int enable) {
+    if (int rc = check_db(db)) return rc;
+    db->profiling = enable != 0;
+    return MC_OK;
+}
+
+int mc_db_kernel_times(mc_db* db, double* build_ms, uint64_t* n_build, double* classify_ms,
+                       uint64_t* n_classify) {
+    if (int rc = check_db(db)) return rc;
+    DeviceGuard dg(db->device);
+    hipError_t e1 = drain(db->t_build, build_ms, n_build);
+    hipError_t e2 = drain(db->t_query, classify_ms, n_classify);
+    if (e1 != hipSuccess || e2 != hipSuccess)
+        return fail(MC_ERR_HIP, "kernel timing: %s",
+                    hipGetErrorString(e1 != hipSuccess ? e1 : e2));
     return MC_OK;
 }
 

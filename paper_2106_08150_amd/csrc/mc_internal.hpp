@@ -74,7 +74,10 @@ struct QueryArgs {
     uint32_t* out_top;            // n_records * top_m * 3 u32, or null
     uint32_t* queue;              // overflow record ids (capacity n_records)
     uint32_t* counters;
+    unsigned long long* qstats;   // kNumQueryStats running totals
 };
+
+enum QueryStat { kQsFeatures = 0, kQsLocations = 1, kQsProbes = 2, kNumQueryStats = 4 };
 
 constexpr uint32_t kListSmall = 512;     // candidate locations per record, fast path
 constexpr uint32_t kListLarge = 16384;   // large-list pass (one wave per workgroup)
@@ -97,6 +100,9 @@ hipError_t launch_dump(const unsigned long long* table, uint64_t nb, uint32_t lo
                        hipStream_t st);
 hipError_t launch_count_valid(const unsigned long long* table, uint64_t nb,
                               unsigned long long* count, hipStream_t st);
-hipError_t launch_classify(const QueryArgs& a, hipStream_t st);
+// Fast path (one wave per record, small LDS list) and the large-list pass
+// over the records the fast path queued.
+hipError_t launch_classify_fast(const QueryArgs& a, hipStream_t st);
+hipError_t launch_classify_large(const QueryArgs& a, hipStream_t st);
 
 }  // namespace mc

@@ -28,7 +28,7 @@ struct QueryLds {
 // has an empty slot. Returns false once the list outgrew LCAP.
 template <uint32_t LCAP>
 __device__ bool lookup(const QueryArgs& a, const uint32_t* F, uint32_t nf, uint32_t* list,
-                       uint32_t& nlist) {
+                       uint32_t& nlist, uint32_t& probes) {
     constexpr int NB = 8;
     const int lane = lane_id();
     const int g = lane >> 4, gl = lane & 15;
@@ -51,8 +51,10 @@ __device__ bool lookup(const QueryArgs& a, const uint32_t* F, uint32_t nf, uint3
             if (ballot(any) == 0) break;
             uint64_t sl[NB];
 #pragma unroll
-            for (int q = 0; q < NB; ++q)
+            for (int q = 0; q < NB; ++q) {
                 sl[q] = pend[q] ? (uint64_t)a.table[b[q] * kSlots + gl] : kEmpty;
+                probes += popc64(ballot(pend[q] && gl == 0));
+            }
 #pragma unroll
             for (int q = 0; q < NB; ++q) {
                 bool m = pend[q] && sl[q] != kEmpty && (uint32_t)(sl[q] >> 32) == f[q] &&
@@ -152,8 +154,13 @@ __device__ __forceinline__ void write_result(const QueryArgs& a, uint32_t rec, u
     }
 }
 
+struct WaveStats {
+    uint32_t features = 0, locations = 0, probes = 0;
+};
+
 template <uint32_t LCAP, int KPL>
-__device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>& L, bool big) {
+__device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>& L, bool big,
+                                WaveStats& ws) {
     const int lane = lane_id();
     uint64_t o0, o1, o2;
     if (a.paired) {
@@ -193,12 +200,16 @@ __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>
             nf += sketch_window<KPL>(L.stage, x0, nk, a.k, a.s, L.feats + nf);
             wave_lds_sync();
             if (nf + a.s > kMaxFeat) {
-                fits = lookup<LCAP>(a, L.feats, nf, L.list, nlist);
+                ws.features += nf;
+                fits = lookup<LCAP>(a, L.feats, nf, L.list, nlist, ws.probes);
                 nf = 0;
             }
         }
     }
-    if (fits && nf) fits = lookup<LCAP>(a, L.feats, nf, L.list, nlist);
+    if (fits && nf) {
+        ws.features += nf;
+        fits = lookup<LCAP>(a, L.feats, nf, L.list, nlist, ws.probes);
+    }
     if (!fits) {
         if (!big) {
             if (lane == 0) {
@@ -213,6 +224,7 @@ __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>
     }
     wave_lds_sync();
     const uint32_t n = nlist;
+    ws.locations += n;
     sort_list<LCAP>(L.list, n);
 
     // run-length encoding: uidx[u] = first index of the u-th distinct location
@@ -281,33 +293,50 @@ __global__ __launch_bounds__(WPB * 64) void k_classify(QueryArgs a, int big) {
     __shared__ QueryLds<LCAP> L[WPB];
     const int wave = (int)uniform(threadIdx.x >> 6);
     const uint32_t n_iter = big ? uniform(a.counters[kQOverflow]) : a.n_records;
+    WaveStats ws;
     for (uint32_t it = blockIdx.x * WPB + wave; it < n_iter; it += gridDim.x * WPB) {
         const uint32_t rec = big ? uniform(a.queue[it]) : it;
-        classify_record<LCAP, KPL>(a, rec, L[wave], big != 0);
+        classify_record<LCAP, KPL>(a, rec, L[wave], big != 0, ws);
+    }
+    // work of records that go on to the large-list pass counts in both passes
+    if (lane_id() == 0 && a.qstats) {
+        if (ws.features) atomicAdd(&a.qstats[kQsFeatures], (unsigned long long)ws.features);
+        if (ws.locations) atomicAdd(&a.qstats[kQsLocations], (unsigned long long)ws.locations);
+        if (ws.probes) atomicAdd(&a.qstats[kQsProbes], (unsigned long long)ws.probes);
     }
 }
 
-template <int KPL>
+template <bool kLarge, int KPL>
 hipError_t launch_kpl(const QueryArgs& a, hipStream_t st) {
-    constexpr int WPB = 4;
-    uint64_t blocks = ((uint64_t)a.n_records + WPB - 1) / WPB;
-    if (blocks > 16384) blocks = 16384;
-    if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL((k_classify<kListSmall, WPB, KPL>), dim3((unsigned)blocks), dim3(WPB * 64),
-                       0, st, a, 0);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_classify<kListLarge, 1, KPL>), dim3(512), dim3(64), 0, st, a, 1);
+    if (kLarge) {
+        hipLaunchKernelGGL((k_classify<kListLarge, 1, KPL>), dim3(512), dim3(64), 0, st, a, 1);
+    } else {
+        constexpr int WPB = 4;
+        uint64_t blocks = ((uint64_t)a.n_records + WPB - 1) / WPB;
+        if (blocks > 16384) blocks = 16384;
+        if (blocks < 1) blocks = 1;
+        hipLaunchKernelGGL((k_classify<kListSmall, WPB, KPL>), dim3((unsigned)blocks),
+                           dim3(WPB * 64), 0, st, a, 0);
+    }
     return hipGetLastError();
+}
+
+template <bool kLarge>
+hipError_t launch_any(const QueryArgs& a, hipStream_t st) {
+    if (a.n_records == 0) return hipSuccess;
+    if (a.S <= 64) return launch_kpl<kLarge, 1>(a, st);
+    if (a.S <= 128) return launch_kpl<kLarge, 2>(a, st);
+    return launch_kpl<kLarge, 4>(a, st);
 }
 
 }  // namespace
 
-hipError_t launch_classify(const QueryArgs& a, hipStream_t st) {
-    if (a.n_records == 0) return hipSuccess;
-    if (a.S <= 64) return launch_kpl<1>(a, st);
-    if (a.S <= 128) return launch_kpl<2>(a, st);
-    return launch_kpl<4>(a, st);
+hipError_t launch_classify_fast(const QueryArgs& a, hipStream_t st) {
+    return launch_any<false>(a, st);
+}
+
+hipError_t launch_classify_large(const QueryArgs& a, hipStream_t st) {
+    return launch_any<true>(a, st);
 }
 
 }  // namespace mc

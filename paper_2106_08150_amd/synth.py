@@ -50,9 +50,15 @@ def random_text(rng: np.random.Generator, n: int) -> np.ndarray:
 def substitute(rng: np.random.Generator, text: np.ndarray, d: float) -> np.ndarray:
     """Copy of ``text`` with each letter replaced w.p. ``d`` by another letter."""
     out = np.array(text, dtype=np.uint8, copy=True)
+    substitute_inplace(rng, out, d)
+    return out
+
+
+def substitute_inplace(rng: np.random.Generator, out: np.ndarray, d: float) -> None:
+    """In-place form of :func:`substitute` (same random draws)."""
     n = out.size
     if d <= 0.0 or n == 0:
-        return out
+        return
     # Bernoulli(d) sites as cumulative geometric gaps.
     est = int(n * d + 10 * np.sqrt(n * d + 1) + 16)
     pos = np.cumsum(rng.geometric(d, size=est)) - 1
@@ -62,7 +68,6 @@ def substitute(rng: np.random.Generator, text: np.ndarray, d: float) -> np.ndarr
     pos = pos[pos < n]
     pick = rng.integers(0, 3, size=pos.size)
     out[pos] = _OTHER[out[pos], pick]
-    return out
 
 
 def reverse_complement_text(text: np.ndarray) -> np.ndarray:
@@ -134,7 +139,7 @@ def tiny_genomes(seed: int = 101, length: int = 100_000) -> Genomes:
 
 def sample_reads(genomes: Genomes, n: int, length: int, seed: int,
                  error: float = 0.01, foreign: float = 0.0,
-                 chunk: int = 200_000) -> Reads:
+                 chunk: int = 200_000, progress=None) -> Reads:
     """``n`` single-end reads of a fixed ``length`` (see the module rules)."""
     rng = rng_for(seed)
     off_g = genomes.offsets
@@ -142,15 +147,14 @@ def sample_reads(genomes: Genomes, n: int, length: int, seed: int,
     ok = np.nonzero(lens >= length)[0]
     text = np.empty(n * length, dtype=np.uint8)
     origin = np.empty(n, dtype=np.int64)
-    ar = np.arange(length, dtype=np.int64)
     for c0 in range(0, n, chunk):
         m = min(chunk, n - c0)
         gi = ok[rng.integers(0, ok.size, size=m)]
         is_foreign = rng.random(m) < foreign
         start = (rng.random(m) * (lens[gi] - length + 1)).astype(np.int64)
         rev = rng.random(m) < 0.5
-        idx = (off_g[gi].astype(np.int64) + start)[:, None] + ar[None, :]
-        block = genomes.text[idx]
+        rows = np.lib.stride_tricks.sliding_window_view(genomes.text, length)
+        block = rows[off_g[gi].astype(np.int64) + start]
         block[rev] = _COMP[block[rev][:, ::-1]]
         nf = int(is_foreign.sum())
         if nf:
@@ -158,6 +162,8 @@ def sample_reads(genomes: Genomes, n: int, length: int, seed: int,
         flat = substitute(rng, block.reshape(-1), error)
         text[c0 * length:(c0 + m) * length] = flat
         origin[c0:c0 + m] = np.where(is_foreign, -1, gi)
+        if progress is not None and (c0 // chunk) % 10 == 9:
+            progress(f"reads {c0 + m}/{n}")
     offsets = np.arange(n + 1, dtype=np.uint64) * np.uint64(length)
     return Reads(text, offsets, False, origin)
 
@@ -173,7 +179,7 @@ def clustered_genomes(n_clusters: int, per_cluster: int, total_bp: float,
                       seed: int, div_lo: float = 0.02, div_hi: float = 0.15,
                       median_bp: float = 4e6, sigma: float = 0.4,
                       clip: tuple[float, float] = (1e6, 1e7),
-                      level1: int | None = None) -> Genomes:
+                      level1: int | None = None, progress=None) -> Genomes:
     """Clusters of mutated copies with log-normal lengths.
 
     Lengths are log-normal around ``median_bp`` (shape ``sigma``), clipped to
@@ -202,7 +208,18 @@ def clustered_genomes(n_clusters: int, per_cluster: int, total_bp: float,
         parents[cl_base + c] = l1_base + (c * level1) // n_clusters
         for j in range(3):
             parents[sub_base + 3 * c + j] = cl_base + c
-    chunks, taxa = [], np.zeros(n, dtype=np.uint32)
+    taxa = np.zeros(n, dtype=np.uint32)
+    # genomes are stored in generation order: cluster by cluster, group by group
+    order = []
+    for c in range(n_clusters):
+        ids = np.arange(c * per_cluster, (c + 1) * per_cluster)
+        for grp in np.array_split(np.arange(per_cluster), 3):
+            order.extend(int(ids[m]) for m in grp)
+    out_len = lengths[np.array(order)]
+    off = np.zeros(n + 1, dtype=np.uint64)
+    np.cumsum(out_len, out=off[1:])
+    text = np.empty(int(off[-1]), dtype=np.uint8)
+    pos = 0
     for c in range(n_clusters):
         ids = np.arange(c * per_cluster, (c + 1) * per_cluster)
         root = random_text(rng, int(lengths[ids].max()))
@@ -211,21 +228,26 @@ def clustered_genomes(n_clusters: int, per_cluster: int, total_bp: float,
         for gidx, grp in enumerate(groups):
             for m in grp:
                 gid = int(ids[m])
-                chunks.append(substitute(rng, root[:lengths[gid]], float(divs[m])))
+                L = int(lengths[gid])
+                dst = text[int(off[pos]):int(off[pos]) + L]
+                dst[:] = root[:L]
+                substitute_inplace(rng, dst, float(divs[m]))
                 parents[leaf_base + gid] = sub_base + 3 * c + gidx
                 taxa[gid] = leaf_base + gid
-    text, off = _pack(chunks)
-    return Genomes(text, np.diff(off).astype(np.uint64), taxa, parents)
+                pos += 1
+        if progress is not None and c % 10 == 9:
+            progress(f"clusters {c + 1}/{n_clusters}")
+    return Genomes(text, out_len.astype(np.uint64), taxa[np.array(order)], parents)
 
 
-def scale_genomes(seed: int = 201, total_bp: float = 4.0e9) -> Genomes:
+def scale_genomes(seed: int = 201, total_bp: float = 4.0e9, progress=None) -> Genomes:
     """1,000 genomes = 100 clusters x 10 (about 4 Gbp), 5-level taxonomy."""
-    return clustered_genomes(100, 10, total_bp, seed, level1=20)
+    return clustered_genomes(100, 10, total_bp, seed, level1=20, progress=progress)
 
 
-def scale_reads(genomes: Genomes, n: int = 10_000_000, seed: int = 202) -> Reads:
+def scale_reads(genomes: Genomes, n: int = 10_000_000, seed: int = 202, progress=None) -> Reads:
     """150 bp reads, 1% substitutions, 5% foreign."""
-    return sample_reads(genomes, n, 150, seed, error=0.01, foreign=0.05)
+    return sample_reads(genomes, n, 150, seed, error=0.01, foreign=0.05, progress=progress)
 
 
 def mixed_records(genomes: Genomes, n: int, seed: int = 301, error: float = 0.01,
