@@ -162,14 +162,20 @@ int mc_classify_ex(mc_db* db, const char* reads, const uint64_t* offsets, uint32
  * the last call whose candidate list was too long (MC_ERR_LIST if > 0). */
 int mc_db_query_status(mc_db* db, void* stream, uint64_t* n_too_long);
 
-/* Inspection: when profiling is enabled, the library brackets its two
- * dominant launches with HIP events on the launch stream: the build kernel of
- * mc_db_add_targets* and the fast-path classify kernel of mc_classify*.
- * mc_db_kernel_times waits for those events, returns the summed milliseconds
- * and launch counts since the previous call, and resets them. */
+/* Inspection: when profiling is enabled, the library brackets its main
+ * launches with HIP events on the launch stream: the three build kernels of
+ * mc_db_add_targets* (sketch, partition scatter, insert) and the fast-path
+ * classify kernel of mc_classify*. mc_db_kernel_times waits for those events
+ * and writes, per kind (MC_K_*), the summed milliseconds and the number of
+ * launches since the previous call into ms[MC_K_COUNT] and
+ * launches[MC_K_COUNT] (host arrays), then resets them. */
+#define MC_K_SKETCH   0
+#define MC_K_SCATTER  1
+#define MC_K_INSERT   2
+#define MC_K_CLASSIFY 3
+#define MC_K_COUNT    4
 int mc_db_set_profiling(mc_db* db, int enable);
-int mc_db_kernel_times(mc_db* db, double* build_ms, uint64_t* n_build, double* classify_ms,
-                       uint64_t* n_classify);
+int mc_db_kernel_times(mc_db* db, double* ms, uint64_t* launches);
 
 /* Counters of the handle (synchronous). */
 int mc_db_get_stats(mc_db* db, mc_db_stats* out);

@@ -97,8 +97,7 @@ def lib():
         L.mc_db_sketch.argtypes = [vp, vp, vp, u32, vp, vp, vp]
         L.mc_db_set_profiling.restype, L.mc_db_set_profiling.argtypes = i32, [vp, i32]
         L.mc_db_kernel_times.restype = i32
-        L.mc_db_kernel_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(u64),
-                                         C.POINTER(C.c_double), C.POINTER(u64)]
+        L.mc_db_kernel_times.argtypes = [vp, vp, vp]
         _lib = L
     return _lib
 
@@ -217,13 +216,15 @@ def mc_db_set_profiling(db: int, enable: bool) -> None:
     _check(lib().mc_db_set_profiling(db, int(enable)))
 
 
+KERNEL_KINDS = ("sketch", "scatter", "insert", "classify")
+
+
 def mc_db_kernel_times(db: int) -> dict:
-    """Summed ms and launch counts of the profiled build / classify kernels."""
-    bm, cm = C.c_double(0), C.c_double(0)
-    nb, nc = C.c_uint64(0), C.c_uint64(0)
-    _check(lib().mc_db_kernel_times(db, C.byref(bm), C.byref(nb), C.byref(cm), C.byref(nc)))
-    return {"build_ms": bm.value, "n_build": int(nb.value), "classify_ms": cm.value,
-            "n_classify": int(nc.value)}
+    """Summed ms and launch counts per profiled kernel kind since the last call."""
+    ms = np.zeros(len(KERNEL_KINDS), np.float64)
+    n = np.zeros(len(KERNEL_KINDS), np.uint64)
+    _check(lib().mc_db_kernel_times(db, _np_ptr(ms), _np_ptr(n)))
+    return {k: {"ms": float(ms[i]), "launches": int(n[i])} for i, k in enumerate(KERNEL_KINDS)}
 
 
 # ------------------------------------------------------------ wrapper ----

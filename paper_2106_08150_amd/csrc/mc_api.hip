@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -41,8 +42,11 @@ int fail(int code, const char* fmt, ...) {
     } while (0)
 
 constexpr double kDefaultLoad = 0.5;
+constexpr uint64_t kMaxSlotsPerChunk = 1ull << 30;      // pair slots per build chunk (8 GiB)
+constexpr uint64_t kPartBytes = 256ull << 20;           // target table bytes per partition
 constexpr uint64_t kMinBuckets = 64;
 constexpr uint64_t kCandCapMax = 1ull << 24;
+constexpr uint32_t kMaxPartsApi = 256;
 
 struct Workspace {
     uint32_t* queue = nullptr;
@@ -77,6 +81,7 @@ struct mc_db {
     double load = kDefaultLoad;
     // table
     unsigned long long* table = nullptr;
+    uint32_t* bcount = nullptr;       // fill counter per bucket
     uint64_t nb = 0;
     uint64_t slots_used = 0;          // occupied slots (stored + tombstones) since the last rehash
     unsigned long long* counters = nullptr;   // kNumBuildCounters
@@ -95,9 +100,16 @@ struct mc_db {
     mc_db_stats st{};
     // per-stream query workspaces
     std::map<hipStream_t, Workspace> ws;
-    // profiling
+    // build scratch (grow-only): per-window pairs, partitioned pairs, partition data
+    unsigned long long* pairs = nullptr;
+    unsigned long long* parted = nullptr;
+    uint64_t pairs_cap = 0;
+    uint32_t* hist = nullptr;
+    unsigned long long* part_start = nullptr;
+    unsigned long long* cursor = nullptr;
+    // profiling: one timer per profiled kernel kind (MC_K_*)
     bool profiling = false;
-    Timed t_build, t_query;
+    Timed timers[MC_K_COUNT];
 };
 
 namespace {
@@ -125,24 +137,31 @@ int ensure_capacity(mc_db* db, uint64_t extra, hipStream_t st) {
     if (db->table) nb = std::max<uint64_t>(nb, db->nb + db->nb / 2);   // grow by >= 1.5x
     nb = std::max<uint64_t>(nb, kMinBuckets);
     unsigned long long* t = nullptr;
+    uint32_t* cnt = nullptr;
     int rc = dev_alloc(&t, nb * kSlots);
     if (rc) return rc;
+    rc = dev_alloc(&cnt, nb);
+    if (rc) { (void)hipFree(t); return rc; }
     HIP_TRY(launch_fill_u64(t, nb * kSlots, ~0ull, st));
+    HIP_TRY(launch_fill_u32(cnt, nb, 0u, st));
     if (db->table) {
         HIP_TRY(launch_fill_u64(db->counters, kNumBuildCounters, 0ull, st));
-        HIP_TRY(launch_rehash(db->table, db->nb, t, nb, db->counters, st));
+        HIP_TRY(launch_rehash(db->table, db->nb, t, cnt, nb, db->counters, st));
         unsigned long long c[kNumBuildCounters];
         HIP_TRY(hipMemcpyAsync(c, db->counters, sizeof c, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         if (c[kCntFull]) {
             (void)hipFree(t);
+            (void)hipFree(cnt);
             return fail(MC_ERR_TABLE_FULL, "rehash found no free slot for %llu entries",
                         (unsigned long long)c[kCntFull]);
         }
         HIP_TRY(hipFree(db->table));
+        HIP_TRY(hipFree(db->bcount));
         db->slots_used = c[kCntMoved];
         db->st.n_rehash += 1;
     }
+    db->bcount = cnt;
     db->table = t;
     db->nb = nb;
     return MC_OK;
@@ -200,6 +219,97 @@ hipError_t drain(Timed& t, double* ms, uint64_t* n) {
     return err;
 }
 
+int ensure_scratch(mc_db* db, uint64_t slots) {
+    if (!db->hist) {
+        int rc = dev_alloc(&db->hist, kMaxPartsApi);
+        if (!rc) rc = dev_alloc(&db->part_start, kMaxPartsApi + 1);
+        if (!rc) rc = dev_alloc(&db->cursor, kMaxPartsApi);
+        if (rc) return rc;
+    }
+    if (slots <= db->pairs_cap) return MC_OK;
+    (void)hipFree(db->pairs);
+    (void)hipFree(db->parted);
+    db->pairs = db->parted = nullptr;
+    db->pairs_cap = 0;
+    int rc = dev_alloc(&db->pairs, slots);
+    if (!rc) rc = dev_alloc(&db->parted, slots);
+    if (rc) return rc;
+    db->pairs_cap = slots;
+    return MC_OK;
+}
+
+// Table partitions for the insert pass: slices of about kPartBytes (the
+// MC_PART_MB environment variable overrides the slice size for tuning).
+uint32_t partition_bits(uint64_t table_bytes) {
+    uint64_t part = kPartBytes;
+    if (const char* env = getenv("MC_PART_MB")) {
+        long mb = atol(env);
+        if (mb > 0) part = (uint64_t)mb << 20;
+    }
+    uint32_t bits = 0;
+    while (bits < 8 && (table_bytes >> bits) > part) ++bits;
+    return bits;
+}
+
+// Build pipeline over targets [t0, t1) of the call (one chunk).
+int build_chunk(mc_db* db, const uint8_t* genomes, const std::vector<TargetDesc>& all,
+                uint32_t t0, uint32_t t1, hipStream_t st) {
+    const uint32_t n = t1 - t0;
+    std::vector<TargetDesc> td(all.begin() + t0, all.begin() + t1);
+    std::vector<uint64_t> tile_first(n + 1, 0);
+    const uint64_t off0 = td[0].off, win0 = td[0].win_base;
+    for (uint32_t i = 0; i < n; ++i) {
+        td[i].off -= off0;
+        td[i].win_base -= win0;
+        tile_first[i + 1] = tile_first[i] + (td[i].nw + kTileWindows - 1) / kTileWindows;
+    }
+    const uint64_t wins = td[n - 1].win_base + td[n - 1].nw;
+    const uint64_t slots = wins * db->s;
+    if (slots == 0) return MC_OK;
+    int rc = ensure_scratch(db, slots);
+    if (rc) return rc;
+    TargetDesc* d_td = nullptr;
+    uint64_t* d_tf = nullptr;
+    rc = dev_alloc(&d_td, n);
+    if (rc) return rc;
+    rc = dev_alloc(&d_tf, n + 1);
+    if (rc) { (void)hipFree(d_td); return rc; }
+    struct Free {
+        void* a; void* b;
+        ~Free() { (void)hipFree(a); (void)hipFree(b); }
+    } guard{d_td, d_tf};
+    HIP_TRY(hipMemcpyAsync(d_td, td.data(), n * sizeof(TargetDesc), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(d_tf, tile_first.data(), (n + 1) * 8, hipMemcpyHostToDevice, st));
+    HIP_TRY(launch_fill_u32(db->hist, kMaxPartsApi, 0u, st));
+
+    BuildArgs a{};
+    a.text = genomes + off0;
+    a.text_len = td[n - 1].off + td[n - 1].len;
+    a.targets = d_td;
+    a.n_targets = n;
+    a.tile_first = d_tf;
+    a.n_tiles = tile_first[n];
+    a.k = db->k; a.w = db->w; a.S = db->S; a.s = db->s;
+    a.table = db->table;
+    a.bcount = db->bcount;
+    a.nb = db->nb;
+    a.cap_dist = db->cap_dist;
+    a.cand = db->cand;
+    a.cand_cap = db->cand_cap;
+    a.counters = db->counters;
+    a.pairs = db->pairs;
+    a.parted = db->parted;
+    a.part_bits = partition_bits(db->nb * kSlots * 8);
+    a.hist = db->hist;
+    a.part_start = db->part_start;
+    a.cursor = db->cursor;
+    HIP_TRY(timed_launch(db, db->timers[MC_K_SKETCH], st, [&] { return launch_sketch(a, true, st); }));
+    HIP_TRY(timed_launch(db, db->timers[MC_K_SCATTER], st,
+                         [&] { return launch_partition(a, slots, st); }));
+    HIP_TRY(timed_launch(db, db->timers[MC_K_INSERT], st, [&] { return launch_insert(a, slots, st); }));
+    return MC_OK;
+}
+
 // Shared by the host and device entry points: genomes is a device pointer.
 int add_targets_dev(mc_db* db, const uint8_t* genomes, const uint64_t* lengths,
                     const uint32_t* taxa, uint32_t n, hipStream_t st) {
@@ -208,7 +318,6 @@ int add_targets_dev(mc_db* db, const uint8_t* genomes, const uint64_t* lengths,
         return fail(MC_ERR_CAPACITY, "at most %u targets (have %zu, adding %u)", MC_MAX_TARGETS,
                     db->taxa.size(), n);
     std::vector<TargetDesc> td(n);
-    std::vector<uint64_t> tile_first(n + 1, 0);
     uint64_t off = 0, wins = 0;
     for (uint32_t i = 0; i < n; ++i) {
         uint64_t nw = num_windows(lengths[i], db->k, db->S);
@@ -216,7 +325,6 @@ int add_targets_dev(mc_db* db, const uint8_t* genomes, const uint64_t* lengths,
             return fail(MC_ERR_CAPACITY, "sequence %u has %llu windows (max %u)", i,
                         (unsigned long long)nw, MC_MAX_WINDOWS);
         td[i] = TargetDesc{off, lengths[i], wins, (uint32_t)db->taxa.size() + i, (uint32_t)nw};
-        tile_first[i + 1] = tile_first[i] + (nw + kTileWindows - 1) / kTileWindows;
         off += lengths[i];
         wins += nw;
     }
@@ -232,35 +340,19 @@ int add_targets_dev(mc_db* db, const uint8_t* genomes, const uint64_t* lengths,
         if (rc) return rc;
         db->cand_cap = cand_need;
     }
-    TargetDesc* d_td = nullptr;
-    uint64_t* d_tf = nullptr;
-    rc = dev_alloc(&d_td, n);
-    if (rc) return rc;
-    rc = dev_alloc(&d_tf, n + 1);
-    if (rc) { (void)hipFree(d_td); return rc; }
-    struct Free {
-        void* a; void* b;
-        ~Free() { (void)hipFree(a); (void)hipFree(b); }
-    } guard{d_td, d_tf};
-    HIP_TRY(hipMemcpyAsync(d_td, td.data(), n * sizeof(TargetDesc), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(d_tf, tile_first.data(), (n + 1) * 8, hipMemcpyHostToDevice, st));
     HIP_TRY(launch_fill_u64(db->counters, kNumBuildCounters, 0ull, st));
-
-    BuildArgs a{};
-    a.text = genomes;
-    a.text_len = off;
-    a.targets = d_td;
-    a.n_targets = n;
-    a.tile_first = d_tf;
-    a.n_tiles = tile_first[n];
-    a.k = db->k; a.w = db->w; a.S = db->S; a.s = db->s;
-    a.table = db->table;
-    a.nb = db->nb;
-    a.cap_dist = db->cap_dist;
-    a.cand = db->cand;
-    a.cand_cap = db->cand_cap;
-    a.counters = db->counters;
-    HIP_TRY(timed_launch(db, db->t_build, st, [&] { return launch_build(a, true, st); }));
+    // chunks of whole targets with at most kMaxSlotsPerChunk pair slots
+    for (uint32_t t0 = 0; t0 < n;) {
+        uint32_t t1 = t0;
+        uint64_t slots = 0;
+        while (t1 < n && (t1 == t0 || slots + (uint64_t)td[t1].nw * db->s <= kMaxSlotsPerChunk)) {
+            slots += (uint64_t)td[t1].nw * db->s;
+            ++t1;
+        }
+        rc = build_chunk(db, genomes, td, t0, t1, st);
+        if (rc) return rc;
+        t0 = t1;
+    }
     unsigned long long c[kNumBuildCounters];
     HIP_TRY(hipMemcpyAsync(c, db->counters, sizeof c, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -356,9 +448,14 @@ int mc_db_destroy(mc_db* db) {
         (void)hipFree(kv.second.counters);
         (void)hipFree(kv.second.qstats);
     }
-    (void)drain(db->t_build, nullptr, nullptr);
-    (void)drain(db->t_query, nullptr, nullptr);
+    for (auto& t : db->timers) (void)drain(t, nullptr, nullptr);
+    (void)hipFree(db->pairs);
+    (void)hipFree(db->parted);
+    (void)hipFree(db->hist);
+    (void)hipFree(db->part_start);
+    (void)hipFree(db->cursor);
     (void)hipFree(db->table);
+    (void)hipFree(db->bcount);
     (void)hipFree(db->counters);
     (void)hipFree(db->cand);
     (void)hipFree(db->d_taxa);
@@ -505,7 +602,7 @@ int mc_classify_ex(mc_db* db, const char* reads, const uint64_t* offsets, uint32
     a.queue = w->queue;
     a.counters = w->counters;
     a.qstats = w->qstats;
-    HIP_TRY(timed_launch(db, db->t_query, st, [&] { return launch_classify_fast(a, st); }));
+    HIP_TRY(timed_launch(db, db->timers[MC_K_CLASSIFY], st, [&] { return launch_classify_fast(a, st); }));
     HIP_TRY(launch_classify_large(a, st));
     return MC_OK;
 }
@@ -563,7 +660,7 @@ int mc_db_get_stats(mc_db* db, mc_db_stats* out) {
     out->n_windows = db->n_windows;
     out->n_pairs_stored = stored;
     out->n_buckets = db->nb;
-    out->table_bytes = db->nb * kSlots * 8;
+    out->table_bytes = db->nb * (kSlots * 8 + 4);
     return MC_OK;
 }
 
@@ -573,15 +670,16 @@ int mc_db_set_profiling(mc_db* db, int enable) {
     return MC_OK;
 }
 
-int mc_db_kernel_times(mc_db* db, double* build_ms, uint64_t* n_build, double* classify_ms,
-                       uint64_t* n_classify) {
+int mc_db_kernel_times(mc_db* db, double* ms, uint64_t* launches) {
     if (int rc = check_db(db)) return rc;
+    if (!ms || !launches) return fail(MC_ERR_INVALID_ARG, "NULL output");
     DeviceGuard dg(db->device);
-    hipError_t e1 = drain(db->t_build, build_ms, n_build);
-    hipError_t e2 = drain(db->t_query, classify_ms, n_classify);
-    if (e1 != hipSuccess || e2 != hipSuccess)
-        return fail(MC_ERR_HIP, "kernel timing: %s",
-                    hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+    hipError_t err = hipSuccess;
+    for (int k = 0; k < MC_K_COUNT; ++k) {
+        hipError_t e = drain(db->timers[k], &ms[k], &launches[k]);
+        if (e != hipSuccess) err = e;
+    }
+    if (err != hipSuccess) return fail(MC_ERR_HIP, "kernel timing: %s", hipGetErrorString(err));
     return MC_OK;
 }
 
@@ -658,7 +756,7 @@ int mc_db_sketch(mc_db* db, const char* seqs_dev, const uint64_t* lengths, uint3
     hipError_t e = hipMemcpyAsync(d_td, td.data(), n * sizeof(TargetDesc), hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(d_tf, tile_first.data(), (n + 1) * 8, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = launch_build(a, false, st);
+    if (e == hipSuccess) e = launch_sketch(a, false, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     (void)hipFree(d_td);
     (void)hipFree(d_tf);

@@ -43,6 +43,36 @@ __device__ __forceinline__ uint32_t shfl_xor(uint32_t v, int m) {
     return shfl_idx(v, lane_id() ^ m);
 }
 
+// Value of lane (lane ^ M), M a power of two < 64: DPP quad permutes for 1
+// and 2, a row rotate for 8 (rotating a 16-lane row by 8 is xor 8),
+// ds_swizzle's xor mode for 4 and 16 (within 32-lane halves), and a
+// backwards permute for 32.
+template <int M>
+__device__ __forceinline__ uint32_t xor_lanes(uint32_t v) {
+    if constexpr (M == 1) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);
+    } else if constexpr (M == 2) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);
+    } else if constexpr (M == 8) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, false);
+    } else if constexpr (M == 4 || M == 16) {
+        return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, (M << 10) | 0x1F);
+    } else {
+        return shfl_idx(v, lane_id() ^ M);
+    }
+}
+
+__device__ __forceinline__ uint32_t xor_lanes_c(uint32_t v, int m) {
+    switch (m) {
+        case 1: return xor_lanes<1>(v);
+        case 2: return xor_lanes<2>(v);
+        case 4: return xor_lanes<4>(v);
+        case 8: return xor_lanes<8>(v);
+        case 16: return xor_lanes<16>(v);
+        default: return xor_lanes<32>(v);
+    }
+}
+
 __device__ __forceinline__ uint32_t uniform(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
@@ -60,6 +90,23 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
         v = o > v ? o : v;
     }
     return v;
+}
+
+// Maximum over the wave: row rotations by 1, 2, 4 and 8 (DPP) reduce each
+// 16-lane row, then the four row results are combined in scalar registers.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+    uint32_t o;
+    o = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x121, 0xF, 0xF, false); v = v > o ? v : o;
+    o = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x122, 0xF, 0xF, false); v = v > o ? v : o;
+    o = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x124, 0xF, 0xF, false); v = v > o ? v : o;
+    o = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, false); v = v > o ? v : o;
+    uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane((int)v, 0);
+    uint32_t r1 = (uint32_t)__builtin_amdgcn_readlane((int)v, 16);
+    uint32_t r2 = (uint32_t)__builtin_amdgcn_readlane((int)v, 32);
+    uint32_t r3 = (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
+    r0 = r0 > r1 ? r0 : r1;
+    r2 = r2 > r3 ? r2 : r3;
+    return r0 > r2 ? r0 : r2;
 }
 
 // Orders LDS accesses of different lanes of one wave (LDS executes a wave's
@@ -200,7 +247,7 @@ __device__ __forceinline__ void wave_sort(uint32_t (&v)[KPL]) {
 #pragma unroll
                 for (int r = 0; r < KPL; ++r) {
                     const int e = r * kWave + lane;
-                    uint32_t o = shfl_xor(v[r], stride);
+                    uint32_t o = xor_lanes_c(v[r], stride);
                     const bool asc = (e & size) == 0;
                     const bool lower = (lane & stride) == 0;
                     uint32_t lo = v[r] < o ? v[r] : o, hi = v[r] < o ? o : v[r];
@@ -211,13 +258,15 @@ __device__ __forceinline__ void wave_sort(uint32_t (&v)[KPL]) {
     }
 }
 
-// After wave_sort: write the s smallest distinct keys (kBadLoc excluded) to
-// sk[0..] in ascending order and return their number. If a valid k-mer hashed
-// to 0xFFFFFFFF (has_top) and fewer than s smaller distinct values exist, that
+// After wave_sort: write the s smallest distinct keys (0xFFFFFFFF excluded)
+// to sk[0..] in ascending order and return their number; `distinct` receives
+// the number of distinct keys below 0xFFFFFFFF. If a valid k-mer hashed to
+// 0xFFFFFFFF (has_top) and fewer than s smaller distinct values exist, that
 // value is appended as the last element.
 template <int KPL>
 __device__ __forceinline__ uint32_t select_distinct(const uint32_t (&v)[KPL], bool has_top,
-                                                    uint32_t s, uint32_t* sk) {
+                                                    uint32_t s, uint32_t* sk,
+                                                    uint32_t& distinct) {
     const int lane = lane_id();
     uint32_t base = 0, prev_last = 0;
 #pragma unroll
@@ -232,6 +281,7 @@ __device__ __forceinline__ uint32_t select_distinct(const uint32_t (&v)[KPL], bo
         base += popc64(bal);
         prev_last = (uint32_t)__builtin_amdgcn_readlane((int)v[r], kWave - 1);
     }
+    distinct = base;
     uint32_t n = base < s ? base : s;
     if (has_top && base < s) {
         if (lane == 0) sk[base] = 0xFFFFFFFFu;
@@ -242,9 +292,17 @@ __device__ __forceinline__ uint32_t select_distinct(const uint32_t (&v)[KPL], bo
 
 // Sketch of one window whose nk k-mer starts begin x0 bases after the first
 // staged word: h1 of each valid canonical k-mer, then the s smallest distinct.
+// scratch: 64 words of LDS owned by the wave.
+//
+// For windows of more than 64 k-mers the wave first keeps only hashes below a
+// threshold T chosen so that about 1.75 s of them are expected; if at least s
+// distinct values lie below T, the s smallest of the window are exactly the s
+// smallest of those candidates, which fit one per lane. Otherwise (fewer than
+// s distinct candidates, or more than 64) it sorts every hash of the window.
 template <int KPL>
 __device__ __forceinline__ uint32_t sketch_window(const Word* W, uint32_t x0, uint32_t nk,
-                                                  uint32_t k, uint32_t s, uint32_t* sk) {
+                                                  uint32_t k, uint32_t s, uint32_t* sk,
+                                                  uint32_t* scratch) {
     const int lane = lane_id();
     uint32_t key[KPL];
     bool top = false;
@@ -261,9 +319,37 @@ __device__ __forceinline__ uint32_t sketch_window(const Word* W, uint32_t x0, ui
             }
         }
     }
+    uint32_t distinct;
+    if constexpr (KPL >= 2) {
+        if (nk > (uint32_t)kWave) {
+            uint64_t t64 = ((uint64_t)(7u * s) << 32) / (4ull * nk);
+            const uint32_t T = t64 > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)t64;
+            uint64_t bal[KPL];
+            uint32_t c = 0;
+#pragma unroll
+            for (int r = 0; r < KPL; ++r) {
+                bal[r] = ballot(key[r] < T);
+                c += popc64(bal[r]);
+            }
+            if (c >= s && c <= (uint32_t)kWave) {
+                uint32_t base = 0;
+#pragma unroll
+                for (int r = 0; r < KPL; ++r) {
+                    if (key[r] < T) scratch[base + rank_below(bal[r])] = key[r];
+                    base += popc64(bal[r]);
+                }
+                wave_lds_sync();
+                uint32_t v[1] = {(uint32_t)lane < c ? scratch[lane] : 0xFFFFFFFFu};
+                wave_lds_sync();
+                wave_sort<1>(v);
+                uint32_t n = select_distinct<1>(v, false, s, sk, distinct);
+                if (distinct >= s) return n;
+            }
+        }
+    }
     bool has_top = ballot(top) != 0;
     wave_sort<KPL>(key);
-    return select_distinct<KPL>(key, has_top, s, sk);
+    return select_distinct<KPL>(key, has_top, s, sk, distinct);
 }
 
 // Stage the bytes [lo, hi) into words relative to A0 = lo & ~15, one word per

@@ -38,6 +38,7 @@ struct BuildArgs {
     uint32_t k, w, S, s;
     // insert mode
     unsigned long long* table;
+    uint32_t* bcount;             // per-bucket fill counters (slots claimed)
     uint64_t nb;                  // buckets
     uint32_t cap_dist;            // inserts at this probe distance or more are cap candidates
     uint32_t* cand;
@@ -46,6 +47,13 @@ struct BuildArgs {
     // sketch-export mode
     uint32_t* out_counts;
     uint32_t* out_feats;
+    // pair mode: per-window pairs, their partition histogram, partitioned copy
+    unsigned long long* pairs;          // n_windows * s slots
+    unsigned long long* parted;         // pairs in partition order
+    uint32_t part_bits;                 // 2^part_bits table partitions (<= 8)
+    uint32_t* hist;                     // 2^part_bits counters
+    unsigned long long* part_start;     // 2^part_bits + 1 offsets
+    unsigned long long* cursor;         // 2^part_bits scatter cursors
 };
 
 constexpr int kTileWindows = 32;  // windows per build workgroup tile
@@ -84,14 +92,18 @@ constexpr uint32_t kListLarge = 16384;   // large-list pass (one wave per workgr
 constexpr uint32_t kMaxTopM = 8;
 
 // Launchers (return hipError_t of the launch).
-hipError_t launch_build(const BuildArgs& a, bool insert, hipStream_t st);
+// Build pipeline: sketch (pairs + partition histogram, or the sketch export),
+// partition scan + scatter, insert.
+hipError_t launch_sketch(const BuildArgs& a, bool pairs, hipStream_t st);
+hipError_t launch_partition(const BuildArgs& a, uint64_t n_slots, hipStream_t st);
+hipError_t launch_insert(const BuildArgs& a, uint64_t max_items, hipStream_t st);
 hipError_t launch_cap_finalize(unsigned long long* table, uint64_t nb, uint32_t cap,
                                const uint32_t* cand, uint64_t n_cand, hipStream_t st);
 hipError_t launch_cap_scan(unsigned long long* table, uint64_t nb, uint32_t cap,
                            uint32_t cap_dist, hipStream_t st);
 hipError_t launch_rehash(const unsigned long long* old_table, uint64_t old_nb,
-                         unsigned long long* table, uint64_t nb, unsigned long long* counters,
-                         hipStream_t st);
+                         unsigned long long* table, uint32_t* bcount, uint64_t nb,
+                         unsigned long long* counters, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v,
                            hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st);

@@ -18,62 +18,71 @@ constexpr uint32_t kMaxFeat = 128; // sketch elements buffered before lookups
 template <uint32_t LCAP>
 struct QueryLds {
     Word stage[kStageWords];
+    uint32_t scratch[kWave];
     uint32_t feats[kMaxFeat];
-    uint32_t list[LCAP];
+    unsigned long long home[kMaxFeat];
+    uint32_t list[LCAP + 1];         // list[LCAP] takes the writes of non-matching lanes
     uint16_t uidx[LCAP + 2];
+    uint16_t score[LCAP];
+    uint32_t sel_t[kMaxTopM], sel_s[kMaxTopM], sel_b[kMaxTopM];   // top-m list
 };
 
-// Append the locations of features F[0..nf) to list (LDS). 16-lane groups
-// read one bucket line each; a feature's chain ends at the first bucket that
-// has an empty slot. Returns false once the list outgrew LCAP.
+// Append the locations of features F[0..nf) to list (LDS). Each feature's
+// home bucket is computed once (one lane per feature, kept in H). 16-lane
+// groups then read one bucket line per feature; a feature's chain ends at the
+// first bucket that has an empty slot. Pending work is tracked in wave-uniform
+// lane masks so that the loop has no per-lane branches: every group loads
+// every round (a finished group re-reads its last line), and lanes without a
+// match write to the dump slot list[LCAP]. Returns false once the list outgrew
+// LCAP.
 template <uint32_t LCAP>
-__device__ bool lookup(const QueryArgs& a, const uint32_t* F, uint32_t nf, uint32_t* list,
-                       uint32_t& nlist, uint32_t& probes) {
+__device__ bool lookup(const QueryArgs& a, const uint32_t* F, unsigned long long* H,
+                       uint32_t nf, uint32_t* list, uint32_t& nlist, uint32_t& probes) {
     constexpr int NB = 8;
-    const int lane = lane_id();
-    const int g = lane >> 4, gl = lane & 15;
+    const uint32_t lane = (uint32_t)lane_id();
+    const uint32_t g = lane >> 4, gl = lane & 15;
+    for (uint32_t i = lane; i < nf; i += kWave) H[i] = home_bucket(F[i], a.nb);
+    wave_lds_sync();
     for (uint32_t base = 0; base < nf; base += 4 * NB) {
-        uint32_t f[NB], d[NB];
+        uint32_t f[NB];
         uint64_t b[NB];
-        bool pend[NB];
+        uint32_t pg[NB];   // groups (bit g) whose q-th feature is still pending
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
-            uint32_t i = base + (uint32_t)g + 4u * (uint32_t)q;
-            pend[q] = i < nf;
-            f[q] = pend[q] ? F[i] : 0u;
-            b[q] = home_bucket(f[q], a.nb);
-            d[q] = 0;
+            const uint32_t i0 = base + 4u * (uint32_t)q;       // feature of group 0
+            const uint32_t ng = nf > i0 ? min(nf - i0, 4u) : 0u; // groups with a feature
+            pg[q] = (1u << ng) - 1u;
+            const uint32_t i = min(i0 + g, nf - 1);
+            f[q] = F[i];
+            b[q] = H[i];
         }
         while (true) {
-            bool any = false;
+            uint32_t any = 0;
 #pragma unroll
-            for (int q = 0; q < NB; ++q) any |= pend[q];
-            if (ballot(any) == 0) break;
+            for (int q = 0; q < NB; ++q) any |= pg[q];
+            if (any == 0) break;
             uint64_t sl[NB];
 #pragma unroll
             for (int q = 0; q < NB; ++q) {
-                sl[q] = pend[q] ? (uint64_t)a.table[b[q] * kSlots + gl] : kEmpty;
-                probes += popc64(ballot(pend[q] && gl == 0));
+                sl[q] = a.table[b[q] * kSlots + gl];
+                probes += (uint32_t)__popc(pg[q]);
             }
 #pragma unroll
             for (int q = 0; q < NB; ++q) {
-                bool m = pend[q] && sl[q] != kEmpty && (uint32_t)(sl[q] >> 32) == f[q] &&
-                         (uint32_t)sl[q] != kBadLoc;
-                uint64_t mb = ballot(m);
-                uint32_t pos = nlist + rank_below(mb);
-                if (m && pos < LCAP) list[pos] = (uint32_t)sl[q];
+                const uint32_t hi = (uint32_t)(sl[q] >> 32), lo = (uint32_t)sl[q];
+                const bool pend = (pg[q] >> g) & 1u;
+                const uint64_t mb = ballot(pend && hi == f[q] && lo != kBadLoc);
+                const bool mine = (mb >> lane) & 1ull;
+                const uint32_t pos = nlist + rank_below(mb);
+                list[mine && pos < LCAP ? pos : LCAP] = lo;
                 nlist += popc64(mb);
-                uint64_t emp = ballot(pend[q] && sl[q] == kEmpty);
-                bool done = ((emp >> (16 * g)) & 0xFFFFull) != 0;
-                if (pend[q]) {
-                    if (done) {
-                        pend[q] = false;
-                    } else {
-                        b[q] = next_bucket(b[q], a.nb);
-                        d[q] += 1;
-                        if ((uint64_t)d[q] > a.nb) pend[q] = false;
-                    }
-                }
+                const uint64_t emp = ballot(sl[q] == kEmpty);
+                uint32_t done = 0;
+#pragma unroll
+                for (int x = 0; x < 4; ++x)
+                    if ((emp >> (16 * x)) & 0xFFFFull) done |= 1u << x;
+                pg[q] &= ~done;
+                if ((pg[q] >> g) & 1u) b[q] = next_bucket(b[q], a.nb);
             }
             if (nlist > LCAP) return false;
         }
@@ -137,20 +146,18 @@ __device__ void sort_list(uint32_t* list, uint32_t n) {
     }
 }
 
+// Label and top-m list of a record (lane x writes the x-th top hit).
+template <typename Lds>
 __device__ __forceinline__ void write_result(const QueryArgs& a, uint32_t rec, uint32_t label,
-                                             const uint32_t* st, const uint32_t* ss,
-                                             const uint32_t* sb, uint32_t nsel) {
+                                             const Lds& L, uint32_t nsel) {
     const uint32_t lane = (uint32_t)lane_id();
     if (lane == 0) a.out_labels[rec] = label;
     if (a.out_top && lane < a.top_m) {
-        uint32_t t = kNone, s = 0, bgn = 0;
-#pragma unroll
-        for (uint32_t x = 0; x < kMaxTopM; ++x)
-            if (x == lane && x < nsel) { t = st[x]; s = ss[x]; bgn = sb[x]; }
+        const bool h = lane < nsel;
         uint32_t* o = a.out_top + ((uint64_t)rec * a.top_m + lane) * 3;
-        o[0] = t;
-        o[1] = s;
-        o[2] = bgn;
+        o[0] = h ? L.sel_t[lane] : kNone;
+        o[1] = h ? L.sel_s[lane] : 0u;
+        o[2] = h ? L.sel_b[lane] : 0u;
     }
 }
 
@@ -169,9 +176,8 @@ __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>
         o0 = a.offsets[rec]; o1 = a.offsets[rec + 1ull]; o2 = o1;
     }
     o0 = uniform64(o0); o1 = uniform64(o1); o2 = uniform64(o2);
-    uint32_t st[kMaxTopM], ss[kMaxTopM], sb[kMaxTopM];
     if (o1 < o0 || o2 < o1) {           // malformed record: nothing to classify
-        write_result(a, rec, kNone, st, ss, sb, 0);
+        write_result(a, rec, kNone, L, 0);
         return;
     }
     const uint64_t len[2] = {o1 - o0, o2 - o1};
@@ -197,18 +203,18 @@ __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>
             wave_lds_sync();
             const uint32_t nk = (uint32_t)min((uint64_t)a.S, n_starts - j * a.S);
             const uint32_t x0 = (uint32_t)(lo & 15u);
-            nf += sketch_window<KPL>(L.stage, x0, nk, a.k, a.s, L.feats + nf);
+            nf += sketch_window<KPL>(L.stage, x0, nk, a.k, a.s, L.feats + nf, L.scratch);
             wave_lds_sync();
             if (nf + a.s > kMaxFeat) {
                 ws.features += nf;
-                fits = lookup<LCAP>(a, L.feats, nf, L.list, nlist, ws.probes);
+                fits = lookup<LCAP>(a, L.feats, L.home, nf, L.list, nlist, ws.probes);
                 nf = 0;
             }
         }
     }
     if (fits && nf) {
         ws.features += nf;
-        fits = lookup<LCAP>(a, L.feats, nf, L.list, nlist, ws.probes);
+        fits = lookup<LCAP>(a, L.feats, L.home, nf, L.list, nlist, ws.probes);
     }
     if (!fits) {
         if (!big) {
@@ -218,7 +224,7 @@ __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>
             }
         } else {
             if (lane == 0) atomicAdd(&a.counters[kQTooLong], 1u);
-            write_result(a, rec, kNone, st, ss, sb, 0);
+            write_result(a, rec, kNone, L, 0);
         }
         return;
     }
@@ -240,52 +246,62 @@ __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>
     if (lane == 0) L.uidx[U] = (uint16_t)n;
     wave_lds_sync();
 
+    // score of the range of sws windows starting at each distinct location
+    for (uint32_t u = (uint32_t)lane; u < U; u += kWave) {
+        const uint32_t loc = L.list[L.uidx[u]];
+        const uint32_t t = loc >> kWindowBits, w_end = (loc & kWindowMask) + sws;
+        uint32_t score = 0;
+        for (uint32_t v = u; v < U; ++v) {
+            const uint32_t l2 = L.list[L.uidx[v]];
+            if ((l2 >> kWindowBits) != t || (l2 & kWindowMask) >= w_end) break;
+            score += (uint32_t)L.uidx[v + 1] - (uint32_t)L.uidx[v];
+        }
+        L.score[u] = (uint16_t)score;
+    }
+    wave_lds_sync();
+
     // top-m targets by (score desc, target asc); per target the range with the
-    // highest score, ties to the smallest start window
+    // highest score, ties to the smallest start window: m rounds of a wave
+    // maximum of the score, then of ~location among the lanes holding it
     uint32_t nsel = 0;
-#pragma unroll
-    for (uint32_t m = 0; m < kMaxTopM; ++m) {
-        if (m >= a.top_m) break;
-        uint64_t best = 0;
+    for (uint32_t m = 0; m < a.top_m; ++m) {
+        uint32_t bs = 0, bl = 0;     // lane's best (score, ~location)
         for (uint32_t u = (uint32_t)lane; u < U; u += kWave) {
             const uint32_t loc = L.list[L.uidx[u]];
             const uint32_t t = loc >> kWindowBits;
             bool excluded = false;
-#pragma unroll
-            for (uint32_t x = 0; x < kMaxTopM; ++x)
-                if (x < m) excluded |= (st[x] == t);
-            if (excluded) continue;
-            const uint32_t w_end = (loc & kWindowMask) + sws;
-            uint32_t score = 0;
-            for (uint32_t v = u; v < U; ++v) {
-                const uint32_t l2 = L.list[L.uidx[v]];
-                if ((l2 >> kWindowBits) != t || (l2 & kWindowMask) >= w_end) break;
-                score += (uint32_t)L.uidx[v + 1] - (uint32_t)L.uidx[v];
+            for (uint32_t x = 0; x < m; ++x) excluded |= (L.sel_t[x] == t);
+            const uint32_t sc = excluded ? 0u : (uint32_t)L.score[u];
+            if (sc > bs || (sc == bs && sc != 0 && ~loc > bl)) {
+                bs = sc;
+                bl = ~loc;
             }
-            const uint64_t key = ((uint64_t)score << 32) | (uint64_t)(~loc);
-            best = key > best ? key : best;
         }
-        best = uniform64(wave_max_u64(best));
-        if (best == 0) break;
-        const uint32_t loc = ~(uint32_t)best;
-        st[m] = loc >> kWindowBits;
-        ss[m] = (uint32_t)(best >> 32);
-        sb[m] = loc & kWindowMask;
+        const uint32_t best_s = wave_max_u32(bs);
+        if (best_s == 0) break;
+        const uint32_t loc = ~wave_max_u32(bs == best_s ? bl : 0u);
+        if (lane == 0) {
+            L.sel_t[m] = loc >> kWindowBits;
+            L.sel_s[m] = best_s;
+            L.sel_b[m] = loc & kWindowMask;
+        }
+        wave_lds_sync();
         nsel = m + 1;
     }
 
+    // label: the best target's taxon on a clear lead, else the LCA of the
+    // taxa of the listed targets within hit_diff of the best score
     uint32_t label = kNone;
-    if (nsel > 0 && ss[0] >= a.min_hits) {
-        const uint32_t c1 = ss[0], c2 = nsel > 1 ? ss[1] : 0u;
-        label = a.target_taxon[st[0]];
+    if (nsel > 0 && L.sel_s[0] >= a.min_hits) {
+        const uint32_t c1 = L.sel_s[0], c2 = nsel > 1 ? L.sel_s[1] : 0u;
+        label = uniform(a.target_taxon[L.sel_t[0]]);
         if (c1 - c2 <= a.hit_diff) {
-#pragma unroll
-            for (uint32_t x = 1; x < kMaxTopM; ++x)
-                if (x < nsel && (uint64_t)ss[x] + a.hit_diff >= c1)
-                    label = lca(label, a.target_taxon[st[x]], a.parents, a.depth);
+            for (uint32_t x = 1; x < nsel; ++x)
+                if ((uint64_t)L.sel_s[x] + a.hit_diff >= c1)
+                    label = uniform(lca(label, a.target_taxon[L.sel_t[x]], a.parents, a.depth));
         }
     }
-    write_result(a, rec, uniform(label), st, ss, sb, nsel);
+    write_result(a, rec, label, L, nsel);
 }
 
 template <uint32_t LCAP, int WPB, int KPL>
