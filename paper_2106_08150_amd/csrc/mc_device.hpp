@@ -187,21 +187,20 @@ __device__ __forceinline__ Word encode16(uint32_t x0, uint32_t x1, uint32_t x2, 
 }
 
 // Word covering absolute bytes [a, a+16), a 16-byte aligned. Bytes outside
-// [vlo, vhi) are not read and count as invalid.
+// [vlo, vhi) count as invalid. A word that overlaps [vlo, vhi) is read with
+// one 16-byte load: an aligned 16-byte block never crosses a page, so it lies
+// in the same mapped page as the valid byte it contains. A word that does not
+// overlap is not read at all.
 __device__ __forceinline__ Word load_word(uintptr_t a, uintptr_t vlo, uintptr_t vhi) {
-    if (a >= vlo && a + 16 <= vhi) {
-        uint4 v = *reinterpret_cast<const uint4*>(a);
-        return encode16(v.x, v.y, v.z, v.w);
-    }
-    uint32_t x[4] = {0x4E4E4E4Eu, 0x4E4E4E4Eu, 0x4E4E4E4Eu, 0x4E4E4E4Eu};   // "NNNN"
-    for (int i = 0; i < 16; ++i) {
-        uintptr_t p = a + (uintptr_t)i;
-        if (p >= vlo && p < vhi) {
-            uint32_t b = *reinterpret_cast<const uint8_t*>(p);
-            x[i >> 2] = (x[i >> 2] & ~(0xFFu << (8 * (i & 3)))) | (b << (8 * (i & 3)));
-        }
-    }
-    return encode16(x[0], x[1], x[2], x[3]);
+    if (a + 16 <= vlo || a >= vhi) return Word{0u, 0xFFFFu};
+    uint4 v = *reinterpret_cast<const uint4*>(a);
+    Word w = encode16(v.x, v.y, v.z, v.w);
+    // bytes [lo, hi) of the word lie inside [vlo, vhi)
+    const uint32_t lo = vlo > a ? (uint32_t)(vlo - a) : 0u;
+    const uint32_t hi = vhi - a < 16 ? (uint32_t)(vhi - a) : 16u;
+    const uint32_t inside = ((0xFFFFu >> lo) & (0xFFFFu << (16 - hi))) & 0xFFFFu;
+    w.mask |= ~inside & 0xFFFFu;
+    return w;
 }
 
 // Canonical k-mer starting x bases after the first staged word (k <= 16).
@@ -348,6 +347,13 @@ __device__ __forceinline__ uint32_t sketch_window(const Word* W, uint32_t x0, ui
         }
     }
     bool has_top = ballot(top) != 0;
+    if constexpr (KPL >= 2) {
+        if (nk <= (uint32_t)kWave) {   // one key per lane: a 64-wide sort suffices
+            uint32_t v[1] = {key[0]};
+            wave_sort<1>(v);
+            return select_distinct<1>(v, has_top, s, sk, distinct);
+        }
+    }
     wave_sort<KPL>(key);
     return select_distinct<KPL>(key, has_top, s, sk, distinct);
 }
