@@ -196,6 +196,66 @@ int mc_db_dump(mc_db* db, uint32_t feature_lo, uint32_t feature_hi, uint32_t* fe
 int mc_db_sketch(mc_db* db, const char* seqs_dev, const uint64_t* lengths, uint32_t n,
                  uint32_t* out_counts, uint32_t* out_features, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Served form: a persistent request loop over a resident database.
+ *
+ * Interactive use keeps the database in memory between queries (Sec. 4); the
+ * server adds continuous batching on top: a dispatcher thread admits queued
+ * read batches into `slots` in-flight slots (each with its own HIP stream,
+ * device buffers and pinned staging) while the device memory they need stays
+ * within `memory_budget`, so copies and kernels of different batches overlap
+ * on the device; batches complete out of order. Genome additions are queued
+ * in the same order as batches: an addition waits for the batches submitted
+ * before it, runs, and the batches submitted after it see the new targets.
+ * While a server is attached, the database must not be used directly.
+ * ------------------------------------------------------------------------ */
+typedef struct mc_server mc_server;
+
+typedef struct mc_server_opts {
+    uint32_t slots;           /* batches in flight at once, 1..16 (0 = 4)            */
+    uint64_t memory_budget;   /* device bytes for in-flight batch buffers
+                                 (0 = a quarter of the free device memory)           */
+} mc_server_opts;
+
+typedef struct mc_server_stats {
+    uint64_t batches;         /* completed classification batches                   */
+    uint64_t records;         /* records in them                                    */
+    uint64_t bases;           /* read bytes in them                                 */
+    uint64_t additions;       /* completed genome additions                          */
+    double p50_ms, p99_ms;    /* batch latency percentiles: submit -> results in the
+                                 caller's buffers                                    */
+    double mean_ms, max_ms;
+    double span_s;            /* first submit -> last completion                     */
+} mc_server_stats;
+
+/* Start a server on db (which it uses exclusively until destroyed). */
+mc_server* mc_server_create(mc_db* db, const mc_server_opts* opts);
+
+/* Queue a batch. reads/offsets/out_labels/out_top are HOST buffers owned by the
+ * caller, laid out as for mc_classify_ex (offsets need not start at 0); they
+ * must stay valid until mc_server_wait returns for the ticket. out_top may be
+ * NULL. opts is copied. Returns at once with a ticket. A batch whose buffers
+ * exceed the memory budget is rejected with MC_ERR_INVALID_ARG. */
+int mc_server_submit(mc_server* srv, const char* reads, const uint64_t* offsets,
+                     uint32_t n_records, const mc_query_opts* opts, uint32_t* out_labels,
+                     mc_tophit* out_top, uint64_t* ticket);
+
+/* Queue a genome addition (as mc_db_add_targets, host buffers copied before
+ * return) optionally followed by a taxonomy replacement (parents may be NULL). */
+int mc_server_add_targets(mc_server* srv, const char* genomes, const uint64_t* lengths,
+                          const uint32_t* taxon_ids, uint32_t n, const uint32_t* parents,
+                          uint32_t n_nodes, uint64_t* ticket);
+
+/* Block until the job is done; returns its status (MC_OK or an error code) and
+ * its latency in milliseconds (may be NULL). Each ticket can be waited once. */
+int mc_server_wait(mc_server* srv, uint64_t ticket, double* latency_ms);
+
+int mc_server_get_stats(mc_server* srv, mc_server_stats* out);
+
+/* Finish every queued job, stop the dispatcher and free the server's
+ * resources (not the database). NULL is accepted. */
+int mc_server_destroy(mc_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

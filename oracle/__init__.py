@@ -49,6 +49,8 @@ def lib():
         L.orc_db_create.argtypes, L.orc_db_create.restype = [u32, u32, u32, u32], vp
         L.orc_db_destroy.argtypes, L.orc_db_destroy.restype = [vp], None
         L.orc_db_set_filter.argtypes, L.orc_db_set_filter.restype = [vp, vp, u64], None
+        L.orc_db_set_filter_range.argtypes = [vp, u32, u32]
+        L.orc_db_set_filter_range.restype = None
         L.orc_db_add_targets.argtypes = [vp, vp, vp, vp, u32, C.c_int]
         L.orc_db_add_targets.restype = C.c_int
         L.orc_db_add_targets_stop_at_cap.argtypes = [vp, vp, vp, vp, u32]
@@ -152,6 +154,9 @@ class OracleDB:
     def set_filter(self, feats):
         f = np.ascontiguousarray(feats, dtype=np.uint32)
         lib().orc_db_set_filter(self.h, _p(f), f.size)
+
+    def set_filter_range(self, lo: int, hi: int):
+        lib().orc_db_set_filter_range(self.h, lo, hi)
 
     def add_targets(self, text, lengths, taxa, threads: int = 1, stop_at_cap: bool = False):
         t = _bytes(text)

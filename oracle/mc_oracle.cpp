@@ -135,8 +135,9 @@ struct Db {
     std::multimap<uint32_t, uint32_t> index;      // feature -> location
     std::vector<uint32_t> target_taxon;
     std::vector<uint32_t> parents;
-    std::unordered_set<uint32_t> filter;          // empty: keep every feature
+    std::unordered_set<uint32_t> filter;          // features kept when filtering
     bool use_filter = false;
+    uint32_t range_lo = 1, range_hi = 0;          // also kept: lo <= feature <= hi
 };
 
 // Cap (Sec. 4.1): at most `cap` locations per feature. The CPU index appends
@@ -167,7 +168,9 @@ void target_pairs(const Db* db, const unsigned char* seq, uint64_t len, uint32_t
     uint64_t nw = num_windows(len, db->k, db->w);
     for (uint64_t j = 0; j < nw; ++j) {
         for (uint32_t f : window_sketch(seq, len, db->k, db->w, db->s, j)) {
-            if (db->use_filter && !db->filter.count(f)) continue;
+            if (db->use_filter && !db->filter.count(f) &&
+                !(f >= db->range_lo && f <= db->range_hi))
+                continue;
             out->push_back({f, (target << kWindowBits) | (uint32_t)j});
         }
     }
@@ -374,6 +377,14 @@ void orc_db_set_filter(void* h, const uint32_t* feats, uint64_t n) {
     Db* db = static_cast<Db*>(h);
     db->filter.clear();
     db->filter.insert(feats, feats + n);
+    db->use_filter = true;
+}
+
+// Additionally keep every feature in [lo, hi] while filtering.
+void orc_db_set_filter_range(void* h, uint32_t lo, uint32_t hi) {
+    Db* db = static_cast<Db*>(h);
+    db->range_lo = lo;
+    db->range_hi = hi;
     db->use_filter = true;
 }
 

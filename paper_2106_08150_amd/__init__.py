@@ -36,6 +36,8 @@ EXPORTS = [
     "mc_db_add_targets_device", "mc_db_set_taxonomy", "mc_classify", "mc_classify_ex",
     "mc_db_query_status", "mc_db_get_stats", "mc_db_dump", "mc_db_sketch",
     "mc_db_set_profiling", "mc_db_kernel_times",
+    "mc_server_create", "mc_server_submit", "mc_server_add_targets", "mc_server_wait",
+    "mc_server_get_stats", "mc_server_destroy",
 ]
 
 
@@ -58,6 +60,19 @@ class DbStats(C.Structure):
 
     def as_dict(self) -> dict:
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
+class ServerOpts(C.Structure):
+    _fields_ = [("slots", C.c_uint32), ("memory_budget", C.c_uint64)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("batches", C.c_uint64), ("records", C.c_uint64), ("bases", C.c_uint64),
+                ("additions", C.c_uint64), ("p50_ms", C.c_double), ("p99_ms", C.c_double),
+                ("mean_ms", C.c_double), ("max_ms", C.c_double), ("span_s", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {n: getattr(self, n) for n, _ in self._fields_}
 
 
 _lib = None
@@ -98,6 +113,18 @@ def lib():
         L.mc_db_set_profiling.restype, L.mc_db_set_profiling.argtypes = i32, [vp, i32]
         L.mc_db_kernel_times.restype = i32
         L.mc_db_kernel_times.argtypes = [vp, vp, vp]
+        L.mc_server_create.restype = vp
+        L.mc_server_create.argtypes = [vp, C.POINTER(ServerOpts)]
+        L.mc_server_submit.restype = i32
+        L.mc_server_submit.argtypes = [vp, vp, vp, u32, C.POINTER(QueryOpts), vp, vp,
+                                       C.POINTER(u64)]
+        L.mc_server_add_targets.restype = i32
+        L.mc_server_add_targets.argtypes = [vp, vp, vp, vp, u32, vp, u32, C.POINTER(u64)]
+        L.mc_server_wait.restype = i32
+        L.mc_server_wait.argtypes = [vp, u64, C.POINTER(C.c_double)]
+        L.mc_server_get_stats.restype = i32
+        L.mc_server_get_stats.argtypes = [vp, C.POINTER(ServerStats)]
+        L.mc_server_destroy.restype, L.mc_server_destroy.argtypes = i32, [vp]
         _lib = L
     return _lib
 
@@ -227,6 +254,24 @@ def mc_db_kernel_times(db: int) -> dict:
     return {k: {"ms": float(ms[i]), "launches": int(n[i])} for i, k in enumerate(KERNEL_KINDS)}
 
 
+def mc_server_create(db: int, slots: int = 4, memory_budget: int = 0) -> int:
+    o = ServerOpts(slots, memory_budget)
+    h = lib().mc_server_create(db, C.byref(o))
+    if not h:
+        raise MCError(MC_ERR_INVALID_ARG, lib().mc_last_error().decode(errors="replace"))
+    return h
+
+
+def mc_server_destroy(srv: int) -> None:
+    _check(lib().mc_server_destroy(srv))
+
+
+def mc_server_get_stats(srv: int) -> dict:
+    s = ServerStats()
+    _check(lib().mc_server_get_stats(srv, C.byref(s)))
+    return s.as_dict()
+
+
 # ------------------------------------------------------------ wrapper ----
 class Database:
     """Owning wrapper of an ``mc_db`` handle with torch-friendly helpers."""
@@ -281,3 +326,69 @@ class Database:
         opts = QueryOpts(top_m, min_hits, hit_diff, insert_size, int(paired))
         mc_classify_ex(self.h, reads, offsets, n_records, opts, labels, top, stream)
         return (labels[:n_records], top[:n_records] if top is not None else None)
+
+
+class Server:
+    """Persistent request loop over a Database (host buffers in and out).
+
+    ``submit`` queues a batch and returns a ticket at once; ``wait`` returns the
+    batch's labels (and top hits) with its latency. ``add_targets`` queues an
+    on-demand genome addition, ordered with the batches.
+    """
+
+    def __init__(self, db: Database, slots: int = 4, memory_budget: int = 0):
+        self.db = db
+        self.h = mc_server_create(db.h, slots, memory_budget)
+        self._jobs = {}
+
+    def submit(self, reads_text, offsets, paired: bool = False, top_m: int = 4,
+               min_hits: int = 4, hit_diff: int = 0, insert_size: int = 0,
+               with_top: bool = False) -> int:
+        text = np.ascontiguousarray(reads_text, dtype=np.uint8)
+        off = np.ascontiguousarray(offsets, dtype=np.uint64)
+        n = (off.size - 1) // (2 if paired else 1)
+        labels = np.empty(max(n, 1), np.uint32)
+        top = np.empty((max(n, 1), top_m, 3), np.uint32) if with_top else None
+        opts = QueryOpts(top_m, min_hits, hit_diff, insert_size, int(paired))
+        t = C.c_uint64(0)
+        _check(lib().mc_server_submit(self.h, _np_ptr(text), _np_ptr(off), n, C.byref(opts),
+                                      _np_ptr(labels), _np_ptr(top) if top is not None else None,
+                                      C.byref(t)))
+        self._jobs[t.value] = (text, off, labels, top, n)   # keep buffers alive
+        return t.value
+
+    def add_targets(self, genomes, lengths, taxon_ids, parents=None) -> int:
+        g = np.ascontiguousarray(genomes, dtype=np.uint8)
+        L = np.ascontiguousarray(lengths, dtype=np.uint64)
+        x = np.ascontiguousarray(taxon_ids, dtype=np.uint32)
+        p = np.ascontiguousarray(parents, dtype=np.uint32) if parents is not None else None
+        t = C.c_uint64(0)
+        _check(lib().mc_server_add_targets(self.h, _np_ptr(g), _np_ptr(L), _np_ptr(x), L.size,
+                                           _np_ptr(p) if p is not None else None,
+                                           0 if p is None else p.size, C.byref(t)))
+        self._jobs[t.value] = None
+        return t.value
+
+    def wait(self, ticket: int):
+        ms = C.c_double(0)
+        rc = lib().mc_server_wait(self.h, ticket, C.byref(ms))
+        job = self._jobs.pop(ticket, None)
+        _check(rc)
+        if job is None:
+            return None, None, ms.value
+        _, _, labels, top, n = job
+        return labels[:n], (top[:n] if top is not None else None), ms.value
+
+    def stats(self) -> dict:
+        return mc_server_get_stats(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            mc_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

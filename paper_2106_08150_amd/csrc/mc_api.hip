@@ -393,6 +393,7 @@ Workspace* workspace(mc_db* db, hipStream_t st, uint64_t n_records, int* rc) {
         }
     }
     if (n_records > w.queue_cap) {
+        (void)hipStreamSynchronize(st);   // the old queue may still be in use on st
         if (w.queue) (void)hipFree(w.queue);
         w.queue = nullptr;
         w.queue_cap = 0;
@@ -404,6 +405,11 @@ Workspace* workspace(mc_db* db, hipStream_t st, uint64_t n_records, int* rc) {
 }
 
 }  // namespace
+
+namespace mc {
+int db_device(const struct ::mc_db* db) { return db->device; }
+int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
+}  // namespace mc
 
 extern "C" {
 

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+struct mc_db;
+
 namespace mc {
 
 constexpr int kSlots = 16;   // 64-bit slots per table bucket (one 128-byte line)
@@ -116,5 +118,11 @@ hipError_t launch_count_valid(const unsigned long long* table, uint64_t nb,
 // over the records the fast path queued.
 hipError_t launch_classify_fast(const QueryArgs& a, hipStream_t st);
 hipError_t launch_classify_large(const QueryArgs& a, hipStream_t st);
+
+// Device of a database handle (for threads that must select it).
+int db_device(const struct ::mc_db* db);
+
+// Set the calling thread's mc_last_error text; returns code.
+int set_error(int code, const char* msg);
 
 }  // namespace mc

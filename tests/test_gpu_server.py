@@ -1,0 +1,120 @@
+"""Served form: results identical alone and in the mix; ordered additions.
+
+Batches of uneven size and layout are submitted to a server with several
+in-flight slots so that their copies and kernels overlap; every batch's labels
+and top hits must equal those of the same batch classified alone (tolerance
+0), and the oracle's. A genome addition queued between batches must be seen by
+every later batch and by no earlier one.
+"""
+import numpy as np
+import pytest
+
+import oracle as orc
+import paper_2106_08150_amd as mc
+from paper_2106_08150_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    if not T.cuda.is_available():
+        pytest.skip("no GPU")
+    return T
+
+
+def plain(torch, db, reads, paired, **opts):
+    r = torch.from_numpy(np.ascontiguousarray(reads.text)).cuda()
+    o = torch.from_numpy(reads.offsets.view(np.int64).copy()).cuda()
+    lab, top = db.classify(r, o, reads.n_records, paired=paired, with_top=True, **opts)
+    torch.cuda.synchronize()
+    return lab.cpu().numpy().view(np.uint32), top.cpu().numpy().view(np.uint32)
+
+
+def sub_batch(reads, a, b):
+    off = reads.offsets[a:b + 1]
+    return synth.Reads(reads.text[int(off[0]):int(off[-1])].copy(), off - off[0], False)
+
+
+def test_results_identical_alone_and_in_the_mix(torch):
+    g = synth.tiny_genomes()
+    db = mc.Database()
+    db.add_targets(torch.from_numpy(g.text.copy()).cuda(), g.lengths, g.taxa)
+    db.set_taxonomy(g.parents)
+    reads = synth.tiny_reads(g, n=40_000, seed=77)
+    cuts = [0, 1, 101, 5101, 25101, 25401, 25418, 33418, 40000]
+    batches = [(sub_batch(reads, a, b), False) for a, b in zip(cuts[:-1], cuts[1:])]
+    batches.append((synth.mixed_records(g, 3000, seed=5), True))
+    alone = [plain(torch, db, r, p, insert_size=400 if p else 0) for r, p in batches]
+
+    srv = mc.Server(db, slots=3)
+    tickets = [srv.submit(r.text, r.offsets, paired=p, with_top=True,
+                          insert_size=400 if p else 0) for r, p in batches]
+    for (lab0, top0), t in zip(alone, tickets):
+        lab, top, ms = srv.wait(t)
+        assert ms >= 0
+        assert np.array_equal(lab, lab0) and np.array_equal(top, top0)
+    st = srv.stats()
+    assert st["batches"] == len(batches)
+    assert st["records"] == sum(r.n_records for r, _ in batches)
+    assert 0 < st["p50_ms"] <= st["p99_ms"] <= st["max_ms"]
+    srv.close()
+
+    # the oracle agrees on a mixed sample
+    odb = orc.OracleDB()
+    odb.add_targets(g.text, g.lengths, g.taxa)
+    odb.set_taxonomy(g.parents)
+    r, _ = batches[3]
+    ol, ot = odb.classify(r.text, r.offsets, first=0, count=2000)
+    assert np.array_equal(alone[3][0][:2000], ol) and np.array_equal(alone[3][1][:2000], ot)
+
+
+def test_additions_are_ordered_with_batches(torch):
+    g = synth.tiny_genomes(length=40_000)
+    # first 5 genomes at start, genomes 5..7 added while serving
+    off = g.offsets
+    first = synth.Genomes(g.text[:int(off[5])].copy(), g.lengths[:5], g.taxa[:5], g.parents)
+    db = mc.Database()
+    db.add_targets(first.text, first.lengths, first.taxa)
+    db.set_taxonomy(first.parents)
+    reads = synth.sample_reads(g, 6000, 100, seed=3)
+
+    before = mc.Database()
+    before.add_targets(first.text, first.lengths, first.taxa)
+    before.set_taxonomy(g.parents)
+    after = mc.Database()
+    after.add_targets(g.text, g.lengths, g.taxa)
+    after.set_taxonomy(g.parents)
+    want_before = plain(torch, before, reads, False)
+    want_after = plain(torch, after, reads, False)
+    assert not np.array_equal(want_before[0], want_after[0])
+
+    srv = mc.Server(db, slots=4)
+    t1 = srv.submit(reads.text, reads.offsets, with_top=True)
+    t2 = srv.submit(reads.text, reads.offsets, with_top=True)
+    ta = srv.add_targets(g.text[int(off[5]):], g.lengths[5:], g.taxa[5:], parents=g.parents)
+    t3 = srv.submit(reads.text, reads.offsets, with_top=True)
+    for t in (t1, t2):
+        lab, top, _ = srv.wait(t)
+        assert np.array_equal(lab, want_before[0]) and np.array_equal(top, want_before[1])
+    assert srv.wait(ta)[0] is None
+    lab, top, _ = srv.wait(t3)
+    assert np.array_equal(lab, want_after[0]) and np.array_equal(top, want_after[1])
+    assert srv.stats()["additions"] == 1
+    srv.close()
+
+
+def test_budget_rejects_oversized_batch(torch):
+    g = synth.tiny_genomes(length=5000)
+    db = mc.Database()
+    db.add_targets(g.text, g.lengths, g.taxa)
+    db.set_taxonomy(g.parents)
+    srv = mc.Server(db, slots=1, memory_budget=4096)
+    reads = synth.sample_reads(g, 1000, 100, seed=1)
+    with pytest.raises(mc.MCError):
+        srv.submit(reads.text, reads.offsets)
+    small = sub_batch(reads, 0, 5)
+    lab, _, _ = srv.wait(srv.submit(small.text, small.offsets))
+    assert lab.size == 5
+    srv.close()
