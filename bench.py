@@ -46,6 +46,11 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=20_000,
                     help="reads classified by the CPU oracle (0 = skip the CPU baseline)")
     ap.add_argument("--cpu-threads", type=int, default=0, help="0 = min(16, host cores)")
+    ap.add_argument("--served-batches", type=int, default=100,
+                    help="batches of the served-form trace (0 = skip the served leg)")
+    ap.add_argument("--served-loads", type=str, default="0.7,1.0,1.5,2.0",
+                    help="offered loads, as fractions of the plain launch's back-to-back "
+                         "throughput, at which served and plain forms are compared")
     return ap.parse_args()
 
 
@@ -76,6 +81,142 @@ def cpu_baseline(g, reads, n_sample, threads, gpu_labels):
         "build_sketch_bp_per_s": float(g.lengths.sum()) / (t2 - t1),
         "build_sketch_cores": threads,
         "sample_label_mismatches_vs_gpu": mism,
+    }
+
+
+def served_leg(args, g, gtext, torch, mc, synth):
+    """Served request loop vs plain per-batch launches on one arrival trace.
+
+    Trace: Poisson arrivals, batch sizes log-uniform in [1e3, 1e6] reads of
+    U{100..250} bp (1% substitutions, 5% foreign); every 50 batches an
+    on-demand addition of 20 genomes (2 new clusters, about 80 Mbp) with the
+    extended taxonomy. Both forms start from the same freshly built database;
+    latency = arrival -> labels in host memory.
+    """
+    import threading
+    nb = args.served_batches
+    unit_t, sizes = synth.arrival_trace(nb, seed=401, lo=1e3, hi=1e6, rate_hz=1.0)
+    reads = synth.sample_reads_varlen(g, int(sizes.sum()), 100, 250, seed=402, foreign=0.05)
+    cuts = np.concatenate([[0], np.cumsum(sizes)])
+    # batch inputs in pinned host memory, as a serving front end would receive them
+    batches = []
+    for i in range(nb):
+        off = reads.offsets[cuts[i]:cuts[i + 1] + 1]
+        txt = torch.from_numpy(reads.text[int(off[0]):int(off[-1])]).pin_memory()
+        batches.append((txt, (off - off[0]).astype(np.uint64)))
+    staging = max(int(t.numel()) + 16 * (o.size + 1) for t, o in batches)
+    adds, base = {}, g
+    for i in range(50, nb, 50):
+        add, parents = synth.addition_genomes(base, 2, 10, 8e7, seed=4000 + i)
+        adds[i] = (add, parents)
+        base = synth.Genomes(base.text[:0], base.lengths[:0], base.taxa[:0], parents)
+    log(f"served trace: {nb} batches, {int(sizes.sum())} reads, {len(adds)} additions")
+
+    # table headroom for the planned additions (no growth while serving)
+    add_pairs = sum(int(((a.lengths.astype(np.int64) - K) // (WINDOW - K + 1) + 1).sum())
+                    * SKETCH for a, _ in adds.values())
+
+    def fresh_db():
+        db = mc.Database(K, WINDOW, SKETCH, CAP)
+        wins = int(((g.lengths.astype(np.int64) - K) // (WINDOW - K + 1) + 1).sum())
+        db.reserve(wins * SKETCH + add_pairs)
+        db.add_targets(gtext, g.lengths, g.taxa)
+        db.set_taxonomy(g.parents)
+        return db
+
+    dev = gtext.device
+
+    def plain_run(arrivals):
+        db = fresh_db()
+        labels, lat = [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i, (txt, off) in enumerate(batches):
+            if arrivals is not None:
+                wait = t0 + arrivals[i] - time.perf_counter()
+                if wait > 0:
+                    time.sleep(wait)
+            if i in adds:
+                add, parents = adds[i]
+                db.add_targets(add.text, add.lengths, add.taxa)
+                db.set_taxonomy(parents)
+            r = txt.to(dev, non_blocking=True)
+            o = torch.from_numpy(off.view(np.int64)).to(dev)
+            lab, _ = db.classify(r, o, off.size - 1)
+            labels.append(lab.cpu().numpy().view(np.uint32).copy())
+            lat.append((time.perf_counter() - t0 - (arrivals[i] if arrivals is not None else 0))
+                       * 1e3)
+        span = time.perf_counter() - t0
+        db.close()
+        return labels, np.array(lat), span
+
+    # throughput of back-to-back plain launches sets the arrival rates
+    _, _, span0 = plain_run(None)
+    plain_tput = reads.n_records / span0
+
+    def served_run(arrivals):
+        db = fresh_db()
+        srv = mc.Server(db, slots=4, staging_bytes=staging)
+        tickets = [None] * nb
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+
+        def feeder():
+            for i, (txt, off) in enumerate(batches):
+                wait = t0 + arrivals[i] - time.perf_counter()
+                if wait > 0:
+                    time.sleep(wait)
+                if i in adds:
+                    add, parents = adds[i]
+                    srv.add_targets(add.text, add.lengths, add.taxa, parents=parents)
+                tickets[i] = srv.submit(txt, off)
+
+        th = threading.Thread(target=feeder)
+        th.start()
+        labels, lat = [], []
+        for i in range(nb):
+            while tickets[i] is None:
+                time.sleep(0.0002)
+            lab, _, ms = srv.wait(tickets[i])
+            labels.append(lab.copy())
+            lat.append(ms)
+        th.join()
+        span = time.perf_counter() - t0
+        srv.close()
+        db.close()
+        return labels, np.array(lat), span
+
+    def pct(v, p):
+        v = np.sort(np.asarray(v))
+        return float(v[min(v.size - 1, max(0, int(np.ceil(p / 100 * v.size)) - 1))])
+
+    def summary(lat, span):
+        return {"p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "mean_ms": float(np.mean(lat)),
+                "reads_per_s": reads.n_records / span}
+
+    results, same_all = [], True
+    for load in [float(x) for x in args.served_loads.split(",") if x]:
+        rate = load * plain_tput / float(sizes.mean())
+        arrivals = unit_t / rate
+        p_lab, p_lat, p_span = plain_run(arrivals)
+        s_lab, s_lat, s_span = served_run(arrivals)
+        same = all(np.array_equal(a, b) for a, b in zip(s_lab, p_lab))
+        same_all &= same
+        results.append({"offered_load": load, "batches_per_s": rate,
+                         "served": summary(s_lat, s_span), "plain": summary(p_lat, p_span),
+                         "labels_identical": bool(same)})
+        log(f"load {load:.2f}: served p50 {pct(s_lat, 50):.2f} p99 {pct(s_lat, 99):.2f} ms, "
+            f"plain p50 {pct(p_lat, 50):.2f} p99 {pct(p_lat, 99):.2f} ms, identical {same}")
+    return {
+        "trace": (f"{nb} batches, Poisson arrivals, sizes log-uniform 1e3..1e6 reads of "
+                  f"100-250 bp (1% substitutions, 5% foreign), {len(adds)} addition(s) of 20 "
+                  "genomes; the database is the at-scale set with headroom reserved; inputs "
+                  "in pinned host memory; latency = arrival -> labels in host memory"),
+        "reads": int(reads.n_records),
+        "slots": 4,
+        "plain_back_to_back_reads_per_s": plain_tput,
+        "loads": results,
+        "labels_identical": bool(same_all),
     }
 
 
@@ -208,6 +349,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": None,
     }
+    if args.served_batches > 0:
+        out["served"] = served_leg(args, g, gtext, torch, mc, synth)
     if args.cpu_sample > 0:
         threads = args.cpu_threads or min(16, os.cpu_count() or 1)
         out["cpu_baseline"] = cpu_baseline(g, reads, min(args.cpu_sample, n), threads,

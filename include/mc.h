@@ -201,10 +201,10 @@ int mc_db_sketch(mc_db* db, const char* seqs_dev, const uint64_t* lengths, uint3
  *
  * Interactive use keeps the database in memory between queries (Sec. 4); the
  * server adds continuous batching on top: a dispatcher thread admits queued
- * read batches into `slots` in-flight slots (each with its own HIP stream,
- * device buffers and pinned staging) while the device memory they need stays
- * within `memory_budget`, so copies and kernels of different batches overlap
- * on the device; batches complete out of order. Genome additions are queued
+ * read batches, in order, into `slots` in-flight slots while the device memory
+ * they need stays within `memory_budget`. Each slot has a worker thread, a HIP
+ * stream, device buffers and pinned staging, so host staging, copies and
+ * kernels of different batches overlap; batches complete out of order. Genome additions are queued
  * in the same order as batches: an addition waits for the batches submitted
  * before it, runs, and the batches submitted after it see the new targets.
  * While a server is attached, the database must not be used directly.
@@ -215,6 +215,8 @@ typedef struct mc_server_opts {
     uint32_t slots;           /* batches in flight at once, 1..16 (0 = 4)            */
     uint64_t memory_budget;   /* device bytes for in-flight batch buffers
                                  (0 = a quarter of the free device memory)           */
+    uint64_t staging_bytes;   /* initial device + pinned buffer per slot, grown by
+                                 doubling when a batch needs more (0 = 64 MiB)       */
 } mc_server_opts;
 
 typedef struct mc_server_stats {
@@ -235,10 +237,14 @@ mc_server* mc_server_create(mc_db* db, const mc_server_opts* opts);
  * caller, laid out as for mc_classify_ex (offsets need not start at 0); they
  * must stay valid until mc_server_wait returns for the ticket. out_top may be
  * NULL. opts is copied. Returns at once with a ticket. A batch whose buffers
- * exceed the memory budget is rejected with MC_ERR_INVALID_ARG. */
+ * exceed the memory budget is rejected with MC_ERR_INVALID_ARG.
+ * flags: MC_SUBMIT_PINNED if `reads` lies in pinned host memory (allocated
+ * with hipHostMalloc or as pinned by the caller's framework): the bases are
+ * then copied to the device directly, without staging. */
+#define MC_SUBMIT_PINNED 1u
 int mc_server_submit(mc_server* srv, const char* reads, const uint64_t* offsets,
                      uint32_t n_records, const mc_query_opts* opts, uint32_t* out_labels,
-                     mc_tophit* out_top, uint64_t* ticket);
+                     mc_tophit* out_top, uint32_t flags, uint64_t* ticket);
 
 /* Queue a genome addition (as mc_db_add_targets, host buffers copied before
  * return) optionally followed by a taxonomy replacement (parents may be NULL). */

@@ -30,6 +30,7 @@ MC_ERR_LIST = -7
 MC_UNCLASSIFIED = 0xFFFFFFFF
 MC_MAX_TARGETS = 16383
 MC_MAX_WINDOWS = 1 << 18
+MC_SUBMIT_PINNED = 1
 
 EXPORTS = [
     "mc_last_error", "mc_db_create", "mc_db_destroy", "mc_db_reserve", "mc_db_add_targets",
@@ -63,7 +64,8 @@ class DbStats(C.Structure):
 
 
 class ServerOpts(C.Structure):
-    _fields_ = [("slots", C.c_uint32), ("memory_budget", C.c_uint64)]
+    _fields_ = [("slots", C.c_uint32), ("memory_budget", C.c_uint64),
+                ("staging_bytes", C.c_uint64)]
 
 
 class ServerStats(C.Structure):
@@ -116,7 +118,7 @@ def lib():
         L.mc_server_create.restype = vp
         L.mc_server_create.argtypes = [vp, C.POINTER(ServerOpts)]
         L.mc_server_submit.restype = i32
-        L.mc_server_submit.argtypes = [vp, vp, vp, u32, C.POINTER(QueryOpts), vp, vp,
+        L.mc_server_submit.argtypes = [vp, vp, vp, u32, C.POINTER(QueryOpts), vp, vp, u32,
                                        C.POINTER(u64)]
         L.mc_server_add_targets.restype = i32
         L.mc_server_add_targets.argtypes = [vp, vp, vp, vp, u32, vp, u32, C.POINTER(u64)]
@@ -254,8 +256,9 @@ def mc_db_kernel_times(db: int) -> dict:
     return {k: {"ms": float(ms[i]), "launches": int(n[i])} for i, k in enumerate(KERNEL_KINDS)}
 
 
-def mc_server_create(db: int, slots: int = 4, memory_budget: int = 0) -> int:
-    o = ServerOpts(slots, memory_budget)
+def mc_server_create(db: int, slots: int = 4, memory_budget: int = 0,
+                     staging_bytes: int = 0) -> int:
+    o = ServerOpts(slots, memory_budget, staging_bytes)
     h = lib().mc_server_create(db, C.byref(o))
     if not h:
         raise MCError(MC_ERR_INVALID_ARG, lib().mc_last_error().decode(errors="replace"))
@@ -336,24 +339,32 @@ class Server:
     on-demand genome addition, ordered with the batches.
     """
 
-    def __init__(self, db: Database, slots: int = 4, memory_budget: int = 0):
+    def __init__(self, db: Database, slots: int = 4, memory_budget: int = 0,
+                 staging_bytes: int = 0):
         self.db = db
-        self.h = mc_server_create(db.h, slots, memory_budget)
+        self.h = mc_server_create(db.h, slots, memory_budget, staging_bytes)
         self._jobs = {}
 
     def submit(self, reads_text, offsets, paired: bool = False, top_m: int = 4,
                min_hits: int = 4, hit_diff: int = 0, insert_size: int = 0,
                with_top: bool = False) -> int:
-        text = np.ascontiguousarray(reads_text, dtype=np.uint8)
+        """reads_text: numpy uint8 array, or a pinned CPU torch uint8 tensor (copied to
+        the device directly)."""
+        pinned = hasattr(reads_text, "is_pinned") and reads_text.is_pinned()
+        if pinned:
+            text, text_ptr = reads_text, C.c_void_p(reads_text.data_ptr())
+        else:
+            text = np.ascontiguousarray(reads_text, dtype=np.uint8)
+            text_ptr = _np_ptr(text)
         off = np.ascontiguousarray(offsets, dtype=np.uint64)
         n = (off.size - 1) // (2 if paired else 1)
         labels = np.empty(max(n, 1), np.uint32)
         top = np.empty((max(n, 1), top_m, 3), np.uint32) if with_top else None
         opts = QueryOpts(top_m, min_hits, hit_diff, insert_size, int(paired))
         t = C.c_uint64(0)
-        _check(lib().mc_server_submit(self.h, _np_ptr(text), _np_ptr(off), n, C.byref(opts),
+        _check(lib().mc_server_submit(self.h, text_ptr, _np_ptr(off), n, C.byref(opts),
                                       _np_ptr(labels), _np_ptr(top) if top is not None else None,
-                                      C.byref(t)))
+                                      MC_SUBMIT_PINNED if pinned else 0, C.byref(t)))
         self._jobs[t.value] = (text, off, labels, top, n)   # keep buffers alive
         return t.value
 

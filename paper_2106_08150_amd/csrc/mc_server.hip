@@ -32,6 +32,7 @@ struct Job {
     uint32_t* out_labels = nullptr;
     mc_tophit* out_top = nullptr;
     uint64_t bytes = 0;          // read bytes
+    bool pinned = false;         // reads are in pinned host memory
     uint64_t dev_need = 0;       // device bytes while in flight
     // genome addition (copied)
     std::vector<char> genomes;
@@ -46,18 +47,19 @@ struct Done {
     double ms = 0.0;
 };
 
-// One in-flight slot: stream, device buffers, pinned staging, completion event.
+// One in-flight slot: a worker thread with its own stream, device buffers and
+// pinned staging. The dispatcher hands it one batch at a time.
 struct Slot {
     hipStream_t stream = nullptr;
-    hipEvent_t done = nullptr;
     char* d_buf = nullptr;
     uint64_t d_cap = 0;
     char* h_buf = nullptr;       // pinned
     uint64_t h_cap = 0;
-    bool busy = false;
+    bool busy = false;           // owned by a batch (guarded by the server mutex)
+    bool has_job = false;
     Job job;
-    // layout of the current job inside the buffers
-    uint64_t off_reads = 0, off_offsets = 0, off_labels = 0, off_top = 0;
+    std::thread thr;
+    std::condition_variable cv;
 };
 
 uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
@@ -69,14 +71,17 @@ struct mc_server {
     int device = 0;
     uint32_t n_slots = 4;
     uint64_t budget = 0;
+    uint64_t staging = 64ull << 20;
     std::vector<Slot> slots;
     std::deque<Job> queue;
     std::map<uint64_t, Done> done;
-    std::mutex mu;
-    std::condition_variable cv_queue, cv_done;
+    std::mutex mu;               // queue, slots' ownership, results, stats
+    std::mutex launch_mu;        // calls into the database
+    std::condition_variable cv_queue, cv_done, cv_slot;
     bool stopping = false;
     uint64_t next_ticket = 1;
     uint64_t inflight_bytes = 0;
+    uint32_t busy_slots = 0;
     std::thread thr;
     // stats
     std::vector<double> lat_ms;
@@ -84,10 +89,10 @@ struct mc_server {
     bool have_first = false;
     Clock::time_point t_first, t_last;
 
-    void finish(const Job& j, int status) {
+    // Record a finished job (caller holds mu).
+    void finish_locked(const Job& j, int status) {
         const double ms =
             std::chrono::duration<double, std::milli>(Clock::now() - j.t_submit).count();
-        std::lock_guard<std::mutex> lk(mu);
         done[j.ticket] = Done{status, ms};
         t_last = Clock::now();
         if (j.is_add) {
@@ -101,151 +106,135 @@ struct mc_server {
         cv_done.notify_all();
     }
 
-    // Copy results of a completed slot to the caller and release the slot.
-    void retire(Slot& s, int status) {
-        if (status == MC_OK) {
-            std::memcpy(s.job.out_labels, s.h_buf + s.off_labels, (size_t)s.job.n * 4);
-            if (s.job.out_top)
-                std::memcpy(s.job.out_top, s.h_buf + s.off_top,
-                            (size_t)s.job.n * s.job.opts.top_m * sizeof(mc_tophit));
-        }
-        inflight_bytes -= s.job.dev_need;
-        s.busy = false;
-        finish(s.job, status);
-    }
-
-    // Retire every slot whose work is complete; with `block`, wait for at least one.
-    void poll(bool block) {
-        for (;;) {
-            bool any_busy = false, any_done = false;
-            for (auto& s : slots) {
-                if (!s.busy) continue;
-                any_busy = true;
-                hipError_t e = hipEventQuery(s.done);
-                if (e == hipSuccess) {
-                    retire(s, MC_OK);
-                    any_done = true;
-                } else if (e != hipErrorNotReady) {
-                    retire(s, MC_ERR_HIP);
-                    any_done = true;
-                }
-            }
-            if (!block || any_done || !any_busy) return;
-            std::this_thread::sleep_for(std::chrono::microseconds(20));
-        }
-    }
-
-    bool any_busy() const {
-        for (auto& s : slots)
-            if (s.busy) return true;
-        return false;
-    }
-
-    int grow(Slot& s, uint64_t dev, uint64_t host) {
-        if (dev > s.d_cap) {
-            (void)hipStreamSynchronize(s.stream);
+    static int grow(Slot& s, uint64_t need) {
+        if (need > s.d_cap) {
+            uint64_t cap = std::max(need, s.d_cap * 2);
             (void)hipFree(s.d_buf);
             s.d_buf = nullptr;
             s.d_cap = 0;
-            if (hipMalloc((void**)&s.d_buf, dev) != hipSuccess) return MC_ERR_OOM;
-            s.d_cap = dev;
+            if (hipMalloc((void**)&s.d_buf, cap) != hipSuccess) return MC_ERR_OOM;
+            s.d_cap = cap;
         }
-        if (host > s.h_cap) {
-            (void)hipStreamSynchronize(s.stream);
+        if (need > s.h_cap) {
+            uint64_t cap = std::max(need, s.h_cap * 2);
             (void)hipHostFree(s.h_buf);
             s.h_buf = nullptr;
             s.h_cap = 0;
-            if (hipHostMalloc((void**)&s.h_buf, host, hipHostMallocDefault) != hipSuccess)
+            if (hipHostMalloc((void**)&s.h_buf, cap, hipHostMallocDefault) != hipSuccess)
                 return MC_ERR_OOM;
-            s.h_cap = host;
+            s.h_cap = cap;
         }
         return MC_OK;
     }
 
-    // Stage a batch into a free slot and queue copy-in, classify, copy-out.
-    void launch(Slot& s, Job&& j) {
+    // Stage, copy in, classify, copy out and hand back one batch (worker thread).
+    int process(Slot& s, Job& j) {
         const uint64_t seg = (j.opts.paired ? 2ull : 1ull) * j.n;   // offsets - 1
         const uint64_t base = j.offsets[0];
         const uint64_t rb = j.offsets[seg] - base;
-        s.off_reads = 0;
-        s.off_offsets = align256(rb);
-        s.off_labels = s.off_offsets + align256((seg + 1) * 8);
-        s.off_top = s.off_labels + align256((uint64_t)j.n * 4);
-        const uint64_t total =
-            s.off_top + (j.out_top ? align256((uint64_t)j.n * j.opts.top_m * sizeof(mc_tophit)) : 0);
-        int rc = grow(s, total, total);
-        s.job = std::move(j);
-        s.busy = true;
-        inflight_bytes += s.job.dev_need;
-        if (rc != MC_OK) { retire(s, rc); return; }
-        std::memcpy(s.h_buf + s.off_reads, s.job.reads + base, rb);
-        uint64_t* ho = reinterpret_cast<uint64_t*>(s.h_buf + s.off_offsets);
-        for (uint64_t i = 0; i <= seg; ++i) ho[i] = s.job.offsets[i] - base;
-        hipError_t e = hipMemcpyAsync(s.d_buf, s.h_buf, s.off_labels, hipMemcpyHostToDevice,
-                                      s.stream);
-        if (e == hipSuccess) {
-            rc = mc_classify_ex(db, s.d_buf + s.off_reads,
-                                reinterpret_cast<const uint64_t*>(s.d_buf + s.off_offsets),
-                                s.job.n, &s.job.opts,
-                                reinterpret_cast<uint32_t*>(s.d_buf + s.off_labels),
-                                s.job.out_top ? reinterpret_cast<mc_tophit*>(s.d_buf + s.off_top)
-                                              : nullptr,
-                                s.stream);
-            if (rc != MC_OK) { (void)hipStreamSynchronize(s.stream); retire(s, rc); return; }
-            e = hipMemcpyAsync(s.h_buf + s.off_labels, s.d_buf + s.off_labels,
-                               total - s.off_labels, hipMemcpyDeviceToHost, s.stream);
+        const uint64_t off_offsets = align256(rb);
+        const uint64_t off_labels = off_offsets + align256((seg + 1) * 8);
+        const uint64_t off_top = off_labels + align256((uint64_t)j.n * 4);
+        const uint64_t top_bytes = (uint64_t)j.n * j.opts.top_m * sizeof(mc_tophit);
+        const uint64_t total = off_top + (j.out_top ? align256(top_bytes) : 0);
+        int rc = grow(s, total);
+        if (rc != MC_OK) return rc;
+        uint64_t* ho = reinterpret_cast<uint64_t*>(s.h_buf + off_offsets);
+        for (uint64_t i = 0; i <= seg; ++i) ho[i] = j.offsets[i] - base;
+        hipError_t e;
+        if (j.pinned) {   // direct DMA from the caller's pinned buffer
+            e = hipMemcpyAsync(s.d_buf, j.reads + base, rb, hipMemcpyHostToDevice, s.stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(s.d_buf + off_offsets, s.h_buf + off_offsets,
+                                   off_labels - off_offsets, hipMemcpyHostToDevice, s.stream);
+        } else {
+            std::memcpy(s.h_buf, j.reads + base, rb);
+            e = hipMemcpyAsync(s.d_buf, s.h_buf, off_labels, hipMemcpyHostToDevice, s.stream);
         }
-        if (e == hipSuccess) e = hipEventRecord(s.done, s.stream);
-        if (e != hipSuccess) { (void)hipStreamSynchronize(s.stream); retire(s, MC_ERR_HIP); }
+        if (e != hipSuccess) return MC_ERR_HIP;
+        {
+            std::lock_guard<std::mutex> lk(launch_mu);
+            rc = mc_classify_ex(db, s.d_buf, reinterpret_cast<const uint64_t*>(s.d_buf + off_offsets),
+                                j.n, &j.opts, reinterpret_cast<uint32_t*>(s.d_buf + off_labels),
+                                j.out_top ? reinterpret_cast<mc_tophit*>(s.d_buf + off_top) : nullptr,
+                                s.stream);
+        }
+        if (rc != MC_OK) return rc;
+        if (hipMemcpyAsync(s.h_buf + off_labels, s.d_buf + off_labels, total - off_labels,
+                           hipMemcpyDeviceToHost, s.stream) != hipSuccess ||
+            hipStreamSynchronize(s.stream) != hipSuccess)
+            return MC_ERR_HIP;
+        std::memcpy(j.out_labels, s.h_buf + off_labels, (size_t)j.n * 4);
+        if (j.out_top) std::memcpy(j.out_top, s.h_buf + off_top, top_bytes);
+        return MC_OK;
+    }
+
+    void worker(Slot& s) {
+        (void)hipSetDevice(device);
+        for (;;) {
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                s.cv.wait(lk, [&] { return s.has_job || stopping; });
+                if (!s.has_job) return;
+            }
+            int rc = process(s, s.job);
+            std::lock_guard<std::mutex> lk(mu);
+            finish_locked(s.job, rc);
+            inflight_bytes -= s.job.dev_need;
+            s.job = Job();
+            s.has_job = false;
+            s.busy = false;
+            busy_slots -= 1;
+            cv_slot.notify_all();
+        }
     }
 
     void run_add(Job& j) {
-        int rc = mc_db_add_targets(db, j.genomes.data(), j.lengths.data(), j.taxa.data(),
+        int rc;
+        {
+            std::lock_guard<std::mutex> lk(launch_mu);
+            rc = mc_db_add_targets(db, j.genomes.data(), j.lengths.data(), j.taxa.data(),
                                    (uint32_t)j.lengths.size());
-        if (rc == MC_OK && !j.parents.empty())
-            rc = mc_db_set_taxonomy(db, j.parents.data(), (uint32_t)j.parents.size());
-        finish(j, rc);
+            if (rc == MC_OK && !j.parents.empty())
+                rc = mc_db_set_taxonomy(db, j.parents.data(), (uint32_t)j.parents.size());
+        }
+        std::lock_guard<std::mutex> lk(mu);
+        finish_locked(j, rc);
     }
 
+    // Dispatcher: FIFO order; a batch waits for a free slot and room in the
+    // memory budget; an addition waits until every earlier batch is done.
     void loop() {
         (void)hipSetDevice(device);
+        std::unique_lock<std::mutex> lk(mu);
         for (;;) {
-            Job j;
-            {
-                std::unique_lock<std::mutex> lk(mu);
-                while (queue.empty() && !stopping) {
-                    if (any_busy()) {
-                        lk.unlock();
-                        poll(false);
-                        std::this_thread::sleep_for(std::chrono::microseconds(20));
-                        lk.lock();
-                    } else {
-                        cv_queue.wait(lk);
-                    }
-                }
-                if (queue.empty() && stopping) break;
-                j = std::move(queue.front());
-                queue.pop_front();
-            }
+            cv_queue.wait(lk, [&] { return !queue.empty() || stopping; });
+            if (queue.empty()) break;
+            Job j = std::move(queue.front());
+            queue.pop_front();
             if (j.is_add) {
-                while (any_busy()) poll(true);   // batches before the addition finish first
+                cv_slot.wait(lk, [&] { return busy_slots == 0; });
+                lk.unlock();
                 run_add(j);
+                lk.lock();
                 continue;
             }
-            // admission: a free slot and room in the memory budget
-            for (;;) {
-                poll(false);
-                Slot* free_slot = nullptr;
+            Slot* free_slot = nullptr;
+            cv_slot.wait(lk, [&] {
+                free_slot = nullptr;
                 for (auto& s : slots)
                     if (!s.busy) { free_slot = &s; break; }
-                if (free_slot && (inflight_bytes + j.dev_need <= budget || !any_busy())) {
-                    launch(*free_slot, std::move(j));
-                    break;
-                }
-                poll(true);
-            }
+                return free_slot &&
+                       (inflight_bytes + j.dev_need <= budget || busy_slots == 0);
+            });
+            free_slot->busy = true;
+            free_slot->has_job = true;
+            inflight_bytes += j.dev_need;
+            busy_slots += 1;
+            free_slot->job = std::move(j);
+            free_slot->cv.notify_one();
         }
-        while (any_busy()) poll(true);
+        cv_slot.wait(lk, [&] { return busy_slots == 0; });
     }
 };
 
@@ -271,25 +260,27 @@ mc_server* mc_server_create(mc_db* db, const mc_server_opts* opts) {
     size_t free_b = 0, total_b = 0;
     (void)hipMemGetInfo(&free_b, &total_b);
     s->budget = opts && opts->memory_budget ? opts->memory_budget : free_b / 4;
-    s->slots.resize(s->n_slots);
+    s->slots = std::vector<Slot>(s->n_slots);
+    if (opts && opts->staging_bytes) s->staging = opts->staging_bytes;
     bool ok = true;
     for (auto& sl : s->slots) {
         ok = ok && hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess;
-        ok = ok && hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess;
+        ok = ok && mc_server::grow(sl, s->staging) == MC_OK;
     }
     (void)hipSetDevice(prev);
     if (!ok) {
         mc_server_destroy(s);
-        mc::set_error(MC_ERR_HIP, "stream/event creation failed");
+        mc::set_error(MC_ERR_OOM, "stream or staging allocation failed");
         return nullptr;
     }
+    for (auto& sl : s->slots) sl.thr = std::thread([s, &sl] { s->worker(sl); });
     s->thr = std::thread([s] { s->loop(); });
     return s;
 }
 
 int mc_server_submit(mc_server* srv, const char* reads, const uint64_t* offsets,
                      uint32_t n_records, const mc_query_opts* opts, uint32_t* out_labels,
-                     mc_tophit* out_top, uint64_t* ticket) {
+                     mc_tophit* out_top, uint32_t flags, uint64_t* ticket) {
     if (!srv || !opts || !offsets || !ticket || (n_records && (!reads || !out_labels)))
         return mc::set_error(MC_ERR_INVALID_ARG, "NULL argument");
     if (opts->top_m < 1 || opts->top_m > mc::kMaxTopM || opts->paired > 1)
@@ -301,6 +292,7 @@ int mc_server_submit(mc_server* srv, const char* reads, const uint64_t* offsets,
     j.opts = *opts;
     j.out_labels = out_labels;
     j.out_top = out_top;
+    j.pinned = (flags & MC_SUBMIT_PINNED) != 0;
     const uint64_t seg = (opts->paired ? 2ull : 1ull) * n_records;
     for (uint64_t i = 0; i < seg; ++i)
         if (offsets[i + 1] < offsets[i])
@@ -395,6 +387,12 @@ int mc_server_destroy(mc_server* srv) {
         srv->cv_queue.notify_all();
     }
     if (srv->thr.joinable()) srv->thr.join();
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        for (auto& s : srv->slots) s.cv.notify_all();
+    }
+    for (auto& s : srv->slots)
+        if (s.thr.joinable()) s.thr.join();
     int prev = 0;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(srv->device);
@@ -402,7 +400,6 @@ int mc_server_destroy(mc_server* srv) {
         if (s.stream) (void)hipStreamSynchronize(s.stream);
         (void)hipFree(s.d_buf);
         (void)hipHostFree(s.h_buf);
-        if (s.done) (void)hipEventDestroy(s.done);
         if (s.stream) (void)hipStreamDestroy(s.stream);
     }
     (void)hipSetDevice(prev);

@@ -70,6 +70,13 @@ def substitute_inplace(rng: np.random.Generator, out: np.ndarray, d: float) -> N
     out[pos] = _OTHER[out[pos], pick]
 
 
+def _windows(text: np.ndarray, width: int) -> np.ndarray:
+    """Read-only view of every ``width``-long substring of ``text`` (one per row)."""
+    t = np.ascontiguousarray(text, dtype=np.uint8)
+    return np.lib.stride_tricks.as_strided(t, shape=(max(t.size - width + 1, 0), width),
+                                           strides=(1, 1), writeable=False)
+
+
 def reverse_complement_text(text: np.ndarray) -> np.ndarray:
     return _COMP[np.asarray(text, dtype=np.uint8)[::-1]]
 
@@ -153,8 +160,7 @@ def sample_reads(genomes: Genomes, n: int, length: int, seed: int,
         is_foreign = rng.random(m) < foreign
         start = (rng.random(m) * (lens[gi] - length + 1)).astype(np.int64)
         rev = rng.random(m) < 0.5
-        rows = np.lib.stride_tricks.sliding_window_view(genomes.text, length)
-        block = rows[off_g[gi].astype(np.int64) + start]
+        block = _windows(genomes.text, length)[off_g[gi].astype(np.int64) + start]
         block[rev] = _COMP[block[rev][:, ::-1]]
         nf = int(is_foreign.sum())
         if nf:
@@ -315,3 +321,65 @@ def arrival_trace(n_batches: int, seed: int, lo: float = 1e3, hi: float = 1e6,
     gaps = rng.exponential(1.0 / rate_hz, size=n_batches)
     sizes = np.exp(rng.uniform(np.log(lo), np.log(hi), size=n_batches)).astype(np.int64)
     return np.cumsum(gaps), sizes
+
+
+def sample_reads_varlen(genomes: Genomes, n: int, lo: int, hi: int, seed: int,
+                        error: float = 0.01, foreign: float = 0.0,
+                        chunk: int = 100_000) -> Reads:
+    """``n`` single-end reads with lengths uniform in {lo..hi} (module rules)."""
+    rng = rng_for(seed)
+    off_g = genomes.offsets.astype(np.int64)
+    lens = genomes.lengths.astype(np.int64)
+    ok = np.nonzero(lens >= 3 * hi)[0]
+    rows = _windows(genomes.text, hi)
+    pieces, all_len = [], []
+    cols = np.arange(hi, dtype=np.int32)
+    for c0 in range(0, n, chunk):
+        m = min(chunk, n - c0)
+        L = rng.integers(lo, hi + 1, size=m)
+        gi = ok[rng.integers(0, ok.size, size=m)]
+        is_foreign = rng.random(m) < foreign
+        # fragment [start, start + L) with start uniform in [hi, len - 2 hi]
+        start = hi + (rng.random(m) * (lens[gi] - 3 * hi + 1)).astype(np.int64)
+        rev = rng.random(m) < 0.5
+        first = off_g[gi] + start
+        # reverse strand: the hi-window ending at the fragment end, reversed
+        block = rows[np.where(rev, first + L - hi, first)]
+        block[rev] = _COMP[block[rev][:, ::-1]]
+        nf = int(is_foreign.sum())
+        if nf:
+            block[is_foreign] = random_text(rng, nf * hi).reshape(nf, hi)
+        keep = cols[None, :] < L[:, None]
+        flat = substitute(rng, block[keep], error)
+        pieces.append(flat)
+        all_len.append(L)
+    lengths = np.concatenate(all_len) if all_len else np.zeros(0, np.int64)
+    offsets = np.zeros(n + 1, dtype=np.uint64)
+    np.cumsum(lengths, out=offsets[1:])
+    text = np.concatenate(pieces) if pieces else np.zeros(0, np.uint8)
+    return Reads(text, offsets, False)
+
+
+def addition_genomes(base: Genomes, n_clusters: int, per_cluster: int, total_bp: float,
+                     seed: int, first_taxon_node: int | None = None) -> tuple[Genomes, np.ndarray]:
+    """New genomes for an on-demand addition and the extended parent array.
+
+    The new clusters hang under existing level-1 nodes of ``base``'s taxonomy
+    (children of its root); their cluster, group and leaf nodes get new ids
+    after the existing ones. Returns the new genomes (taxa in the extended
+    numbering) and the extended parents.
+    """
+    add = clustered_genomes(n_clusters, per_cluster, total_bp, seed, level1=1)
+    root = int(np.nonzero(base.parents == np.arange(base.parents.size))[0][0])
+    level1 = np.nonzero((base.parents == root) & (np.arange(base.parents.size) != root))[0]
+    start = base.parents.size if first_taxon_node is None else first_taxon_node
+    n_new = add.parents.size - 2            # drop the small set's root and level-1 node
+    mapping = np.zeros(add.parents.size, dtype=np.int64)
+    mapping[0] = root
+    rng = rng_for(seed + 1)
+    mapping[1] = int(level1[rng.integers(0, level1.size)]) if level1.size else root
+    mapping[2:] = np.arange(start, start + n_new)
+    parents = np.concatenate([base.parents, np.zeros(n_new, dtype=np.uint32)])
+    parents[start:start + n_new] = mapping[add.parents[2:]].astype(np.uint32)
+    taxa = mapping[add.taxa].astype(np.uint32)
+    return Genomes(add.text, add.lengths, taxa, parents), parents
