@@ -177,6 +177,40 @@ int mc_db_query_status(mc_db* db, void* stream, uint64_t* n_too_long);
 int mc_db_set_profiling(mc_db* db, int enable);
 int mc_db_kernel_times(mc_db* db, double* ms, uint64_t* launches);
 
+/* Launch shape of the fast classification path (tuning only; results never
+ * depend on it): candidate locations held in LDS per record (256, 512 or
+ * 1024; longer lists take the large-list pass), waves per workgroup (2, 4 or
+ * 8) and the largest grid (records beyond it are taken grid-stride).
+ * Default {512, 4, 16384}. */
+typedef struct mc_launch_config {
+    uint32_t list_capacity;
+    uint32_t waves_per_block;
+    uint32_t max_blocks;
+} mc_launch_config;
+int mc_db_set_launch_config(mc_db* db, const mc_launch_config* cfg);
+int mc_db_get_launch_config(mc_db* db, mc_launch_config* cfg);
+
+/* Autotuner: classifies the given batch (device buffers, as mc_classify_ex)
+ * with every supported launch shape, checks that all give identical labels
+ * (MC_ERR_STATE otherwise), keeps the fastest in the handle for later calls
+ * and reports it (best and best_ms may be NULL). Synchronous on `stream`. */
+int mc_db_autotune(mc_db* db, const char* reads, const uint64_t* offsets, uint32_t n_records,
+                   const mc_query_opts* opts, uint32_t* out_labels, void* stream,
+                   mc_launch_config* best, double* best_ms);
+
+/* A classification call (fixed device buffers and sizes, as mc_classify_ex)
+ * captured once into a HIP graph and replayed with one launch; the buffers'
+ * contents may change between replays. The graph owns its own workspace, so
+ * replays must not overlap each other. If the database changed since the
+ * capture (targets added, taxonomy or launch shape replaced), the next launch
+ * captures it again. */
+typedef struct mc_graph mc_graph;
+mc_graph* mc_classify_graph_create(mc_db* db, const char* reads, const uint64_t* offsets,
+                                   uint32_t n_records, const mc_query_opts* opts,
+                                   uint32_t* out_labels, mc_tophit* out_top, void* stream);
+int mc_classify_graph_launch(mc_graph* g, void* stream);
+int mc_classify_graph_destroy(mc_graph* g);
+
 /* Counters of the handle (synchronous). */
 int mc_db_get_stats(mc_db* db, mc_db_stats* out);
 

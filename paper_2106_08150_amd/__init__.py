@@ -39,6 +39,8 @@ EXPORTS = [
     "mc_db_set_profiling", "mc_db_kernel_times",
     "mc_server_create", "mc_server_submit", "mc_server_add_targets", "mc_server_wait",
     "mc_server_get_stats", "mc_server_destroy",
+    "mc_db_set_launch_config", "mc_db_get_launch_config", "mc_db_autotune",
+    "mc_classify_graph_create", "mc_classify_graph_launch", "mc_classify_graph_destroy",
 ]
 
 
@@ -61,6 +63,14 @@ class DbStats(C.Structure):
 
     def as_dict(self) -> dict:
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
+class LaunchConfig(C.Structure):
+    _fields_ = [("list_capacity", C.c_uint32), ("waves_per_block", C.c_uint32),
+                ("max_blocks", C.c_uint32)]
+
+    def as_tuple(self):
+        return (self.list_capacity, self.waves_per_block, self.max_blocks)
 
 
 class ServerOpts(C.Structure):
@@ -127,6 +137,18 @@ def lib():
         L.mc_server_get_stats.restype = i32
         L.mc_server_get_stats.argtypes = [vp, C.POINTER(ServerStats)]
         L.mc_server_destroy.restype, L.mc_server_destroy.argtypes = i32, [vp]
+        L.mc_db_set_launch_config.restype = i32
+        L.mc_db_set_launch_config.argtypes = [vp, C.POINTER(LaunchConfig)]
+        L.mc_db_get_launch_config.restype = i32
+        L.mc_db_get_launch_config.argtypes = [vp, C.POINTER(LaunchConfig)]
+        L.mc_db_autotune.restype = i32
+        L.mc_db_autotune.argtypes = [vp, vp, vp, u32, C.POINTER(QueryOpts), vp, vp,
+                                     C.POINTER(LaunchConfig), C.POINTER(C.c_double)]
+        L.mc_classify_graph_create.restype = vp
+        L.mc_classify_graph_create.argtypes = [vp, vp, vp, u32, C.POINTER(QueryOpts), vp, vp, vp]
+        L.mc_classify_graph_launch.restype, L.mc_classify_graph_launch.argtypes = i32, [vp, vp]
+        L.mc_classify_graph_destroy.restype = i32
+        L.mc_classify_graph_destroy.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -254,6 +276,55 @@ def mc_db_kernel_times(db: int) -> dict:
     n = np.zeros(len(KERNEL_KINDS), np.uint64)
     _check(lib().mc_db_kernel_times(db, _np_ptr(ms), _np_ptr(n)))
     return {k: {"ms": float(ms[i]), "launches": int(n[i])} for i, k in enumerate(KERNEL_KINDS)}
+
+
+def mc_db_set_launch_config(db: int, list_capacity: int, waves_per_block: int,
+                            max_blocks: int) -> None:
+    c = LaunchConfig(list_capacity, waves_per_block, max_blocks)
+    _check(lib().mc_db_set_launch_config(db, C.byref(c)))
+
+
+def mc_db_get_launch_config(db: int) -> tuple:
+    c = LaunchConfig()
+    _check(lib().mc_db_get_launch_config(db, C.byref(c)))
+    return c.as_tuple()
+
+
+def mc_db_autotune(db: int, reads, offsets, n_records: int, opts: QueryOpts, out_labels,
+                   stream=None) -> tuple:
+    c, ms = LaunchConfig(), C.c_double(0)
+    _check(lib().mc_db_autotune(db, _dev_ptr(reads), _dev_ptr(offsets), n_records,
+                                C.byref(opts), _dev_ptr(out_labels), _stream(stream),
+                                C.byref(c), C.byref(ms)))
+    return c.as_tuple(), ms.value
+
+
+class ClassifyGraph:
+    """One classification call captured into a HIP graph (fixed device buffers)."""
+
+    def __init__(self, db: int, reads, offsets, n_records: int, opts: QueryOpts, out_labels,
+                 out_top=None, stream=None):
+        self._keep = (reads, offsets, out_labels, out_top)
+        top = _dev_ptr(out_top) if out_top is not None else None
+        self.h = lib().mc_classify_graph_create(db, _dev_ptr(reads), _dev_ptr(offsets),
+                                                n_records, C.byref(opts), _dev_ptr(out_labels),
+                                                top, _stream(stream))
+        if not self.h:
+            raise MCError(MC_ERR_HIP, lib().mc_last_error().decode(errors="replace"))
+
+    def launch(self, stream=None):
+        _check(lib().mc_classify_graph_launch(self.h, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().mc_classify_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def mc_server_create(db: int, slots: int = 4, memory_budget: int = 0,

@@ -107,6 +107,10 @@ struct mc_db {
     uint32_t* hist = nullptr;
     unsigned long long* part_start = nullptr;
     unsigned long long* cursor = nullptr;
+    // fast-path launch shape (set by mc_db_set_launch_config / mc_db_autotune)
+    ClassifyConfig cfg;
+    // bumped whenever device arrays a captured graph refers to may have moved
+    uint64_t version = 1;
     // profiling: one timer per profiled kernel kind (MC_K_*)
     bool profiling = false;
     Timed timers[MC_K_COUNT];
@@ -164,6 +168,7 @@ int ensure_capacity(mc_db* db, uint64_t extra, hipStream_t st) {
     db->bcount = cnt;
     db->table = t;
     db->nb = nb;
+    db->version += 1;
     return MC_OK;
 }
 
@@ -177,6 +182,7 @@ int upload_taxa(mc_db* db, hipStream_t st) {
         if (db->d_taxa) HIP_TRY(hipFree(db->d_taxa));
         db->d_taxa = p;
         db->d_taxa_cap = c;
+        db->version += 1;
     }
     if (n) HIP_TRY(hipMemcpyAsync(db->d_taxa, db->taxa.data(), n * 4, hipMemcpyHostToDevice, st));
     return MC_OK;
@@ -406,6 +412,143 @@ Workspace* workspace(mc_db* db, hipStream_t st, uint64_t n_records, int* rc) {
 
 }  // namespace
 
+namespace {
+
+int check_classify(mc_db* db, const char* reads, const uint64_t* offsets, uint32_t n_records,
+                   const mc_query_opts* opts, const uint32_t* out_labels) {
+    if (int rc = check_db(db)) return rc;
+    if (!opts) return fail(MC_ERR_INVALID_ARG, "opts is NULL");
+    if (opts->top_m < 1 || opts->top_m > kMaxTopM)
+        return fail(MC_ERR_INVALID_ARG, "top_m %u not in [1, %u]", opts->top_m, kMaxTopM);
+    if (opts->paired > 1) return fail(MC_ERR_INVALID_ARG, "paired must be 0 or 1");
+    if (n_records == 0) return MC_OK;
+    if (!reads || !offsets || !out_labels) return fail(MC_ERR_INVALID_ARG, "NULL pointer");
+    if (!db->taxa.empty()) {
+        if (db->parents.empty()) return fail(MC_ERR_STATE, "taxonomy not set");
+        for (size_t t = 0; t < db->taxa.size(); ++t)
+            if (db->taxa[t] >= db->parents.size())
+                return fail(MC_ERR_STATE, "target %zu has taxon %u outside the taxonomy", t,
+                            db->taxa[t]);
+    }
+    return MC_OK;
+}
+
+// Queue the classification launches on st with workspace w (no allocation, no
+// synchronisation: usable under stream capture).
+int classify_launch(mc_db* db, const char* reads, const uint64_t* offsets, uint32_t n_records,
+                    const mc_query_opts& opts, uint32_t* out_labels, mc_tophit* out_top,
+                    Workspace& w, const ClassifyConfig& cfg, hipStream_t st, bool profile) {
+    HIP_TRY(launch_fill_u32(w.counters + kQOverflow, 1, 0u, st));
+    QueryArgs a{};
+    a.table = db->table;
+    a.nb = db->nb;
+    a.reads = reinterpret_cast<const uint8_t*>(reads);
+    a.offsets = offsets;
+    a.n_records = n_records;
+    a.paired = opts.paired;
+    a.k = db->k; a.w = db->w; a.S = db->S; a.s = db->s;
+    a.top_m = opts.top_m;
+    a.min_hits = opts.min_hits;
+    a.hit_diff = opts.hit_diff;
+    a.insert_size = opts.insert_size;
+    a.target_taxon = db->d_taxa;
+    a.parents = db->d_parents;
+    a.depth = db->d_depth;
+    a.out_labels = out_labels;
+    a.out_top = reinterpret_cast<uint32_t*>(out_top);
+    a.queue = w.queue;
+    a.counters = w.counters;
+    a.qstats = w.qstats;
+    if (profile) {
+        HIP_TRY(timed_launch(db, db->timers[MC_K_CLASSIFY], st,
+                             [&] { return launch_classify_fast(a, cfg, st); }));
+    } else {
+        HIP_TRY(launch_classify_fast(a, cfg, st));
+    }
+    HIP_TRY(launch_classify_large(a, st));
+    return MC_OK;
+}
+
+int alloc_workspace(Workspace& w, uint64_t n_records, hipStream_t st) {
+    int rc = dev_alloc(&w.counters, kNumQueryCounters);
+    if (!rc) rc = dev_alloc(&w.qstats, kNumQueryStats);
+    if (!rc) rc = dev_alloc(&w.queue, std::max<uint64_t>(n_records, 1));
+    if (rc) return rc;
+    w.queue_cap = std::max<uint64_t>(n_records, 1);
+    HIP_TRY(launch_fill_u32(w.counters, kNumQueryCounters, 0u, st));
+    HIP_TRY(launch_fill_u64(w.qstats, kNumQueryStats, 0ull, st));
+    return MC_OK;
+}
+
+void free_workspace(Workspace& w) {
+    (void)hipFree(w.queue);
+    (void)hipFree(w.counters);
+    (void)hipFree(w.qstats);
+    w = Workspace();
+}
+
+}  // namespace
+
+// A classification call captured into a HIP graph with its own workspace.
+// It is captured again (transparently) when the database's device arrays
+// have changed since the capture.
+struct mc_graph {
+    mc_db* db = nullptr;
+    const char* reads = nullptr;
+    const uint64_t* offsets = nullptr;
+    uint32_t n = 0;
+    mc_query_opts opts{};
+    uint32_t* out_labels = nullptr;
+    mc_tophit* out_top = nullptr;
+    Workspace ws;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t version = 0;
+};
+
+namespace {
+
+void release_graph(mc_graph* g) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    g->exec = nullptr;
+    g->graph = nullptr;
+}
+
+int capture_graph(mc_graph* g, hipStream_t st) {
+    mc_db* db = g->db;
+    release_graph(g);
+    // capture needs a stream other than the legacy default stream
+    hipStream_t cs = st;
+    bool own = false;
+    if (cs == nullptr) {
+        HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        own = true;
+    }
+    int rc = MC_OK;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        rc = classify_launch(db, g->reads, g->offsets, g->n, g->opts, g->out_labels, g->out_top,
+                             g->ws, db->cfg, cs, false);
+        hipGraph_t graph = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cs, &graph);
+        if (e2 != hipSuccess && rc == MC_OK) rc = fail(MC_ERR_HIP, "graph capture failed");
+        g->graph = graph;
+        if (rc == MC_OK) {
+            e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) rc = fail(MC_ERR_HIP, "graph instantiation failed");
+        }
+    } else {
+        rc = fail(MC_ERR_HIP, "stream capture could not begin");
+    }
+    if (own) (void)hipStreamDestroy(cs);
+    if (rc == MC_OK) g->version = db->version;
+    else release_graph(g);
+    return rc;
+}
+
+}  // namespace
+
 namespace mc {
 int db_device(const struct ::mc_db* db) { return db->device; }
 int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
@@ -561,6 +704,7 @@ int mc_db_set_taxonomy(mc_db* db, const uint32_t* parents, uint32_t n_nodes) {
     (void)hipFree(db->d_depth);
     db->d_parents = dp;
     db->d_depth = dd;
+    db->version += 1;
     db->parents.assign(parents, parents + n_nodes);
     return MC_OK;
 }
@@ -568,49 +712,15 @@ int mc_db_set_taxonomy(mc_db* db, const uint32_t* parents, uint32_t n_nodes) {
 int mc_classify_ex(mc_db* db, const char* reads, const uint64_t* offsets, uint32_t n_records,
                    const mc_query_opts* opts, uint32_t* out_labels, mc_tophit* out_top,
                    void* stream) {
-    if (int rc = check_db(db)) return rc;
-    if (!opts) return fail(MC_ERR_INVALID_ARG, "opts is NULL");
-    if (opts->top_m < 1 || opts->top_m > kMaxTopM)
-        return fail(MC_ERR_INVALID_ARG, "top_m %u not in [1, %u]", opts->top_m, kMaxTopM);
-    if (opts->paired > 1) return fail(MC_ERR_INVALID_ARG, "paired must be 0 or 1");
+    if (int rc = check_classify(db, reads, offsets, n_records, opts, out_labels)) return rc;
     if (n_records == 0) return MC_OK;
-    if (!reads || !offsets || !out_labels) return fail(MC_ERR_INVALID_ARG, "NULL pointer");
-    if (!db->taxa.empty()) {
-        if (db->parents.empty()) return fail(MC_ERR_STATE, "taxonomy not set");
-        for (size_t t = 0; t < db->taxa.size(); ++t)
-            if (db->taxa[t] >= db->parents.size())
-                return fail(MC_ERR_STATE, "target %zu has taxon %u outside the taxonomy", t,
-                            db->taxa[t]);
-    }
     DeviceGuard dg(db->device);
     hipStream_t st = static_cast<hipStream_t>(stream);
     int rc = 0;
     Workspace* w = workspace(db, st, n_records, &rc);
     if (!w) return rc;
-    HIP_TRY(launch_fill_u32(w->counters + kQOverflow, 1, 0u, st));
-    QueryArgs a{};
-    a.table = db->table;
-    a.nb = db->nb;
-    a.reads = reinterpret_cast<const uint8_t*>(reads);
-    a.offsets = offsets;
-    a.n_records = n_records;
-    a.paired = opts->paired;
-    a.k = db->k; a.w = db->w; a.S = db->S; a.s = db->s;
-    a.top_m = opts->top_m;
-    a.min_hits = opts->min_hits;
-    a.hit_diff = opts->hit_diff;
-    a.insert_size = opts->insert_size;
-    a.target_taxon = db->d_taxa;
-    a.parents = db->d_parents;
-    a.depth = db->d_depth;
-    a.out_labels = out_labels;
-    a.out_top = reinterpret_cast<uint32_t*>(out_top);
-    a.queue = w->queue;
-    a.counters = w->counters;
-    a.qstats = w->qstats;
-    HIP_TRY(timed_launch(db, db->timers[MC_K_CLASSIFY], st, [&] { return launch_classify_fast(a, st); }));
-    HIP_TRY(launch_classify_large(a, st));
-    return MC_OK;
+    return classify_launch(db, reads, offsets, n_records, *opts, out_labels, out_top, *w,
+                           db->cfg, st, db->profiling);
 }
 
 int mc_classify(mc_db* db, const char* reads, const uint64_t* offsets, uint32_t n_reads,
@@ -767,6 +877,130 @@ int mc_db_sketch(mc_db* db, const char* seqs_dev, const uint64_t* lengths, uint3
     (void)hipFree(d_td);
     (void)hipFree(d_tf);
     if (e != hipSuccess) return fail(MC_ERR_HIP, "sketch: %s", hipGetErrorString(e));
+    return MC_OK;
+}
+
+int mc_db_set_launch_config(mc_db* db, const mc_launch_config* cfg) {
+    if (int rc = check_db(db)) return rc;
+    if (!cfg) return fail(MC_ERR_INVALID_ARG, "cfg is NULL");
+    ClassifyConfig c{cfg->list_capacity, cfg->waves_per_block, cfg->max_blocks};
+    if (!classify_config_valid(c)) return fail(MC_ERR_INVALID_ARG, "unsupported launch config");
+    db->cfg = c;
+    db->version += 1;
+    return MC_OK;
+}
+
+int mc_db_get_launch_config(mc_db* db, mc_launch_config* cfg) {
+    if (int rc = check_db(db)) return rc;
+    if (!cfg) return fail(MC_ERR_INVALID_ARG, "cfg is NULL");
+    cfg->list_capacity = db->cfg.list_cap;
+    cfg->waves_per_block = db->cfg.waves_per_block;
+    cfg->max_blocks = db->cfg.max_blocks;
+    return MC_OK;
+}
+
+int mc_db_autotune(mc_db* db, const char* reads, const uint64_t* offsets, uint32_t n_records,
+                   const mc_query_opts* opts, uint32_t* out_labels, void* stream,
+                   mc_launch_config* best, double* best_ms) {
+    if (int rc = check_classify(db, reads, offsets, n_records, opts, out_labels)) return rc;
+    if (n_records == 0) return fail(MC_ERR_INVALID_ARG, "autotune needs records");
+    DeviceGuard dg(db->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int rc = 0;
+    Workspace* w = workspace(db, st, n_records, &rc);
+    if (!w) return rc;
+    std::vector<uint32_t> ref(n_records), cur(n_records);
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const uint32_t caps[] = {256, 512, 1024};
+    const uint32_t wpbs[] = {2, 4, 8};
+    const uint32_t grids[] = {2048, 8192, 32768, 1u << 30};
+    ClassifyConfig win = db->cfg;
+    double win_ms = 1e30;
+    bool first = true;
+    for (uint32_t lc : caps)
+        for (uint32_t wp : wpbs)
+            for (uint32_t gb : grids) {
+                ClassifyConfig c{lc, wp, gb};
+                float ms = 0.f;
+                for (int rep = 0; rep < 2; ++rep) {   // the first run warms caches
+                    HIP_TRY(hipEventRecord(e0, st));
+                    rc = classify_launch(db, reads, offsets, n_records, *opts, out_labels,
+                                         nullptr, *w, c, st, false);
+                    if (rc) return rc;
+                    HIP_TRY(hipEventRecord(e1, st));
+                    HIP_TRY(hipEventSynchronize(e1));
+                    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                }
+                HIP_TRY(hipMemcpy(first ? ref.data() : cur.data(), out_labels,
+                                  (size_t)n_records * 4, hipMemcpyDeviceToHost));
+                if (!first && cur != ref)
+                    return fail(MC_ERR_STATE, "launch shapes disagree (%u, %u, %u)", lc, wp, gb);
+                first = false;
+                if (ms < win_ms) {
+                    win_ms = ms;
+                    win = c;
+                }
+            }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    db->cfg = win;
+    db->version += 1;
+    if (best) *best = mc_launch_config{win.list_cap, win.waves_per_block, win.max_blocks};
+    if (best_ms) *best_ms = win_ms;
+    return MC_OK;
+}
+
+mc_graph* mc_classify_graph_create(mc_db* db, const char* reads, const uint64_t* offsets,
+                                   uint32_t n_records, const mc_query_opts* opts,
+                                   uint32_t* out_labels, mc_tophit* out_top, void* stream) {
+    if (check_classify(db, reads, offsets, n_records, opts, out_labels)) return nullptr;
+    if (n_records == 0) {
+        fail(MC_ERR_INVALID_ARG, "a graph needs records");
+        return nullptr;
+    }
+    DeviceGuard dg(db->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    mc_graph* g = new mc_graph();
+    g->db = db;
+    g->reads = reads;
+    g->offsets = offsets;
+    g->n = n_records;
+    g->opts = *opts;
+    g->out_labels = out_labels;
+    g->out_top = out_top;
+    if (alloc_workspace(g->ws, n_records, st) != MC_OK || hipStreamSynchronize(st) != hipSuccess ||
+        capture_graph(g, st) != MC_OK) {
+        std::string e = g_err;
+        mc_classify_graph_destroy(g);
+        g_err = e;
+        return nullptr;
+    }
+    return g;
+}
+
+int mc_classify_graph_launch(mc_graph* g, void* stream) {
+    if (!g) return fail(MC_ERR_INVALID_ARG, "graph is NULL");
+    DeviceGuard dg(g->db->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (g->version != g->db->version) {
+        if (int rc = check_classify(g->db, g->reads, g->offsets, g->n, &g->opts, g->out_labels))
+            return rc;
+        HIP_TRY(hipDeviceSynchronize());   // no replay of the old graph may still run
+        if (int rc = capture_graph(g, st)) return rc;
+    }
+    HIP_TRY(hipGraphLaunch(g->exec, st));
+    return MC_OK;
+}
+
+int mc_classify_graph_destroy(mc_graph* g) {
+    if (!g) return MC_OK;
+    DeviceGuard dg(g->db->device);
+    (void)hipDeviceSynchronize();
+    release_graph(g);
+    free_workspace(g->ws);
+    delete g;
     return MC_OK;
 }
 

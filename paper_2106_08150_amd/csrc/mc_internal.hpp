@@ -114,9 +114,19 @@ hipError_t launch_dump(const unsigned long long* table, uint64_t nb, uint32_t lo
                        hipStream_t st);
 hipError_t launch_count_valid(const unsigned long long* table, uint64_t nb,
                               unsigned long long* count, hipStream_t st);
+// Launch shape of the fast classification path: candidate locations held in
+// LDS per record (256, 512 or 1024), waves per workgroup (2, 4 or 8) and the
+// largest grid (records beyond it are taken grid-stride).
+struct ClassifyConfig {
+    uint32_t list_cap = kListSmall;
+    uint32_t waves_per_block = 4;
+    uint32_t max_blocks = 16384;
+};
+bool classify_config_valid(const ClassifyConfig& c);
+
 // Fast path (one wave per record, small LDS list) and the large-list pass
 // over the records the fast path queued.
-hipError_t launch_classify_fast(const QueryArgs& a, hipStream_t st);
+hipError_t launch_classify_fast(const QueryArgs& a, const ClassifyConfig& c, hipStream_t st);
 hipError_t launch_classify_large(const QueryArgs& a, hipStream_t st);
 
 // Device of a database handle (for threads that must select it).

@@ -322,37 +322,61 @@ __global__ __launch_bounds__(WPB * 64) void k_classify(QueryArgs a, int big) {
     }
 }
 
-template <bool kLarge, int KPL>
-hipError_t launch_kpl(const QueryArgs& a, hipStream_t st) {
-    if (kLarge) {
-        hipLaunchKernelGGL((k_classify<kListLarge, 1, KPL>), dim3(512), dim3(64), 0, st, a, 1);
-    } else {
-        constexpr int WPB = 4;
-        uint64_t blocks = ((uint64_t)a.n_records + WPB - 1) / WPB;
-        if (blocks > 16384) blocks = 16384;
-        if (blocks < 1) blocks = 1;
-        hipLaunchKernelGGL((k_classify<kListSmall, WPB, KPL>), dim3((unsigned)blocks),
-                           dim3(WPB * 64), 0, st, a, 0);
-    }
+template <uint32_t LCAP, int WPB, int KPL>
+hipError_t launch_fast_t(const QueryArgs& a, uint32_t max_blocks, hipStream_t st) {
+    uint64_t blocks = ((uint64_t)a.n_records + WPB - 1) / WPB;
+    if (blocks > max_blocks) blocks = max_blocks;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL((k_classify<LCAP, WPB, KPL>), dim3((unsigned)blocks), dim3(WPB * 64), 0,
+                       st, a, 0);
     return hipGetLastError();
 }
 
-template <bool kLarge>
-hipError_t launch_any(const QueryArgs& a, hipStream_t st) {
-    if (a.n_records == 0) return hipSuccess;
-    if (a.S <= 64) return launch_kpl<kLarge, 1>(a, st);
-    if (a.S <= 128) return launch_kpl<kLarge, 2>(a, st);
-    return launch_kpl<kLarge, 4>(a, st);
+// Tuned variants exist for windows of at most 128 k-mers (two per lane); other
+// window sizes use the default list capacity and workgroup shape.
+template <int KPL>
+hipError_t launch_fast_k(const QueryArgs& a, const ClassifyConfig& c, hipStream_t st) {
+    if constexpr (KPL == 2) {
+        const uint32_t key = c.list_cap * 16 + c.waves_per_block;
+        switch (key) {
+            case 256 * 16 + 2: return launch_fast_t<256, 2, KPL>(a, c.max_blocks, st);
+            case 256 * 16 + 4: return launch_fast_t<256, 4, KPL>(a, c.max_blocks, st);
+            case 256 * 16 + 8: return launch_fast_t<256, 8, KPL>(a, c.max_blocks, st);
+            case 512 * 16 + 2: return launch_fast_t<512, 2, KPL>(a, c.max_blocks, st);
+            case 512 * 16 + 8: return launch_fast_t<512, 8, KPL>(a, c.max_blocks, st);
+            case 1024 * 16 + 2: return launch_fast_t<1024, 2, KPL>(a, c.max_blocks, st);
+            case 1024 * 16 + 4: return launch_fast_t<1024, 4, KPL>(a, c.max_blocks, st);
+            case 1024 * 16 + 8: return launch_fast_t<1024, 8, KPL>(a, c.max_blocks, st);
+            default: break;
+        }
+    }
+    return launch_fast_t<kListSmall, 4, KPL>(a, c.max_blocks, st);
 }
 
 }  // namespace
 
-hipError_t launch_classify_fast(const QueryArgs& a, hipStream_t st) {
-    return launch_any<false>(a, st);
+bool classify_config_valid(const ClassifyConfig& c) {
+    return (c.list_cap == 256 || c.list_cap == 512 || c.list_cap == 1024) &&
+           (c.waves_per_block == 2 || c.waves_per_block == 4 || c.waves_per_block == 8) &&
+           c.max_blocks >= 1;
+}
+
+hipError_t launch_classify_fast(const QueryArgs& a, const ClassifyConfig& c, hipStream_t st) {
+    if (a.n_records == 0) return hipSuccess;
+    if (a.S <= 64) return launch_fast_k<1>(a, c, st);
+    if (a.S <= 128) return launch_fast_k<2>(a, c, st);
+    return launch_fast_k<4>(a, c, st);
 }
 
 hipError_t launch_classify_large(const QueryArgs& a, hipStream_t st) {
-    return launch_any<true>(a, st);
+    if (a.n_records == 0) return hipSuccess;
+    if (a.S <= 64)
+        hipLaunchKernelGGL((k_classify<kListLarge, 1, 1>), dim3(512), dim3(64), 0, st, a, 1);
+    else if (a.S <= 128)
+        hipLaunchKernelGGL((k_classify<kListLarge, 1, 2>), dim3(512), dim3(64), 0, st, a, 1);
+    else
+        hipLaunchKernelGGL((k_classify<kListLarge, 1, 4>), dim3(512), dim3(64), 0, st, a, 1);
+    return hipGetLastError();
 }
 
 }  // namespace mc

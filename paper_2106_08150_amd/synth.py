@@ -257,19 +257,22 @@ def scale_reads(genomes: Genomes, n: int = 10_000_000, seed: int = 202, progress
 
 
 def mixed_records(genomes: Genomes, n: int, seed: int = 301, error: float = 0.01,
-                  foreign: float = 0.05, chunk: int = 100_000) -> Reads:
+                  foreign: float = 0.05, chunk: int = 100_000, progress=None) -> Reads:
     """Uneven batch in the paired layout.
 
     Half the records are single-end with length U{50..250} (empty mate 2);
     half are pairs 2 x 150 from a fragment of length round(N(400, 50))
-    clipped to [150, 700]: mate 1 is the fragment start, mate 2 the reverse
-    complement of the fragment end, on a random fragment strand.
+    clipped to [150, 700] on a random strand: mate 1 reads the fragment's
+    first 150 bases, mate 2 the reverse complement of its last 150.
     """
     rng = rng_for(seed)
     off_g = genomes.offsets.astype(np.int64)
     lens = genomes.lengths.astype(np.int64)
-    pieces: list[np.ndarray] = []
-    origin = np.empty(n, dtype=np.int64)
+    ok = np.nonzero(lens >= 1500)[0]
+    w150 = _windows(genomes.text, 150)
+    w250 = _windows(genomes.text, 250)
+    cols = np.arange(250, dtype=np.int32)
+    texts, mlens = [], []
     for c0 in range(0, n, chunk):
         m = min(chunk, n - c0)
         is_pair = rng.random(m) < 0.5
@@ -277,30 +280,46 @@ def mixed_records(genomes: Genomes, n: int, seed: int = 301, error: float = 0.01
         se_len = rng.integers(50, 251, size=m)
         frag = np.clip(np.round(rng.normal(400, 50, size=m)), 150, 700).astype(np.int64)
         span = np.where(is_pair, frag, se_len)
-        gi = rng.integers(0, lens.size, size=m)
-        gi = np.where(lens[gi] >= span, gi, int(np.argmax(lens)))
-        start = (rng.random(m) * (lens[gi] - span + 1)).astype(np.int64)
+        gi = ok[rng.integers(0, ok.size, size=m)]
+        start = off_g[gi] + 250 + (rng.random(m) * (lens[gi] - 1000)).astype(np.int64)
         rev = rng.random(m) < 0.5
-        for r in range(m):
-            L = int(span[r])
-            if is_foreign[r]:
-                frag_txt = random_text(rng, L)
-            else:
-                s0 = int(off_g[gi[r]] + start[r])
-                frag_txt = genomes.text[s0:s0 + L]
-                if rev[r]:
-                    frag_txt = reverse_complement_text(frag_txt)
-            if is_pair[r]:
-                m1 = frag_txt[:150]
-                m2 = reverse_complement_text(frag_txt[L - 150:])
-            else:
-                m1 = frag_txt
-                m2 = frag_txt[:0]
-            pieces.append(substitute(rng, m1, error))
-            pieces.append(substitute(rng, m2, error) if m2.size else m2)
-            origin[c0 + r] = -1 if is_foreign[r] else gi[r]
-    text, off = _pack(pieces)
-    return Reads(text, off, True, origin)
+        # genome segment [start, start + span); on the reverse strand the
+        # fragment is its reverse complement
+        head = w150[start]                       # segment's first 150 bases
+        rc_tail = _COMP[w150[start + span - 150][:, ::-1]]
+        m1 = head.copy()                         # fragment's first 150
+        m1[rev] = rc_tail[rev]
+        m2 = rc_tail                             # revcomp of fragment's last 150
+        m2[rev] = head[rev]
+        # single-end reads: first se_len bases of the fragment
+        seg = w250[np.where(rev, start + span - 250, start)]
+        seg[rev] = _COMP[seg[rev][:, ::-1]]
+        nf = int(is_foreign.sum())
+        if nf:
+            m1[is_foreign] = random_text(rng, nf * 150).reshape(nf, 150)
+            m2[is_foreign] = random_text(rng, nf * 150).reshape(nf, 150)
+            seg[is_foreign] = random_text(rng, nf * 250).reshape(nf, 250)
+        l1 = np.where(is_pair, 150, se_len)
+        l2 = np.where(is_pair, 150, 0)
+        first = np.where(is_pair[:, None], np.concatenate([m1, np.zeros((m, 100), np.uint8)], 1),
+                         seg)
+        keep1 = cols[None, :] < l1[:, None]
+        keep2 = cols[None, :150] < l2[:, None]
+        # interleave mate 1 and mate 2 per record
+        both = np.concatenate([first, m2], axis=1)
+        keep = np.concatenate([keep1, keep2], axis=1)
+        texts.append(substitute(rng, both[keep], error))
+        ml = np.empty(2 * m, dtype=np.int64)
+        ml[0::2] = l1
+        ml[1::2] = l2
+        mlens.append(ml)
+        if progress is not None and (c0 // chunk) % 20 == 19:
+            progress(f"records {c0 + m}/{n}")
+    ml = np.concatenate(mlens) if mlens else np.zeros(0, np.int64)
+    off = np.zeros(ml.size + 1, dtype=np.uint64)
+    np.cumsum(ml, out=off[1:])
+    text = np.concatenate(texts) if texts else np.zeros(0, np.uint8)
+    return Reads(text, off, True)
 
 
 def repeated_genome(n_copies: int, length: int, seed: int) -> Genomes:

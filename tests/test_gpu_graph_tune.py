@@ -1,0 +1,117 @@
+"""Captured query graphs and the launch-shape autotuner.
+
+Every launch shape must give identical labels and top hits; a captured graph
+must reproduce the eager result on every replay (with eager work and input
+changes between replays) and be captured again after the database changes.
+"""
+import numpy as np
+import pytest
+
+import paper_2106_08150_amd as mc
+from paper_2106_08150_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    g = synth.tiny_genomes(length=60_000)
+    db = mc.Database()
+    db.add_targets(torch.from_numpy(g.text.copy()).cuda(), g.lengths, g.taxa)
+    db.set_taxonomy(g.parents)
+    recs = synth.mixed_records(g, 6000, seed=3)
+    return torch, g, db, recs
+
+
+def dev(torch, recs):
+    r = torch.from_numpy(recs.text.copy()).cuda()
+    o = torch.from_numpy(recs.offsets.view(np.int64).copy()).cuda()
+    return r, o
+
+
+def test_all_launch_shapes_agree(setup):
+    torch, g, db, recs = setup
+    r, o = dev(torch, recs)
+    ref = db.classify(r, o, recs.n_records, paired=True, insert_size=400, with_top=True)
+    for cap in (256, 512, 1024):
+        for wpb in (2, 4, 8):
+            for blocks in (1, 37, 16384):
+                mc.mc_db_set_launch_config(db.h, cap, wpb, blocks)
+                lab, top = db.classify(r, o, recs.n_records, paired=True, insert_size=400,
+                                       with_top=True)
+                torch.cuda.synchronize()
+                assert torch.equal(lab, ref[0]) and torch.equal(top, ref[1]), (cap, wpb, blocks)
+    with pytest.raises(mc.MCError):
+        mc.mc_db_set_launch_config(db.h, 300, 4, 10)
+    mc.mc_db_set_launch_config(db.h, 512, 4, 16384)
+
+
+def test_autotune_keeps_results(setup):
+    torch, g, db, recs = setup
+    r, o = dev(torch, recs)
+    ref, _ = db.classify(r, o, recs.n_records, paired=True, insert_size=400)
+    torch.cuda.synchronize()
+    out = torch.empty(recs.n_records, dtype=torch.int32, device="cuda")
+    cfg, ms = mc.mc_db_autotune(db.h, r, o, recs.n_records, mc.QueryOpts(4, 4, 0, 400, 1), out)
+    assert ms > 0 and cfg == mc.mc_db_get_launch_config(db.h)
+    lab, _ = db.classify(r, o, recs.n_records, paired=True, insert_size=400)
+    torch.cuda.synchronize()
+    assert torch.equal(lab, ref) and torch.equal(out, ref)
+    mc.mc_db_set_launch_config(db.h, 512, 4, 16384)
+
+
+def test_graph_replays_match_eager(setup):
+    torch, g, db, recs = setup
+    other = synth.mixed_records(g, recs.n_records, seed=99)
+    r, o = dev(torch, recs)
+    r2, o2 = dev(torch, other)
+    n = recs.n_records
+    opts = mc.QueryOpts(4, 4, 0, 400, 1)
+    eager1 = db.classify(r, o, n, paired=True, insert_size=400, with_top=True)
+    eager2 = db.classify(r2, o2, n, paired=True, insert_size=400, with_top=True)
+    # graph buffers: copies that we overwrite between replays
+    gr = torch.empty(max(r.numel(), r2.numel()), dtype=torch.uint8, device="cuda")
+    go = torch.empty_like(o)
+    lab = torch.empty(n, dtype=torch.int32, device="cuda")
+    top = torch.empty((n, 4, 3), dtype=torch.int32, device="cuda")
+    gr[:r.numel()].copy_(r)
+    go.copy_(o)
+    graph = mc.ClassifyGraph(db.h, gr, go, n, opts, lab, top)
+    for rep in range(4):
+        src, so, want = ((r, o, eager1) if rep % 2 == 0 else (r2, o2, eager2))
+        gr[:src.numel()].copy_(src)
+        go.copy_(so)
+        lab.fill_(-7)
+        top.fill_(-7)
+        graph.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(lab, want[0]) and torch.equal(top, want[1]), rep
+        # eager work between replays
+        db.classify(r2, o2, n, paired=True, insert_size=400)
+        torch.cuda.synchronize()
+    graph.close()
+
+
+def test_graph_recaptured_after_addition(setup):
+    torch, g, _, recs = setup
+    off = g.offsets
+    db = mc.Database()
+    db.add_targets(g.text[:int(off[4])], g.lengths[:4], g.taxa[:4])
+    db.set_taxonomy(g.parents)
+    r, o = dev(torch, recs)
+    n = recs.n_records
+    lab = torch.empty(n, dtype=torch.int32, device="cuda")
+    graph = mc.ClassifyGraph(db.h, r, o, n, mc.QueryOpts(4, 4, 0, 400, 1), lab)
+    graph.launch()
+    torch.cuda.synchronize()
+    before = lab.clone()
+    db.add_targets(g.text[int(off[4]):], g.lengths[4:], g.taxa[4:])
+    graph.launch()
+    torch.cuda.synchronize()
+    want, _ = db.classify(r, o, n, paired=True, insert_size=400)
+    torch.cuda.synchronize()
+    assert torch.equal(lab, want) and not torch.equal(before, want)
+    graph.close()
