@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=20_000,
                     help="reads classified by the CPU oracle (0 = skip the CPU baseline)")
     ap.add_argument("--cpu-threads", type=int, default=0, help="0 = min(16, host cores)")
+    ap.add_argument("--uneven-records", type=int, default=20_000_000,
+                    help="records of the uneven-batch leg (0 = skip)")
     ap.add_argument("--served-batches", type=int, default=100,
                     help="batches of the served-form trace (0 = skip the served leg)")
     ap.add_argument("--served-loads", type=str, default="0.7,1.0,1.5,2.0",
@@ -81,6 +83,60 @@ def cpu_baseline(g, reads, n_sample, threads, gpu_labels):
         "build_sketch_bp_per_s": float(g.lengths.sum()) / (t2 - t1),
         "build_sketch_cores": threads,
         "sample_label_mismatches_vs_gpu": mism,
+    }
+
+
+def uneven_leg(args, g, gtext, torch, mc, synth):
+    """Mixed single-end (U{50..250} bp) and paired (2 x 150 bp, fragment
+    N(400, 50)) records in one offsets array: autotuned launch shape, then the
+    classification captured in a HIP graph and replayed."""
+    recs = synth.mixed_records(g, args.uneven_records, seed=301, progress=log)
+    n = recs.n_records
+    mates = int((np.diff(recs.offsets) > 0).sum())
+    dev = gtext.device
+    r = torch.from_numpy(recs.text).to(dev)
+    o = torch.from_numpy(recs.offsets.view(np.int64)).to(dev)
+    labels = torch.empty(n, dtype=torch.int32, device=dev)
+    db = mc.Database(K, WINDOW, SKETCH, CAP)
+    db.add_targets(gtext, g.lengths, g.taxa)
+    db.set_taxonomy(g.parents)
+    opts = mc.QueryOpts(4, 4, 0, 400, 1)
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    default_ms = timed(lambda: mc.mc_classify_ex(db.h, r, o, n, opts, labels))
+    ref = labels.clone()
+    m = min(n, 500_000)
+    sub_o = o[:2 * m + 1].contiguous()
+    cfg, _ = mc.mc_db_autotune(db.h, r, sub_o, m, opts, labels)
+    graph = mc.ClassifyGraph(db.h, r, o, n, opts, labels)
+    graph_ms = timed(graph.launch)
+    same = bool(torch.equal(labels, ref))
+    graph.close()
+    db.close()
+    log(f"uneven: {n} records ({mates} mates), default {default_ms:.2f} ms, tuned "
+        f"{cfg} + graph {graph_ms:.2f} ms, identical {same}")
+    return {
+        "workload": (f"{n} records in one paired-layout offsets array: 50% single-end "
+                     "U{50..250} bp, 50% pairs 2 x 150 bp (fragment N(400, 50)), 1% "
+                     "substitutions, 5% foreign; insert_size 400"),
+        "records": n, "mates": mates,
+        "default_config_ms": default_ms,
+        "tuned_config": {"list_capacity": cfg[0], "waves_per_block": cfg[1],
+                         "max_blocks": cfg[2]},
+        "graph_ms": graph_ms,
+        "records_per_s": n / (graph_ms * 1e-3),
+        "mates_per_s": mates / (graph_ms * 1e-3),
+        "labels_identical_to_default": same,
     }
 
 
@@ -349,6 +405,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": None,
     }
+    if args.uneven_records > 0:
+        out["uneven"] = uneven_leg(args, g, gtext, torch, mc, synth)
     if args.served_batches > 0:
         out["served"] = served_leg(args, g, gtext, torch, mc, synth)
     if args.cpu_sample > 0:
