@@ -140,6 +140,9 @@ int ensure_capacity(mc_db* db, uint64_t extra, hipStream_t st) {
     uint64_t nb = (uint64_t)std::ceil((double)need / (db->load * slots_per_bucket));
     if (db->table) nb = std::max<uint64_t>(nb, db->nb + db->nb / 2);   // grow by >= 1.5x
     nb = std::max<uint64_t>(nb, kMinBuckets);
+    // bucket indices are 32-bit in the query kernels (2^32 buckets = 512 GiB)
+    if (nb > 0xFFFFFFFFull)
+        return fail(MC_ERR_OOM, "table of %llu buckets exceeds 2^32 - 1", (unsigned long long)nb);
     unsigned long long* t = nullptr;
     uint32_t* cnt = nullptr;
     int rc = dev_alloc(&t, nb * kSlots);

@@ -287,9 +287,9 @@ __device__ uint32_t chain_pass(unsigned long long* table, uint64_t nb, uint32_t 
         for (int x = 3; x >= 0; --x)
             if ((emp >> (16 * x)) & 0xFFFFull) gend = x;
         uint32_t loc = (uint32_t)sl;
-        bool mine = g <= gend && sl != kEmpty && (uint32_t)(sl >> 32) == f && loc != kBadLoc;
+        bool mine = g <= gend && (uint32_t)(sl >> 32) == f && live_entry(sl);
         if (kMark) {
-            if (mine && loc > thr) *p = ((unsigned long long)f << 32) | kBadLoc;
+            if (mine && loc > thr) *p = ((unsigned long long)f << 32) | kTombLoc;
         } else {
             total += popc64(ballot(mine && loc <= thr));
         }
@@ -332,7 +332,7 @@ __global__ __launch_bounds__(256) void k_cap_scan(unsigned long long* table, uin
         uint64_t sl = i < n ? (uint64_t)table[i] : kEmpty;
         bool hit = false;
         uint32_t f = (uint32_t)(sl >> 32);
-        if (sl != kEmpty && (uint32_t)sl != kBadLoc) {
+        if (live_entry(sl)) {
             uint64_t hb = home_bucket(f, nb), bb = i / kSlots;
             uint64_t dist = bb >= hb ? bb - hb : bb + nb - hb;
             hit = dist >= cap_dist;
@@ -357,7 +357,7 @@ __global__ __launch_bounds__(256) void k_rehash(const unsigned long long* old_ta
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * blockDim.x) {
         const unsigned long long e = old_table[i];
-        if (e == kEmpty || (uint32_t)e == kBadLoc) continue;
+        if (!live_entry(e)) continue;
         const uint64_t d = insert_one(table, bcount, nb, home_bucket((uint32_t)(e >> 32), nb), e);
         if (d <= nb) moved += 1;
         else atomicAdd(&counters[kCntFull], 1ull);
@@ -389,7 +389,7 @@ __global__ __launch_bounds__(256) void k_dump(const unsigned long long* table, u
         uint64_t i = i0 + threadIdx.x;
         uint64_t e = i < n ? (uint64_t)table[i] : kEmpty;
         uint32_t f = (uint32_t)(e >> 32);
-        bool keep = e != kEmpty && (uint32_t)e != kBadLoc && f >= lo && f <= hi;
+        bool keep = live_entry(e) && f >= lo && f <= hi;
         uint64_t m = ballot(keep);
         if (m == 0) continue;
         uint64_t base = 0;
@@ -408,7 +408,7 @@ __global__ __launch_bounds__(256) void k_count_valid(const unsigned long long* t
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * blockDim.x) {
         uint64_t e = table[i];
-        c += (e != kEmpty && (uint32_t)e != kBadLoc) ? 1u : 0u;
+        c += live_entry(e) ? 1u : 0u;
     }
 #pragma unroll
     for (int m = 1; m < kWave; m <<= 1) c += shfl_xor(c, m);

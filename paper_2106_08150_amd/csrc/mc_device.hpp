@@ -17,20 +17,28 @@ namespace mc {
 constexpr uint32_t kWindowBits = 18;
 constexpr uint32_t kWindowMask = (1u << kWindowBits) - 1;
 constexpr uint32_t kNone = 0xFFFFFFFFu;        // unclassified label / unused hit
-constexpr uint32_t kBadLoc = 0xFFFFFFFFu;      // never a real location
 constexpr uint64_t kEmpty = ~0ull;             // empty table slot
+// Location field of a capped-away entry (tombstone). Real locations stay below
+// 0xFFFC0000 (targets < 16383), and a tombstone never equals an empty slot,
+// not even for feature 0xFFFFFFFF.
+constexpr uint32_t kTombLoc = 0xFFFFFFFEu;
+
+// A slot holding a stored pair (neither empty nor a tombstone).
+__device__ __forceinline__ bool live_entry(uint64_t e) { return (uint32_t)e < kTombLoc; }
 
 constexpr int kWave = 64;
 
 // ------------------------------------------------------------------ lanes --
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
-__device__ __forceinline__ uint64_t ballot(bool p) { return (uint64_t)__ballot(p); }
+// Lanes whose predicate holds (the builtin takes the compare result directly;
+// going through an int would materialise it in a VGPR first).
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
-// Number of set bits of `mask` in lanes below the calling lane.
-__device__ __forceinline__ uint32_t rank_below(uint64_t mask) {
+// Number of set bits of `mask` in lanes below the calling lane, plus `base`.
+__device__ __forceinline__ uint32_t rank_below(uint64_t mask, uint32_t base = 0u) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, base));
 }
 
 __device__ __forceinline__ uint32_t popc64(uint64_t m) { return (uint32_t)__popcll(m); }

@@ -91,6 +91,7 @@ enum QueryStat { kQsFeatures = 0, kQsLocations = 1, kQsProbes = 2, kNumQueryStat
 
 constexpr uint32_t kListSmall = 512;     // candidate locations per record, fast path
 constexpr uint32_t kListLarge = 16384;   // large-list pass (one wave per workgroup)
+static_assert(kListLarge < 0x10000, "top-m keys pack a distinct-location index in 16 bits");
 constexpr uint32_t kMaxTopM = 8;
 
 // Launchers (return hipError_t of the launch).

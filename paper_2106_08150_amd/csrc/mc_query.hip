@@ -15,77 +15,90 @@ namespace {
 constexpr int kStageWords = 20;    // one window of at most 271 bases
 constexpr uint32_t kMaxFeat = 128; // sketch elements buffered before lookups
 
+constexpr uint32_t kRing = kMaxFeat;   // lookup work items: at most one per feature
+
 template <uint32_t LCAP>
 struct QueryLds {
     Word stage[kStageWords];
     uint32_t scratch[kWave];
     uint32_t feats[kMaxFeat];
-    unsigned long long home[kMaxFeat];
-    uint32_t list[LCAP + 1];         // list[LCAP] takes the writes of non-matching lanes
+    uint2 ring[kRing];                // (feature, bucket) lookup work items
+    uint32_t list[LCAP + kWave];      // one item batch may overshoot LCAP by < 64
     uint16_t uidx[LCAP + 2];
     uint16_t score[LCAP];
     uint32_t sel_t[kMaxTopM], sel_s[kMaxTopM], sel_b[kMaxTopM];   // top-m list
 };
 
-// Append the locations of features F[0..nf) to list (LDS). Each feature's
-// home bucket is computed once (one lane per feature, kept in H). 16-lane
-// groups then read one bucket line per feature; a feature's chain ends at the
-// first bucket that has an empty slot. Pending work is tracked in wave-uniform
-// lane masks so that the loop has no per-lane branches: every group loads
-// every round (a finished group re-reads its last line), and lanes without a
-// match write to the dump slot list[LCAP]. Returns false once the list outgrew
-// LCAP.
+// s_waitcnt immediate for vmcnt(0) with the other counters left alone (gfx9
+// encoding: vmcnt bits 3..0 and 15..14, expcnt 6..4, lgkmcnt 11..8).
+constexpr int kWaitVmem0 = 0x0F70;
+
+// Lanes 15, 31, 47 and 63: the last slot of the bucket each 16-lane group reads.
+constexpr uint64_t kLastSlots = 0x8000800080008000ull;
+
+// Append the locations of features F[0..nf) to list (LDS). A work item is a
+// (feature, bucket) pair; the wave takes up to 4 * NB items at a time, item
+// 4q + g read by 16-lane group g as one 128-byte bucket line (lane = slot), so
+// that NB lines per group are in flight. Slots of a bucket fill in order, so
+// a bucket is full exactly when its last slot is occupied: a full bucket
+// queues the feature's next bucket as a new item, and a feature's chain ends
+// at its first bucket that is not full (inserts never pass such a bucket).
+// Items wait in a ring in LDS, at most one per feature. Returns false once the
+// list outgrew LCAP.
 template <uint32_t LCAP>
-__device__ bool lookup(const QueryArgs& a, const uint32_t* F, unsigned long long* H,
-                       uint32_t nf, uint32_t* list, uint32_t& nlist, uint32_t& probes) {
+__device__ bool lookup(const QueryArgs& a, const uint32_t* F, uint32_t nf, uint2* ring,
+                       uint32_t* list, uint32_t& nlist, uint32_t& probes) {
     constexpr int NB = 8;
     const uint32_t lane = (uint32_t)lane_id();
-    const uint32_t g = lane >> 4, gl = lane & 15;
-    for (uint32_t i = lane; i < nf; i += kWave) H[i] = home_bucket(F[i], a.nb);
+    const uint32_t g = lane >> 4;
+    const uint32_t nb = (uint32_t)a.nb;
+    for (uint32_t i = lane; i < nf; i += kWave)
+        ring[i] = make_uint2(F[i], (uint32_t)home_bucket(F[i], a.nb));
     wave_lds_sync();
-    for (uint32_t base = 0; base < nf; base += 4 * NB) {
-        uint32_t f[NB];
-        uint64_t b[NB];
-        uint32_t pg[NB];   // groups (bit g) whose q-th feature is still pending
+    const unsigned long long* slot = a.table + (lane & 15u);
+    uint32_t head = 0, tail = nf;
+    while (head < tail) {
+        const uint32_t c = min(tail - head, 4u * NB);
+        uint32_t f[NB], b[NB];
+        uint64_t sl[NB];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {   // groups past the last item take the last item
+            const uint2 it = ring[(head + min(4u * q + g, c - 1u)) & (kRing - 1u)];
+            f[q] = it.x;
+            b[q] = it.y;
+        }
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+            if (4u * q < c) sl[q] = slot[(uint64_t)b[q] * kSlots];
+        head += c;
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
-            const uint32_t i0 = base + 4u * (uint32_t)q;       // feature of group 0
-            const uint32_t ng = nf > i0 ? min(nf - i0, 4u) : 0u; // groups with a feature
-            pg[q] = (1u << ng) - 1u;
-            const uint32_t i = min(i0 + g, nf - 1);
-            f[q] = F[i];
-            b[q] = H[i];
-        }
-        while (true) {
-            uint32_t any = 0;
-#pragma unroll
-            for (int q = 0; q < NB; ++q) any |= pg[q];
-            if (any == 0) break;
-            uint64_t sl[NB];
-#pragma unroll
-            for (int q = 0; q < NB; ++q) {
-                sl[q] = a.table[b[q] * kSlots + gl];
-                probes += (uint32_t)__popc(pg[q]);
+            if (4u * q >= c) break;
+            const uint32_t nv = min(c - 4u * q, 4u);   // groups holding an item
+            probes += nv;
+            const bool valid = g < nv;
+            const uint32_t hi = (uint32_t)(sl[q] >> 32), lo = (uint32_t)sl[q];
+            const bool mine = valid && hi == f[q] && lo < kTombLoc;
+            const uint64_t hit = ballot(mine);
+            if (hit) {
+                if (mine) list[rank_below(hit, nlist)] = lo;
+                nlist += popc64(hit);
+                if (nlist > LCAP) return false;
             }
-#pragma unroll
-            for (int q = 0; q < NB; ++q) {
-                const uint32_t hi = (uint32_t)(sl[q] >> 32), lo = (uint32_t)sl[q];
-                const bool pend = (pg[q] >> g) & 1u;
-                const uint64_t mb = ballot(pend && hi == f[q] && lo != kBadLoc);
-                const bool mine = (mb >> lane) & 1ull;
-                const uint32_t pos = nlist + rank_below(mb);
-                list[mine && pos < LCAP ? pos : LCAP] = lo;
-                nlist += popc64(mb);
-                const uint64_t emp = ballot(sl[q] == kEmpty);
-                uint32_t done = 0;
-#pragma unroll
-                for (int x = 0; x < 4; ++x)
-                    if ((emp >> (16 * x)) & 0xFFFFull) done |= 1u << x;
-                pg[q] &= ~done;
-                if ((pg[q] >> g) & 1u) b[q] = next_bucket(b[q], a.nb);
+            const bool occupied = valid && sl[q] != kEmpty;
+            const uint64_t full = ballot(occupied) & kLastSlots;
+            if (full) {
+                if (occupied && (lane & 15u) == 15u) {
+                    const uint32_t nxt = b[q] + 1u == nb ? 0u : b[q] + 1u;
+                    ring[(tail + rank_below(full)) & (kRing - 1u)] = make_uint2(f[q], nxt);
+                }
+                tail += popc64(full);
             }
-            if (nlist > LCAP) return false;
         }
+        // every issued line has been used by now; saying so lets the next
+        // batch's loads go out without waiting on the lines of unused groups
+        __builtin_amdgcn_s_waitcnt(kWaitVmem0);
+        wave_lds_sync();
     }
     return true;
 }
@@ -207,14 +220,14 @@ __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>
             wave_lds_sync();
             if (nf + a.s > kMaxFeat) {
                 ws.features += nf;
-                fits = lookup<LCAP>(a, L.feats, L.home, nf, L.list, nlist, ws.probes);
+                fits = lookup<LCAP>(a, L.feats, nf, L.ring, L.list, nlist, ws.probes);
                 nf = 0;
             }
         }
     }
     if (fits && nf) {
         ws.features += nf;
-        fits = lookup<LCAP>(a, L.feats, L.home, nf, L.list, nlist, ws.probes);
+        fits = lookup<LCAP>(a, L.feats, nf, L.ring, L.list, nlist, ws.probes);
     }
     if (!fits) {
         if (!big) {
@@ -261,32 +274,52 @@ __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>
     wave_lds_sync();
 
     // top-m targets by (score desc, target asc); per target the range with the
-    // highest score, ties to the smallest start window: m rounds of a wave
-    // maximum of the score, then of ~location among the lanes holding it
+    // highest score, ties to the smallest start window. The key of distinct
+    // location u is score << 16 | (0xFFFF - u): distinct locations ascend with
+    // u, so the wave maximum of the keys is the highest score and, among equal
+    // scores, the smallest location (smallest target, then window). Each of
+    // the m rounds takes one wave maximum and then drops the chosen target.
     uint32_t nsel = 0;
-    for (uint32_t m = 0; m < a.top_m; ++m) {
-        uint32_t bs = 0, bl = 0;     // lane's best (score, ~location)
-        for (uint32_t u = (uint32_t)lane; u < U; u += kWave) {
-            const uint32_t loc = L.list[L.uidx[u]];
-            const uint32_t t = loc >> kWindowBits;
-            bool excluded = false;
-            for (uint32_t x = 0; x < m; ++x) excluded |= (L.sel_t[x] == t);
-            const uint32_t sc = excluded ? 0u : (uint32_t)L.score[u];
-            if (sc > bs || (sc == bs && sc != 0 && ~loc > bl)) {
-                bs = sc;
-                bl = ~loc;
-            }
+    if (U <= (uint32_t)kWave) {          // one distinct location per lane
+        uint32_t key = 0, t = kNone;
+        if ((uint32_t)lane < U) {
+            t = L.list[L.uidx[lane]] >> kWindowBits;
+            key = ((uint32_t)L.score[lane] << 16) | (0xFFFFu - (uint32_t)lane);
         }
-        const uint32_t best_s = wave_max_u32(bs);
-        if (best_s == 0) break;
-        const uint32_t loc = ~wave_max_u32(bs == best_s ? bl : 0u);
-        if (lane == 0) {
-            L.sel_t[m] = loc >> kWindowBits;
-            L.sel_s[m] = best_s;
-            L.sel_b[m] = loc & kWindowMask;
+        for (uint32_t m = 0; m < a.top_m; ++m) {
+            const uint32_t k = wave_max_u32(key);
+            if (k == 0) break;
+            const uint32_t loc = L.list[L.uidx[0xFFFFu - (k & 0xFFFFu)]];
+            if (lane == 0) {
+                L.sel_t[m] = loc >> kWindowBits;
+                L.sel_s[m] = k >> 16;
+                L.sel_b[m] = loc & kWindowMask;
+            }
+            if (t == loc >> kWindowBits) key = 0;
+            nsel = m + 1;
         }
         wave_lds_sync();
-        nsel = m + 1;
+    } else {
+        for (uint32_t m = 0; m < a.top_m; ++m) {
+            uint32_t key = 0;
+            for (uint32_t u = (uint32_t)lane; u < U; u += kWave) {
+                const uint32_t t = L.list[L.uidx[u]] >> kWindowBits;
+                bool excluded = false;
+                for (uint32_t x = 0; x < m; ++x) excluded |= (L.sel_t[x] == t);
+                const uint32_t ku = ((uint32_t)L.score[u] << 16) | (0xFFFFu - u);
+                if (!excluded && ku > key) key = ku;
+            }
+            const uint32_t k = wave_max_u32(key);
+            if (k == 0) break;
+            const uint32_t loc = L.list[L.uidx[0xFFFFu - (k & 0xFFFFu)]];
+            if (lane == 0) {
+                L.sel_t[m] = loc >> kWindowBits;
+                L.sel_s[m] = k >> 16;
+                L.sel_b[m] = loc & kWindowMask;
+            }
+            wave_lds_sync();
+            nsel = m + 1;
+        }
     }
 
     // label: the best target's taxon on a clear lead, else the LCA of the

@@ -173,6 +173,26 @@ def test_cap_stress_repeated_genomes(torch):
     assert mc.mc_db_query_status(gdb.h) == 0
 
 
+def test_sentinel_feature_over_cap(torch):
+    """Feature 0xFFFFFFFF stored more often than the cap: its capped-away
+    entries must not read as empty slots, or the chains of other features
+    that run through those buckets would end early."""
+    rng = np.random.default_rng(23)
+    base = np.frombuffer(b"ACGT", np.uint8)[rng.integers(0, 4, 20_000)]
+    island = np.frombuffer(b"N" * 120 + SENTINEL_KMER.encode() + b"N" * 120, np.uint8)
+    one = np.concatenate([base[:9_000], island, base[9_000:]])
+    n = 300
+    g = synth.Genomes(np.tile(one, n), np.full(n, one.size, np.uint64),
+                      np.arange(1, n + 1, dtype=np.uint32), np.zeros(n + 1, np.uint32))
+    gdb, odb = build_both(torch, g)
+    assert_same_table(gdb, odb)
+    f, _ = gdb.dump(0xFFFFFFFF, 0xFFFFFFFF)
+    assert f.size == 254
+    reads = synth.sample_reads(g, 300, 100, seed=9, error=0.0)
+    gl, gt, ol, ot = classify_both(torch, gdb, odb, reads, top_m=8, min_hits=1)
+    assert_same_results(gl, gt, ol, ot)
+
+
 @pytest.mark.parametrize("cap", [1, 3, 17])
 def test_small_caps_and_incremental_adds(torch, cap):
     g = synth.tiny_genomes(length=30_000)
