@@ -46,7 +46,6 @@ constexpr uint64_t kMaxSlotsPerChunk = 1ull << 30;      // pair slots per build 
 constexpr uint64_t kPartBytes = 256ull << 20;           // target table bytes per partition
 constexpr uint64_t kMinBuckets = 64;
 constexpr uint64_t kCandCapMax = 1ull << 24;
-constexpr uint32_t kMaxPartsApi = 256;
 
 struct Workspace {
     uint32_t* queue = nullptr;
@@ -107,6 +106,10 @@ struct mc_db {
     uint32_t* hist = nullptr;
     unsigned long long* part_start = nullptr;
     unsigned long long* cursor = nullptr;
+    uint32_t* hist2 = nullptr;                  // slice-mode insert: kMaxSlices
+    unsigned long long* slice_start = nullptr;  // kMaxSlices + 1
+    unsigned long long* cursor2 = nullptr;      // kMaxSlices
+    unsigned long long* chunk_first = nullptr;  // 2 * (kMaxParts + 1)
     // fast-path launch shape (set by mc_db_set_launch_config / mc_db_autotune)
     ClassifyConfig cfg;
     // bumped whenever device arrays a captured graph refers to may have moved
@@ -230,9 +233,13 @@ hipError_t drain(Timed& t, double* ms, uint64_t* n) {
 
 int ensure_scratch(mc_db* db, uint64_t slots) {
     if (!db->hist) {
-        int rc = dev_alloc(&db->hist, kMaxPartsApi);
-        if (!rc) rc = dev_alloc(&db->part_start, kMaxPartsApi + 1);
-        if (!rc) rc = dev_alloc(&db->cursor, kMaxPartsApi);
+        int rc = dev_alloc(&db->hist, kMaxParts);
+        if (!rc) rc = dev_alloc(&db->part_start, kMaxParts + 1);
+        if (!rc) rc = dev_alloc(&db->cursor, kMaxParts);
+        if (!rc) rc = dev_alloc(&db->hist2, kMaxSlices);
+        if (!rc) rc = dev_alloc(&db->slice_start, kMaxSlices + 1);
+        if (!rc) rc = dev_alloc(&db->cursor2, kMaxSlices);
+        if (!rc) rc = dev_alloc(&db->chunk_first, 2 * (kMaxParts + 1));
         if (rc) return rc;
     }
     if (slots <= db->pairs_cap) return MC_OK;
@@ -247,17 +254,44 @@ int ensure_scratch(mc_db* db, uint64_t slots) {
     return MC_OK;
 }
 
-// Table partitions for the insert pass: slices of about kPartBytes (the
-// MC_PART_MB environment variable overrides the slice size for tuning).
-uint32_t partition_bits(uint64_t table_bytes) {
-    uint64_t part = kPartBytes;
-    if (const char* env = getenv("MC_PART_MB")) {
-        long mb = atol(env);
-        if (mb > 0) part = (uint64_t)mb << 20;
+uint32_t ceil_log2(uint64_t x) {
+    uint32_t b = 0;
+    while (b < 63 && (1ull << b) < x) ++b;
+    return b;
+}
+
+// Partitioning of the insert pass. Slice mode (the default): slices of
+// 2^slice_shift buckets (at least 1024, at most 65536 slices, counters fit
+// LDS), 2^fine_bits slices per partition, at most 256 partitions. Otherwise
+// (tables too large for that, or MC_INSERT=global) partitions of about
+// kPartBytes of table each (MC_PART_MB overrides) with global counters.
+void plan_partitions(const mc_db* db, BuildArgs& a) {
+    const uint64_t nb = db->nb;
+    const uint32_t lg = ceil_log2(nb);
+    const uint32_t sb = std::max<uint32_t>(kMinSliceShift, lg > 16 ? lg - 16 : 0);
+    const char* mode = getenv("MC_INSERT");
+    const bool global = mode && std::string(mode) == "global";
+    if (!global && slice_mode_fits(sb)) {
+        const uint32_t ns_bits = lg > sb ? lg - sb : 0;       // slices: 2^ns_bits >= nb >> sb
+        const uint32_t fb = ns_bits > 8 ? ns_bits - 8 : 0;
+        a.slice_mode = 1;
+        a.slice_shift = sb;
+        a.fine_bits = fb;
+        a.part_shift = sb + fb;
+    } else {
+        uint64_t part = kPartBytes;
+        if (const char* env = getenv("MC_PART_MB")) {
+            long mb = atol(env);
+            if (mb > 0) part = (uint64_t)mb << 20;
+        }
+        const uint64_t per = std::max<uint64_t>(1, part / (kSlots * 8));   // buckets
+        uint32_t sh = ceil_log2(per);
+        while (((nb - 1) >> sh) + 1 > kMaxParts) ++sh;
+        a.slice_mode = 0;
+        a.slice_shift = a.fine_bits = 0;
+        a.part_shift = sh;
     }
-    uint32_t bits = 0;
-    while (bits < 8 && (table_bytes >> bits) > part) ++bits;
-    return bits;
+    a.n_parts = (uint32_t)(((nb - 1) >> a.part_shift) + 1);
 }
 
 // Build pipeline over targets [t0, t1) of the call (one chunk).
@@ -289,7 +323,7 @@ int build_chunk(mc_db* db, const uint8_t* genomes, const std::vector<TargetDesc>
     } guard{d_td, d_tf};
     HIP_TRY(hipMemcpyAsync(d_td, td.data(), n * sizeof(TargetDesc), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(d_tf, tile_first.data(), (n + 1) * 8, hipMemcpyHostToDevice, st));
-    HIP_TRY(launch_fill_u32(db->hist, kMaxPartsApi, 0u, st));
+    HIP_TRY(launch_fill_u32(db->hist, kMaxParts, 0u, st));
 
     BuildArgs a{};
     a.text = genomes + off0;
@@ -308,10 +342,18 @@ int build_chunk(mc_db* db, const uint8_t* genomes, const std::vector<TargetDesc>
     a.counters = db->counters;
     a.pairs = db->pairs;
     a.parted = db->parted;
-    a.part_bits = partition_bits(db->nb * kSlots * 8);
+    plan_partitions(db, a);
     a.hist = db->hist;
     a.part_start = db->part_start;
     a.cursor = db->cursor;
+    a.hist2 = db->hist2;
+    a.slice_start = db->slice_start;
+    a.cursor2 = db->cursor2;
+    a.chunk_first = db->chunk_first;
+    if (a.slice_mode) {
+        HIP_TRY(launch_fill_u32(db->hist2, (uint64_t)a.n_parts << a.fine_bits, 0u, st));
+        HIP_TRY(launch_fill_u64(db->counters + kCntDefer, 1, 0ull, st));
+    }
     HIP_TRY(timed_launch(db, db->timers[MC_K_SKETCH], st, [&] { return launch_sketch(a, true, st); }));
     HIP_TRY(timed_launch(db, db->timers[MC_K_SCATTER], st,
                          [&] { return launch_partition(a, slots, st); }));
@@ -606,6 +648,10 @@ int mc_db_destroy(mc_db* db) {
     (void)hipFree(db->hist);
     (void)hipFree(db->part_start);
     (void)hipFree(db->cursor);
+    (void)hipFree(db->hist2);
+    (void)hipFree(db->slice_start);
+    (void)hipFree(db->cursor2);
+    (void)hipFree(db->chunk_first);
     (void)hipFree(db->table);
     (void)hipFree(db->bcount);
     (void)hipFree(db->counters);

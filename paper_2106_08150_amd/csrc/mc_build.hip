@@ -16,20 +16,18 @@ constexpr int kMaxSketch = 64;
 // window of at most 271 bases, 16 bases per word, plus alignment and one
 // look-ahead word.
 constexpr int kTileWordsMax = ((kTileWindows - 1) * 256 + 271 + 15) / 16 + 3;
-constexpr uint32_t kMaxParts = 256;   // table partitions (8 bits)
 
 struct SketchLds {
     Word words[kTileWordsMax];
     uint32_t scratch[kWavesPerBuild][kWave];
-    uint32_t feats[kWavesPerBuild][kMaxSketch];
+    uint32_t feats[kWavesPerBuild][2 * kMaxSketch];   // sketches of a window pair
     uint32_t hist[kMaxParts];
 };
 
-// Bucket-range partition of a feature: the top bits of h2, so partition p
-// holds the features whose home buckets form the p-th contiguous slice of the
-// table (home = floor(h2 * nb / 2^64) is monotone in h2).
-__device__ __forceinline__ uint32_t part_of(uint32_t f, uint32_t bits) {
-    return bits ? (uint32_t)(h2(f) >> (64 - bits)) : 0u;
+// Partition of a feature: its home bucket >> part_shift, so partition p holds
+// the features whose home buckets form the p-th contiguous range of the table.
+__device__ __forceinline__ uint32_t part_of(uint32_t f, uint64_t nb, uint32_t shift) {
+    return (uint32_t)(home_bucket(f, nb) >> shift);
 }
 
 // Sketch every window of the call (B1-B4). One workgroup stages a tile of 32
@@ -44,7 +42,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_sketch(BuildArgs a) {
     __shared__ SketchLds L;
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
-    const uint32_t P = 1u << a.part_bits;
+    const uint32_t P = a.n_parts;
     if (kPairs) {
         for (uint32_t p = tid; p < P; p += kBuildThreads) L.hist[p] = 0;
     }
@@ -68,28 +66,39 @@ __global__ __launch_bounds__(kBuildThreads) void k_sketch(BuildArgs a) {
         __syncthreads();
         const uintptr_t A0 = blo & ~(uintptr_t)15;
         const uint64_t n_starts = td.len - a.k + 1;
-        for (uint32_t wv = (uint32_t)wave; wv < nwin; wv += kWavesPerBuild) {
-            const uint32_t j = j0 + wv;
-            const uint64_t first = (uint64_t)j * a.S;
-            const uint32_t nk = (uint32_t)min((uint64_t)a.S, n_starts - first);
-            const uint32_t x0 = (uint32_t)(tstart + first - A0);
+        // each wave sketches pairs of windows (2i, 2i+1) of the tile
+        for (uint32_t wv = 2u * (uint32_t)wave; wv < nwin; wv += 2u * kWavesPerBuild) {
+            uint32_t nk[2], x0[2];
+            for (int h = 0; h < 2; ++h) {
+                const uint32_t j = j0 + wv + (uint32_t)h;
+                const uint64_t first = (uint64_t)j * a.S;
+                nk[h] = wv + h < nwin ? (uint32_t)min((uint64_t)a.S, n_starts - first) : 0u;
+                x0[h] = wv + h < nwin ? (uint32_t)(tstart + first - A0) : 0u;
+            }
             uint32_t* sk = L.feats[wave];
-            uint32_t n = sketch_window<KPL>(L.words, x0, nk, a.k, a.s, sk, L.scratch[wave]);
+            uint32_t n[2];
+            sketch_pair<KPL>(L.words, x0[0], nk[0], L.words, x0[1], nk[1], a.k, a.s, sk,
+                             sk + kMaxSketch, L.scratch[wave], n[0], n[1]);
             wave_lds_sync();
-            const uint64_t gw = td.win_base + j;
-            if (kPairs) {
-                if ((uint32_t)lane < a.s) {
-                    uint64_t e = kEmpty;
-                    if ((uint32_t)lane < n) {
-                        uint32_t f = sk[lane];
-                        e = ((uint64_t)f << 32) | ((td.id << kWindowBits) | j);
-                        atomicAdd(&L.hist[part_of(f, a.part_bits)], 1u);
+            // entry e of the pair: window e / s, sketch slot e % s
+            const uint32_t npair = wv + 1 < nwin ? 2u : 1u;
+            for (uint32_t e = (uint32_t)lane; e < npair * a.s; e += kWave) {
+                const uint32_t h = e >= a.s ? 1u : 0u, i = e - h * a.s;
+                const uint32_t j = j0 + wv + h;
+                const uint64_t gw = td.win_base + j;
+                const uint32_t nh = h ? n[1] : n[0];
+                if (kPairs) {
+                    uint64_t pe = kEmpty;
+                    if (i < nh) {
+                        const uint32_t f = sk[h * kMaxSketch + i];
+                        pe = ((uint64_t)f << 32) | ((td.id << kWindowBits) | j);
+                        atomicAdd(&L.hist[part_of(f, a.nb, a.part_shift)], 1u);
                     }
-                    a.pairs[gw * a.s + lane] = e;
+                    a.pairs[gw * a.s + i] = pe;
+                } else {
+                    if (i == 0) a.out_counts[gw] = nh;
+                    if (i < nh) a.out_feats[gw * a.s + i] = sk[h * kMaxSketch + i];
                 }
-            } else {
-                if (lane == 0) a.out_counts[gw] = n;
-                if ((uint32_t)lane < n) a.out_feats[gw * a.s + lane] = sk[lane];
             }
             wave_lds_sync();
         }
@@ -101,14 +110,12 @@ __global__ __launch_bounds__(kBuildThreads) void k_sketch(BuildArgs a) {
     }
 }
 
-// Exclusive scan of the partition histogram (one workgroup, P <= 256):
-// part_start[p] and the scatter cursors; part_start[P] = number of pairs.
-__global__ __launch_bounds__(kMaxParts) void k_scan_parts(const uint32_t* hist, uint32_t P,
-                                                          unsigned long long* part_start,
-                                                          unsigned long long* cursor) {
-    __shared__ unsigned long long wsum[kMaxParts / kWave];
+// Exclusive scan of one value per thread over a 256-thread workgroup; returns
+// the thread's exclusive prefix and sets total.
+__device__ __forceinline__ unsigned long long block_scan256(unsigned long long v,
+                                                            unsigned long long* wsum,
+                                                            unsigned long long& total) {
     const uint32_t t = threadIdx.x, lane = t & 63, w = t >> 6;
-    unsigned long long v = t < P ? hist[t] : 0ull;
     unsigned long long x = v;      // inclusive wave scan
 #pragma unroll
     for (int d = 1; d < kWave; d <<= 1) {
@@ -116,85 +123,193 @@ __global__ __launch_bounds__(kMaxParts) void k_scan_parts(const uint32_t* hist, 
         uint32_t hi = shfl_idx((uint32_t)(x >> 32), lane >= (uint32_t)d ? lane - d : lane);
         if (lane >= (uint32_t)d) x += ((unsigned long long)hi << 32) | lo;
     }
+    __syncthreads();
     if (lane == kWave - 1) wsum[w] = x;
     __syncthreads();
     unsigned long long base = 0;
     for (uint32_t i = 0; i < w; ++i) base += wsum[i];
-    unsigned long long excl = base + x - v;
-    if (t < P) {
-        part_start[t] = excl;
-        cursor[t] = excl;
-    }
-    if (t == kMaxParts - 1) part_start[P] = base + x;
+    total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    return base + x - v;
 }
 
-// Scatter the pairs into partition order (counting sort). A workgroup takes a
-// chunk of 4096 slots, sorts its pairs by partition in LDS, reserves one run
-// per partition with an atomic on that partition's cursor, and writes the
-// runs out contiguously.
+constexpr uint32_t kHistChunk = 65536;   // pairs per histogram chunk (slice mode)
 constexpr int kScatPer = 16;
-constexpr int kScatChunk = kBuildThreads * kScatPer;
+constexpr int kScatChunk = kBuildThreads * kScatPer;   // pairs per scatter chunk
 
-__global__ __launch_bounds__(kBuildThreads) void k_scatter(const unsigned long long* pairs,
-                                                           uint64_t n_slots, uint32_t bits,
-                                                           unsigned long long* cursor,
-                                                           unsigned long long* out) {
-    __shared__ unsigned long long buf[kScatChunk];
-    __shared__ uint8_t bpart[kScatChunk];
-    __shared__ uint32_t hist[kMaxParts], lstart[kMaxParts];
-    __shared__ unsigned long long gbase[kMaxParts];
-    __shared__ uint32_t wsum[kBuildThreads / kWave];
-    const uint32_t t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const uint32_t P = 1u << bits;
+// Exclusive scan of the partition histogram (one workgroup of 256 threads):
+// part_start[p] and the scatter cursors; part_start[P] = number of pairs. In
+// slice mode also the prefix of histogram and scatter chunks per partition
+// (chunks never straddle two partitions).
+__global__ __launch_bounds__(kMaxParts) void k_scan_parts(BuildArgs a) {
+    __shared__ unsigned long long wsum[kMaxParts / kWave];
+    const uint32_t t = threadIdx.x, P = a.n_parts;
+    const unsigned long long v = t < P ? a.hist[t] : 0ull;
+    unsigned long long total;
+    const unsigned long long excl = block_scan256(v, wsum, total);
+    if (t < P) {
+        a.part_start[t] = excl;
+        a.cursor[t] = excl;
+    }
+    if (t == 0) a.part_start[P] = total;
+    if (!a.slice_mode) return;
+    const unsigned long long ch = t < P ? (v + kHistChunk - 1) / kHistChunk : 0ull;
+    const unsigned long long cs = t < P ? (v + kScatChunk - 1) / kScatChunk : 0ull;
+    unsigned long long th, ts;
+    const unsigned long long eh = block_scan256(ch, wsum, th);
+    const unsigned long long es = block_scan256(cs, wsum, ts);
+    if (t < P) {
+        a.chunk_first[t] = eh;
+        a.chunk_first[kMaxParts + 1 + t] = es;
+    }
+    if (t == 0) {
+        a.chunk_first[P] = th;
+        a.chunk_first[kMaxParts + 1 + P] = ts;
+    }
+}
+
+struct ScatLds {
+    unsigned long long buf[kScatChunk];
+    uint8_t bin[kScatChunk];
+    uint32_t hist[256], lstart[256];
+    unsigned long long gbase[256];
+    unsigned long long wsum[kBuildThreads / kWave];
+};
+
+// Scatter in[c0, c1) (at most kScatChunk entries; kEmpty entries are
+// skipped) into 256 or fewer bins: the workgroup sorts its entries by bin in
+// LDS, reserves one run per bin with an atomic on that bin's cursor, and
+// writes the runs out contiguously (counting sort).
+template <typename BinOf>
+__device__ __forceinline__ void scatter_chunk(const unsigned long long* in, uint64_t c0,
+                                              uint64_t c1, BinOf bin_of,
+                                              unsigned long long* cursor,
+                                              unsigned long long* out, ScatLds& S) {
+    const uint32_t t = threadIdx.x;
+    S.hist[t] = 0;
+    __syncthreads();
+    unsigned long long e[kScatPer];
+    uint32_t pos[kScatPer], pb[kScatPer];
+#pragma unroll
+    for (int j = 0; j < kScatPer; ++j) {
+        const uint64_t i = c0 + (uint64_t)j * kBuildThreads + t;
+        e[j] = i < c1 ? in[i] : kEmpty;
+        pb[j] = 0;
+        pos[j] = 0;
+        if (e[j] != kEmpty) {
+            pb[j] = bin_of(e[j]);
+            pos[j] = atomicAdd(&S.hist[pb[j]], 1u);
+        }
+    }
+    __syncthreads();
+    const uint32_t v = S.hist[t];   // thread t owns bin t
+    unsigned long long total;
+    const uint32_t excl = (uint32_t)block_scan256(v, S.wsum, total);
+    S.lstart[t] = excl;
+    S.gbase[t] = v ? atomicAdd(&cursor[t], (unsigned long long)v) : 0ull;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kScatPer; ++j) {
+        if (e[j] != kEmpty) {
+            const uint32_t d = S.lstart[pb[j]] + pos[j];
+            S.buf[d] = e[j];
+            S.bin[d] = (uint8_t)pb[j];
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = t; i < (uint32_t)total; i += kBuildThreads) {
+        const uint32_t b = S.bin[i];
+        out[S.gbase[b] + (i - S.lstart[b])] = S.buf[i];
+    }
+    __syncthreads();
+}
+
+// Level 1: the per-window pairs into partition order (parted).
+__global__ __launch_bounds__(kBuildThreads) void k_scatter(BuildArgs a, uint64_t n_slots) {
+    __shared__ ScatLds S;
+    const uint64_t nb = a.nb;
+    const uint32_t sh = a.part_shift;
     for (uint64_t c0 = (uint64_t)blockIdx.x * kScatChunk; c0 < n_slots;
          c0 += (uint64_t)gridDim.x * kScatChunk) {
-        hist[t] = 0;
+        const uint64_t c1 = c0 + kScatChunk < n_slots ? c0 + kScatChunk : n_slots;
+        scatter_chunk(a.pairs, c0, c1,
+                      [=](unsigned long long e) { return part_of((uint32_t)(e >> 32), nb, sh); },
+                      a.cursor, a.parted, S);
+    }
+}
+
+// Partition of chunk ci of the prefix first[0..P] (first[P] = number of chunks).
+__device__ __forceinline__ uint32_t chunk_part(const unsigned long long* first, uint32_t P,
+                                               uint64_t ci) {
+    uint32_t lo = 0, hi = P;
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (first[mid] <= ci) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint32_t fine_of(unsigned long long e, uint64_t nb, uint32_t shift,
+                                            uint32_t mask) {
+    return (uint32_t)(home_bucket((uint32_t)(e >> 32), nb) >> shift) & mask;
+}
+
+// Slice mode, level 2 histogram: pairs per slice within each partition.
+__global__ __launch_bounds__(kBuildThreads) void k_hist2(BuildArgs a) {
+    __shared__ uint32_t h[256];
+    const uint32_t t = threadIdx.x, P = a.n_parts;
+    const uint32_t mask = (1u << a.fine_bits) - 1u;
+    const uint64_t n_chunks = a.chunk_first[P];
+    for (uint64_t ci = blockIdx.x; ci < n_chunks; ci += gridDim.x) {
+        const uint32_t p = chunk_part(a.chunk_first, P, ci);
+        const uint64_t c0 = a.part_start[p] + (ci - a.chunk_first[p]) * kHistChunk;
+        const uint64_t end = a.part_start[p + 1];
+        const uint64_t c1 = c0 + kHistChunk < end ? c0 + kHistChunk : end;
+        h[t] = 0;
         __syncthreads();
-        unsigned long long e[kScatPer];
-        uint32_t pos[kScatPer], pp[kScatPer];
-#pragma unroll
-        for (int j = 0; j < kScatPer; ++j) {
-            uint64_t i = c0 + (uint64_t)j * kBuildThreads + t;
-            e[j] = i < n_slots ? pairs[i] : kEmpty;
-            pp[j] = 0;
-            pos[j] = 0;
-            if (e[j] != kEmpty) {
-                pp[j] = part_of((uint32_t)(e[j] >> 32), bits);
-                pos[j] = atomicAdd(&hist[pp[j]], 1u);
-            }
-        }
+        for (uint64_t i = c0 + t; i < c1; i += kBuildThreads)
+            atomicAdd(&h[fine_of(a.parted[i], a.nb, a.slice_shift, mask)], 1u);
         __syncthreads();
-        // exclusive scan of hist (thread t owns partition t)
-        uint32_t v = t < P ? hist[t] : 0u, x = v;
-#pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) {
-            uint32_t y = shfl_idx(x, lane >= (uint32_t)d ? lane - d : lane);
-            if (lane >= (uint32_t)d) x += y;
-        }
-        if (lane == kWave - 1) wsum[w] = x;
+        if (t <= mask && h[t]) atomicAdd(&a.hist2[(p << a.fine_bits) + t], h[t]);
         __syncthreads();
-        uint32_t base = 0;
-        for (uint32_t i = 0; i < w; ++i) base += wsum[i];
-        const uint32_t total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
-        if (t < P) {
-            lstart[t] = base + x - v;
-            gbase[t] = v ? atomicAdd(&cursor[t], (unsigned long long)v) : 0ull;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < kScatPer; ++j) {
-            if (e[j] != kEmpty) {
-                uint32_t d = lstart[pp[j]] + pos[j];
-                buf[d] = e[j];
-                bpart[d] = (uint8_t)pp[j];
-            }
-        }
-        __syncthreads();
-        for (uint32_t i = t; i < total; i += kBuildThreads) {
-            uint32_t p = bpart[i];
-            out[gbase[p] + (i - lstart[p])] = buf[i];
-        }
-        __syncthreads();
+    }
+}
+
+// Slice mode: exclusive scan of the n_parts << fine_bits slice counts (one
+// workgroup, 256 consecutive slices per thread).
+__global__ __launch_bounds__(kBuildThreads) void k_scan2(BuildArgs a) {
+    __shared__ unsigned long long wsum[kBuildThreads / kWave];
+    const uint32_t t = threadIdx.x;
+    const uint32_t n = a.n_parts << a.fine_bits;
+    const uint32_t per = (n + kBuildThreads - 1) / kBuildThreads;
+    const uint32_t i0 = min(n, t * per), i1 = min(n, i0 + per);
+    unsigned long long sum = 0;
+    for (uint32_t i = i0; i < i1; ++i) sum += a.hist2[i];
+    unsigned long long total;
+    unsigned long long run = block_scan256(sum, wsum, total);
+    for (uint32_t i = i0; i < i1; ++i) {
+        a.slice_start[i] = run;
+        a.cursor2[i] = run;
+        run += a.hist2[i];
+    }
+    if (t == 0) a.slice_start[n] = total;
+}
+
+// Slice mode, level 2: parted (partition order) into slice order (pairs).
+__global__ __launch_bounds__(kBuildThreads) void k_scatter2(BuildArgs a) {
+    __shared__ ScatLds S;
+    const uint32_t P = a.n_parts;
+    const unsigned long long* first = a.chunk_first + kMaxParts + 1;
+    const uint64_t n_chunks = first[P];
+    const uint64_t nb = a.nb;
+    const uint32_t sh = a.slice_shift, mask = (1u << a.fine_bits) - 1u;
+    for (uint64_t ci = blockIdx.x; ci < n_chunks; ci += gridDim.x) {
+        const uint32_t p = chunk_part(first, P, ci);
+        const uint64_t c0 = a.part_start[p] + (ci - first[p]) * kScatChunk;
+        const uint64_t end = a.part_start[p + 1];
+        const uint64_t c1 = c0 + kScatChunk < end ? c0 + kScatChunk : end;
+        scatter_chunk(a.parted, c0, c1,
+                      [=](unsigned long long e) { return fine_of(e, nb, sh, mask); },
+                      a.cursor2 + ((uint64_t)p << a.fine_bits), a.pairs, S);
     }
 }
 
@@ -220,18 +335,50 @@ __device__ __forceinline__ uint64_t insert_one(unsigned long long* table, uint32
     return nb + 1;
 }
 
-// B5: insert the partition-ordered pairs, one entry per lane. A persistent
-// grid of resident workgroups takes the entries in order (entry = thread slot
-// + i * threads in the grid), so the threads in flight all work in one slice
-// of the table: its counters stay in L2 and its lines in the Infinity Cache.
-__global__ __launch_bounds__(kBuildThreads) void k_insert(BuildArgs a) {
-    __shared__ uint32_t red[3][kWavesPerBuild];
+// Adds a workgroup's insert statistics to the build counters.
+__device__ __forceinline__ void add_insert_stats(BuildArgs& a, uint32_t ins, uint32_t probe,
+                                                 uint32_t full, uint32_t* red) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const uint64_t n = a.part_start[1u << a.part_bits];
+#pragma unroll
+    for (int m = 1; m < kWave; m <<= 1) {
+        ins += shfl_xor(ins, m);
+        probe += shfl_xor(probe, m);
+        full += shfl_xor(full, m);
+    }
+    __syncthreads();
+    if (lane == 0) {
+        red[0 * kWavesPerBuild + wave] = ins;
+        red[1 * kWavesPerBuild + wave] = probe;
+        red[2 * kWavesPerBuild + wave] = full;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        uint32_t v = 0;
+        for (int w = 0; w < kWavesPerBuild; ++w) v += red[threadIdx.x * kWavesPerBuild + w];
+        const int idx[3] = {kCntInserted, kCntProbe, kCntFull};
+        if (v) atomicAdd(&a.counters[idx[threadIdx.x]], (unsigned long long)v);
+    }
+}
+
+__device__ __forceinline__ void push_candidate(BuildArgs& a, uint32_t f) {
+    unsigned long long c = atomicAdd(&a.counters[kCntCand], 1ull);
+    if (c < a.cand_cap) a.cand[c] = f;
+}
+
+// B5: insert src[0, *n) with the global bucket counters, one entry per lane.
+// A persistent grid of resident workgroups takes the entries in order (entry
+// = thread slot + i * threads in the grid); with partition-ordered entries
+// the threads in flight all work in one range of the table, whose counters
+// stay in L2 and lines in the Infinity Cache.
+__global__ __launch_bounds__(kBuildThreads) void k_insert(BuildArgs a,
+                                                          const unsigned long long* src,
+                                                          const unsigned long long* n_ptr) {
+    __shared__ uint32_t red[3 * kWavesPerBuild];
+    const uint64_t n = *n_ptr;
     uint32_t ins = 0, probe = 0, full = 0;
     const uint64_t step = (uint64_t)gridDim.x * kBuildThreads;
     for (uint64_t i = (uint64_t)blockIdx.x * kBuildThreads + threadIdx.x; i < n; i += step) {
-        const unsigned long long e = a.parted[i];
+        const unsigned long long e = src[i];
         const uint32_t f = (uint32_t)(e >> 32);
         const uint64_t d = insert_one(a.table, a.bcount, a.nb, home_bucket(f, a.nb), e);
         if (d > a.nb) {
@@ -240,29 +387,63 @@ __global__ __launch_bounds__(kBuildThreads) void k_insert(BuildArgs a) {
         }
         ins += 1;
         probe += (uint32_t)d;
-        if (d >= a.cap_dist) {
-            unsigned long long c = atomicAdd(&a.counters[kCntCand], 1ull);
-            if (c < a.cand_cap) a.cand[c] = f;
+        if (d >= a.cap_dist) push_candidate(a, f);
+    }
+    add_insert_stats(a, ins, probe, full, red);
+}
+
+// B5, slice mode: workgroup z inserts the pairs of slice z (buckets
+// [z << slice_shift, (z + 1) << slice_shift), the pairs in slice order), with
+// the slice's fill counters held in LDS; no other workgroup touches those
+// buckets meanwhile. The entry goes to the claimed slot of the global table as
+// with global counters. An entry whose chain runs past the end of its slice
+// is deferred to the global pass (k_insert), which runs once every slice has
+// stored its counters back.
+__global__ __launch_bounds__(kBuildThreads) void k_insert_slices(BuildArgs a) {
+    extern __shared__ uint32_t cnt[];     // 2^slice_shift counters
+    __shared__ uint32_t red[3 * kWavesPerBuild];
+    const uint32_t n_slices = a.n_parts << a.fine_bits;
+    const uint64_t sb = 1ull << a.slice_shift;
+    uint32_t ins = 0, probe = 0, full = 0;
+    for (uint32_t z = blockIdx.x; z < n_slices; z += gridDim.x) {
+        const uint64_t b0 = (uint64_t)z << a.slice_shift;
+        if (b0 >= a.nb) break;            // slices past the table are empty
+        const uint32_t nbk = (uint32_t)(b0 + sb <= a.nb ? sb : a.nb - b0);
+        const uint64_t p0 = a.slice_start[z], p1 = a.slice_start[z + 1];
+        if (p0 == p1) continue;
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < nbk; i += kBuildThreads) cnt[i] = a.bcount[b0 + i];
+        __syncthreads();
+        for (uint64_t i = p0 + threadIdx.x; i < p1; i += kBuildThreads) {
+            const unsigned long long e = a.pairs[i];
+            const uint32_t f = (uint32_t)(e >> 32);
+            const uint64_t home = home_bucket(f, a.nb);
+            uint32_t r = (uint32_t)(home - b0);   // bucket within the slice
+            bool done = false;
+            for (; r < nbk; ++r) {
+                if (cnt[r] < (uint32_t)kSlots) {
+                    const uint32_t pos = atomicAdd(&cnt[r], 1u);
+                    if (pos < (uint32_t)kSlots) {
+                        a.table[(b0 + r) * kSlots + pos] = e;
+                        done = true;
+                        break;
+                    }
+                }
+            }
+            if (done) {
+                const uint32_t d = r - (uint32_t)(home - b0);
+                ins += 1;
+                probe += d;
+                if (d >= a.cap_dist) push_candidate(a, f);
+            } else {
+                const unsigned long long q = atomicAdd(&a.counters[kCntDefer], 1ull);
+                a.parted[q] = e;
+            }
         }
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < nbk; i += kBuildThreads) a.bcount[b0 + i] = cnt[i];
     }
-#pragma unroll
-    for (int m = 1; m < kWave; m <<= 1) {
-        ins += shfl_xor(ins, m);
-        probe += shfl_xor(probe, m);
-        full += shfl_xor(full, m);
-    }
-    if (lane == 0) {
-        red[0][wave] = ins;
-        red[1][wave] = probe;
-        red[2][wave] = full;
-    }
-    __syncthreads();
-    if (threadIdx.x < 3) {
-        uint32_t v = 0;
-        for (int w = 0; w < kWavesPerBuild; ++w) v += red[threadIdx.x][w];
-        const int idx[3] = {kCntInserted, kCntProbe, kCntFull};
-        if (v) atomicAdd(&a.counters[idx[threadIdx.x]], (unsigned long long)v);
-    }
+    add_insert_stats(a, ins, probe, full, red);
 }
 
 // ---------------------------------------------------------------- cap -----
@@ -441,34 +622,62 @@ hipError_t launch_sketch(const BuildArgs& a, bool pairs, hipStream_t st) {
     return hipGetLastError();
 }
 
+bool slice_mode_fits(uint32_t slice_shift) { return slice_shift <= kMaxSliceShift; }
+
 hipError_t launch_partition(const BuildArgs& a, uint64_t n_slots, hipStream_t st) {
-    const uint32_t P = 1u << a.part_bits;
-    hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kMaxParts), 0, st, a.hist, P, a.part_start,
-                       a.cursor);
+    hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kMaxParts), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || n_slots == 0) return e;
     hipLaunchKernelGGL(k_scatter, dim3(grid_for(n_slots, kScatChunk, 8192)), dim3(kBuildThreads),
-                       0, st, (const unsigned long long*)a.pairs, n_slots, a.part_bits, a.cursor,
-                       a.parted);
+                       0, st, a, n_slots);
+    e = hipGetLastError();
+    if (e != hipSuccess || !a.slice_mode) return e;
+    const uint64_t pairs_bound = n_slots;   // chunks: at most one partial per partition
+    hipLaunchKernelGGL(k_hist2, dim3(grid_for(pairs_bound, kHistChunk, 4096) + a.n_parts),
+                       dim3(kBuildThreads), 0, st, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scan2, dim3(1), dim3(kBuildThreads), 0, st, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scatter2, dim3(grid_for(pairs_bound, kScatChunk, 8192)),
+                       dim3(kBuildThreads), 0, st, a);
     return hipGetLastError();
 }
+
+namespace {
+int resident_blocks(const void* kernel, size_t lds) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBuildThreads, lds) !=
+            hipSuccess || cus * per_cu <= 0)
+        return 2048;
+    return cus * per_cu;
+}
+}  // namespace
 
 hipError_t launch_insert(const BuildArgs& a, uint64_t max_items, hipStream_t st) {
     if (max_items == 0) return hipSuccess;
     static int resident = 0;   // workgroups of k_insert resident on the device at once
-    if (resident == 0) {
-        int dev = 0, cus = 0, per_cu = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_insert, kBuildThreads, 0) !=
-                hipSuccess || cus * per_cu <= 0)
-            resident = 2048;
-        else
-            resident = cus * per_cu;
+    if (resident == 0) resident = resident_blocks((const void*)k_insert, 0);
+    if (!a.slice_mode) {
+        uint64_t need = (max_items + kBuildThreads - 1) / kBuildThreads;
+        unsigned grid = (unsigned)std::min<uint64_t>(need, (uint64_t)resident);
+        hipLaunchKernelGGL(k_insert, dim3(grid), dim3(kBuildThreads), 0, st, a,
+                           (const unsigned long long*)a.parted,
+                           (const unsigned long long*)(a.part_start + a.n_parts));
+        return hipGetLastError();
     }
-    uint64_t need = (max_items + kBuildThreads - 1) / kBuildThreads;
-    unsigned grid = (unsigned)std::min<uint64_t>(need, (uint64_t)resident);
-    hipLaunchKernelGGL(k_insert, dim3(grid), dim3(kBuildThreads), 0, st, a);
+    const uint32_t n_slices = a.n_parts << a.fine_bits;
+    const size_t lds = ((size_t)1 << a.slice_shift) * sizeof(uint32_t);
+    hipLaunchKernelGGL(k_insert_slices, dim3(n_slices), dim3(kBuildThreads), lds, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // deferred entries (count known on the device only): a small persistent grid
+    hipLaunchKernelGGL(k_insert, dim3(std::min(resident, 1024)), dim3(kBuildThreads), 0, st, a,
+                       (const unsigned long long*)a.parted,
+                       (const unsigned long long*)(a.counters + kCntDefer));
     return hipGetLastError();
 }
 

@@ -297,21 +297,22 @@ __device__ __forceinline__ uint32_t select_distinct(const uint32_t (&v)[KPL], bo
     return n;
 }
 
-// Sketch of one window whose nk k-mer starts begin x0 bases after the first
-// staged word: h1 of each valid canonical k-mer, then the s smallest distinct.
-// scratch: 64 words of LDS owned by the wave.
-//
-// For windows of more than 64 k-mers the wave first keeps only hashes below a
-// threshold T chosen so that about 1.75 s of them are expected; if at least s
-// distinct values lie below T, the s smallest of the window are exactly the s
-// smallest of those candidates, which fit one per lane. Otherwise (fewer than
-// s distinct candidates, or more than 64) it sorts every hash of the window.
+// Hash threshold below which about `expect` of the nk hashes of a window are
+// expected (uniform hashes). Any value is correct: callers verify that enough
+// distinct candidates fell below it and otherwise take every hash.
+__device__ __forceinline__ uint32_t hash_threshold(float expect, uint32_t nk) {
+    const float t = expect * 4294967296.0f / (float)nk;
+    return t >= 4294967040.0f ? 0xFFFFFFFFu : (uint32_t)t;
+}
+
+// h1 of the canonical k-mers of one window whose nk k-mer starts begin x0
+// bases after the first staged word: key[r] belongs to k-mer r*64 + lane and is
+// 0xFFFFFFFF for an invalid k-mer or past nk. Returns whether some valid k-mer
+// hashed to 0xFFFFFFFF (that value then still counts as a distinct feature).
 template <int KPL>
-__device__ __forceinline__ uint32_t sketch_window(const Word* W, uint32_t x0, uint32_t nk,
-                                                  uint32_t k, uint32_t s, uint32_t* sk,
-                                                  uint32_t* scratch) {
+__device__ __forceinline__ bool window_keys(const Word* W, uint32_t x0, uint32_t nk, uint32_t k,
+                                            uint32_t (&key)[KPL]) {
     const int lane = lane_id();
-    uint32_t key[KPL];
     bool top = false;
 #pragma unroll
     for (int r = 0; r < KPL; ++r) {
@@ -326,11 +327,26 @@ __device__ __forceinline__ uint32_t sketch_window(const Word* W, uint32_t x0, ui
             }
         }
     }
+    return ballot(top) != 0;
+}
+
+// The s smallest distinct keys of one window (its nk keys as left by
+// window_keys) into sk[0..), ascending; returns their number. scratch: 64
+// words of LDS owned by the wave.
+//
+// For windows of more than 64 k-mers the wave first keeps only hashes below a
+// threshold chosen so that about 1.75 s of them are expected; if at least s
+// distinct values lie below it, the s smallest of the window are exactly the s
+// smallest of those candidates, which fit one per lane. Otherwise (fewer than
+// s distinct candidates, or more than 64) it sorts every hash of the window.
+template <int KPL>
+__device__ __forceinline__ uint32_t sketch_keys(uint32_t (&key)[KPL], uint32_t nk, bool has_top,
+                                                uint32_t s, uint32_t* sk, uint32_t* scratch) {
+    const int lane = lane_id();
     uint32_t distinct;
     if constexpr (KPL >= 2) {
         if (nk > (uint32_t)kWave) {
-            uint64_t t64 = ((uint64_t)(7u * s) << 32) / (4ull * nk);
-            const uint32_t T = t64 > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)t64;
+            const uint32_t T = hash_threshold(1.75f * (float)s, nk);
             uint64_t bal[KPL];
             uint32_t c = 0;
 #pragma unroll
@@ -353,9 +369,6 @@ __device__ __forceinline__ uint32_t sketch_window(const Word* W, uint32_t x0, ui
                 if (distinct >= s) return n;
             }
         }
-    }
-    bool has_top = ballot(top) != 0;
-    if constexpr (KPL >= 2) {
         if (nk <= (uint32_t)kWave) {   // one key per lane: a 64-wide sort suffices
             uint32_t v[1] = {key[0]};
             wave_sort<1>(v);
@@ -364,6 +377,142 @@ __device__ __forceinline__ uint32_t sketch_window(const Word* W, uint32_t x0, ui
     }
     wave_sort<KPL>(key);
     return select_distinct<KPL>(key, has_top, s, sk, distinct);
+}
+
+// Sketch of one window (B2-B4, Q2).
+template <int KPL>
+__device__ __forceinline__ uint32_t sketch_window(const Word* W, uint32_t x0, uint32_t nk,
+                                                  uint32_t k, uint32_t s, uint32_t* sk,
+                                                  uint32_t* scratch) {
+    uint32_t key[KPL];
+    const bool top = window_keys<KPL>(W, x0, nk, k, key);
+    return sketch_keys<KPL>(key, nk, top, s, sk, scratch);
+}
+
+// Out-of-line copy for rare paths, so that the hot loops stay small in the
+// instruction cache.
+template <int KPL>
+__device__ __attribute__((noinline)) uint32_t sketch_window_rare(const Word* W, uint32_t x0,
+                                                                 uint32_t nk, uint32_t k,
+                                                                 uint32_t s, uint32_t* sk,
+                                                                 uint32_t* scratch) {
+    return sketch_window<KPL>(W, x0, nk, k, s, sk, scratch);
+}
+
+// Ascending bitonic sort of each 32-lane half of the wave (one key per lane).
+__device__ __forceinline__ void wave_sort_halves(uint32_t& v) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int size = 2; size <= 32; size <<= 1) {
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            uint32_t o = xor_lanes_c(v, stride);
+            const bool asc = ((lane & 31) & size) == 0;
+            const bool lower = (lane & stride) == 0;
+            uint32_t lo = v < o ? v : o, hi = v < o ? o : v;
+            v = (asc == lower) ? lo : hi;
+        }
+    }
+}
+
+// Candidates of one window for a 32-entry half of scratch. A window of at
+// most 32 k-mers contributes all its keys (mode 0, exact). A longer one
+// contributes its keys below a threshold that about 1.5 s of them pass (mode
+// 1), valid only if at least s distinct values end up below it; if fewer than
+// s or more than 32 keys pass, it contributes nothing (mode 2) and is
+// sketched on its own. Returns the number of entries written.
+template <int KPL>
+__device__ __forceinline__ uint32_t half_candidates(const uint32_t (&key)[KPL], uint32_t nk,
+                                                    uint32_t s, uint32_t* half, int& mode) {
+    const int lane = lane_id();
+    if (nk <= 32u) {
+        if (lane < 32) half[lane] = key[0];
+        mode = 0;
+        return 32u;
+    }
+    const uint32_t T = hash_threshold(1.5f * (float)s, nk);
+    uint64_t bal[KPL];
+    uint32_t c = 0;
+#pragma unroll
+    for (int r = 0; r < KPL; ++r) {
+        bal[r] = ballot(key[r] < T);
+        c += popc64(bal[r]);
+    }
+    if (c < s || c > 32u) {
+        mode = 2;
+        return 0u;
+    }
+    uint32_t base = 0;
+#pragma unroll
+    for (int r = 0; r < KPL; ++r) {
+        if (key[r] < T) half[rank_below(bal[r], base)] = key[r];
+        base += popc64(bal[r]);
+    }
+    mode = 1;
+    return c;
+}
+
+// Sketches of two windows A and B (either may be empty, nk = 0) at once: the
+// candidates of A fill lanes 0..31 and those of B lanes 32..63, one 32-wide
+// sort orders both halves, and one ballot ranks the distinct values of both.
+// A window whose candidates do not decide its sketch is redone alone (its
+// staged words must still be in place). Writes
+// skA[0..nA) and skB[0..nB). scratch: 64 words of LDS owned by the wave.
+template <int KPL>
+__device__ __forceinline__ void sketch_pair(const Word* WA, uint32_t xA, uint32_t nkA,
+                                            const Word* WB, uint32_t xB, uint32_t nkB,
+                                            uint32_t k, uint32_t s, uint32_t* skA, uint32_t* skB,
+                                            uint32_t* scratch, uint32_t& nA, uint32_t& nB) {
+    const int lane = lane_id();
+    int modeA, modeB;
+    uint32_t cA, cB;
+    bool topA, topB;
+    {
+        uint32_t key[KPL];
+        topA = window_keys<KPL>(WA, xA, nkA, k, key);
+        cA = half_candidates<KPL>(key, nkA, s, scratch, modeA);
+        topB = window_keys<KPL>(WB, xB, nkB, k, key);
+        cB = half_candidates<KPL>(key, nkB, s, scratch + 32, modeB);
+    }
+    wave_lds_sync();
+    const uint32_t hl = (uint32_t)lane & 31u;
+    uint32_t v = hl < (lane < 32 ? cA : cB) ? scratch[lane] : 0xFFFFFFFFu;
+    wave_lds_sync();
+    wave_sort_halves(v);
+    // previous lane's key (whole-wave shift right by one lane)
+    const uint32_t prev = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x138, 0xF, 0xF, false);
+    const bool first = v != 0xFFFFFFFFu && (hl == 0 || v != prev);
+    const uint64_t bal = ballot(first);
+    const uint32_t dA = popc64(bal & 0xFFFFFFFFull), dB = popc64(bal >> 32);
+    const bool okA = modeA == 0 || (modeA == 1 && dA >= s);
+    const bool okB = modeB == 0 || (modeB == 1 && dB >= s);
+    const uint32_t rank = rank_below(bal) - (lane < 32 ? 0u : dA);
+    if (first && rank < s) {
+        if (lane < 32) {
+            if (okA) skA[rank] = v;
+        } else if (okB) {
+            skB[rank] = v;
+        }
+    }
+    nA = dA < s ? dA : s;
+    nB = dB < s ? dB : s;
+    if (okA && topA && dA < s) {
+        if (lane == 0) skA[dA] = 0xFFFFFFFFu;
+        nA = dA + 1;
+    }
+    if (okB && topB && dB < s) {
+        if (lane == 0) skB[dB] = 0xFFFFFFFFu;
+        nB = dB + 1;
+    }
+    // rare: the keys of an undecided window are recomputed from the staged words
+    if (!okA) {
+        wave_lds_sync();
+        nA = sketch_window_rare<KPL>(WA, xA, nkA, k, s, skA, scratch);
+    }
+    if (!okB) {
+        wave_lds_sync();
+        nB = sketch_window_rare<KPL>(WB, xB, nkB, k, s, skB, scratch);
+    }
 }
 
 // Stage the bytes [lo, hi) into words relative to A0 = lo & ~15, one word per

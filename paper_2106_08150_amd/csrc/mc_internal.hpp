@@ -27,6 +27,7 @@ enum BuildCounter {
     kCntCand = 2,        // cap candidates pushed (may exceed the list capacity)
     kCntFull = 3,        // inserts that found no free slot
     kCntMoved = 4,       // entries re-inserted by a rehash
+    kCntDefer = 5,       // slice-local inserts whose chain ran past their slice
     kNumBuildCounters = 8
 };
 
@@ -52,11 +53,27 @@ struct BuildArgs {
     // pair mode: per-window pairs, their partition histogram, partitioned copy
     unsigned long long* pairs;          // n_windows * s slots
     unsigned long long* parted;         // pairs in partition order
-    uint32_t part_bits;                 // 2^part_bits table partitions (<= 8)
-    uint32_t* hist;                     // 2^part_bits counters
-    unsigned long long* part_start;     // 2^part_bits + 1 offsets
-    unsigned long long* cursor;         // 2^part_bits scatter cursors
+    uint32_t part_shift;                // partition of a pair: home bucket >> part_shift
+    uint32_t n_parts;                   // partitions (<= kMaxParts)
+    uint32_t* hist;                     // n_parts counters
+    unsigned long long* part_start;     // n_parts + 1 offsets
+    unsigned long long* cursor;         // n_parts scatter cursors
+    // slice mode: partitions split into 2^fine_bits slices of 2^slice_shift
+    // buckets each; a workgroup inserts one slice's pairs with LDS counters
+    uint32_t slice_mode;
+    uint32_t slice_shift;
+    uint32_t fine_bits;                 // part_shift = slice_shift + fine_bits
+    uint32_t* hist2;                    // n_parts << fine_bits counters
+    unsigned long long* slice_start;    // (n_parts << fine_bits) + 1 offsets
+    unsigned long long* cursor2;        // n_parts << fine_bits scatter cursors
+    unsigned long long* chunk_first;    // [0, n_parts]: prefix of histogram chunks per
+                                        // partition; [kMaxParts + 1, ...]: scatter chunks
 };
+
+constexpr uint32_t kMaxParts = 256;         // partitions (8 bits)
+constexpr uint32_t kMaxSliceShift = 13;     // slice of at most 8192 buckets (32 KiB counters)
+constexpr uint32_t kMinSliceShift = 10;
+constexpr uint32_t kMaxSlices = 65536;      // kMaxParts << 8
 
 constexpr int kTileWindows = 32;  // windows per build workgroup tile
 constexpr int kBuildThreads = 256;
@@ -100,6 +117,7 @@ constexpr uint32_t kMaxTopM = 8;
 hipError_t launch_sketch(const BuildArgs& a, bool pairs, hipStream_t st);
 hipError_t launch_partition(const BuildArgs& a, uint64_t n_slots, hipStream_t st);
 hipError_t launch_insert(const BuildArgs& a, uint64_t max_items, hipStream_t st);
+bool slice_mode_fits(uint32_t slice_shift);
 hipError_t launch_cap_finalize(unsigned long long* table, uint64_t nb, uint32_t cap,
                                const uint32_t* cand, uint64_t n_cand, hipStream_t st);
 hipError_t launch_cap_scan(unsigned long long* table, uint64_t nb, uint32_t cap,

@@ -12,14 +12,14 @@ namespace mc {
 
 namespace {
 
-constexpr int kStageWords = 20;    // one window of at most 271 bases
+constexpr int kStageWords = 20;    // one window of at most 271 bases (19 words)
 constexpr uint32_t kMaxFeat = 128; // sketch elements buffered before lookups
 
 constexpr uint32_t kRing = kMaxFeat;   // lookup work items: at most one per feature
 
 template <uint32_t LCAP>
 struct QueryLds {
-    Word stage[kStageWords];
+    Word stage[2 * kStageWords];
     uint32_t scratch[kWave];
     uint32_t feats[kMaxFeat];
     uint2 ring[kRing];                // (feature, bucket) lookup work items
@@ -174,6 +174,43 @@ __device__ __forceinline__ void write_result(const QueryArgs& a, uint32_t rec, u
     }
 }
 
+// One window of a record: its bytes [lo, hi) inside the mate [vlo, vhi), its
+// number of k-mer starts and the offset of its first base in the staged words.
+struct WinRef {
+    uintptr_t lo, hi, vlo, vhi;
+    uint32_t nk, x0;
+};
+
+// Window i of the record (mate 1's windows first); i >= nwt gives an empty one.
+__device__ __forceinline__ WinRef window_ref(const QueryArgs& a, uint64_t i, uint64_t nwt,
+                                             uint64_t nw0, uint64_t o0, uint64_t o1,
+                                             const uint64_t (&len)[2]) {
+    WinRef r{0, 0, 0, 0, 0u, 0u};
+    if (i >= nwt) return r;
+    const int sg = i < nw0 ? 0 : 1;
+    const uint64_t j = sg ? i - nw0 : i;
+    r.vlo = (uintptr_t)(a.reads + (sg ? o1 : o0));
+    r.vhi = r.vlo + len[sg];
+    r.lo = r.vlo + j * a.S;
+    r.hi = r.lo + a.w < r.vhi ? r.lo + a.w : r.vhi;
+    const uint64_t n_starts = len[sg] - a.k + 1;
+    r.nk = (uint32_t)min((uint64_t)a.S, n_starts - j * a.S);
+    r.x0 = (uint32_t)(r.lo & 15u);
+    return r;
+}
+
+// Stage two windows at once: lanes 0..kStageWords-1 take the words of A into
+// W[0..), the next kStageWords lanes those of B into W[kStageWords..).
+__device__ __forceinline__ void stage_pair(Word* W, const WinRef& A, const WinRef& B, int lane) {
+    const bool second = lane >= kStageWords;
+    const WinRef& r = second ? B : A;
+    const int q = second ? lane - kStageWords : lane;
+    if (r.nk == 0 || q >= kStageWords) return;
+    const uintptr_t A0 = r.lo & ~(uintptr_t)15;
+    const int nw = (int)((r.hi - A0 + 15) / 16) + 1;
+    if (q < nw) W[lane] = load_word(A0 + 16 * (uintptr_t)q, r.vlo, r.vhi);
+}
+
 struct WaveStats {
     uint32_t features = 0, locations = 0, probes = 0;
 };
@@ -198,36 +235,37 @@ __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>
     if (len[0] > 0 && len[1] > 0 && a.insert_size > F) F = a.insert_size;
     const uint32_t sws = F < a.k ? 1u : (uint32_t)((F - a.k + a.S - 1) / a.S + 1);
 
+    // windows of the record, mate 1's then mate 2's, sketched two at a time
+    uint64_t nws[2];
+    for (int sg = 0; sg < 2; ++sg)
+        nws[sg] = len[sg] < a.k ? 0 : (len[sg] - a.k + 1 + a.S - 1) / a.S;
+    const uint64_t nwt = nws[0] + nws[1];
     uint32_t nlist = 0, nf = 0;
     bool fits = true;
-    for (int sg = 0; sg < 2 && fits; ++sg) {
-        const uint64_t L0 = len[sg];
-        if (L0 < a.k) continue;
-        const uintptr_t p0 = (uintptr_t)(a.reads + (sg ? o1 : o0));
-        const uintptr_t p1 = p0 + L0;
-        const uint64_t n_starts = L0 - a.k + 1;
-        const uint64_t nw = (n_starts + a.S - 1) / a.S;
-        for (uint64_t j = 0; j < nw && fits; ++j) {
-            const uintptr_t lo = p0 + j * a.S;
-            uintptr_t hi = lo + a.w;
-            if (hi > p1) hi = p1;
+    for (uint64_t p = 0; p < nwt && fits; p += 2) {
+        WinRef wr[2];
+        for (int h = 0; h < 2; ++h) wr[h] = window_ref(a, p + h, nwt, nws[0], o0, o1, len);
+        wave_lds_sync();
+        stage_pair(L.stage, wr[0], wr[1], lane);
+        wave_lds_sync();
+        uint32_t nA, nB;
+        sketch_pair<KPL>(L.stage, wr[0].x0, wr[0].nk, L.stage + kStageWords, wr[1].x0, wr[1].nk,
+                         a.k, a.s, L.feats + nf, L.feats + nf + a.s, L.scratch, nA, nB);
+        wave_lds_sync();
+        if (nA < a.s && nB) {      // close the gap after A's features
+            const uint32_t f = (uint32_t)lane < nB ? L.feats[nf + a.s + lane] : 0u;
             wave_lds_sync();
-            stage_words(L.stage, lo, hi, p0, p1, lane, kWave);
+            if ((uint32_t)lane < nB) L.feats[nf + nA + lane] = f;
             wave_lds_sync();
-            const uint32_t nk = (uint32_t)min((uint64_t)a.S, n_starts - j * a.S);
-            const uint32_t x0 = (uint32_t)(lo & 15u);
-            nf += sketch_window<KPL>(L.stage, x0, nk, a.k, a.s, L.feats + nf, L.scratch);
-            wave_lds_sync();
-            if (nf + a.s > kMaxFeat) {
-                ws.features += nf;
-                fits = lookup<LCAP>(a, L.feats, nf, L.ring, L.list, nlist, ws.probes);
-                nf = 0;
-            }
         }
-    }
-    if (fits && nf) {
-        ws.features += nf;
-        fits = lookup<LCAP>(a, L.feats, nf, L.ring, L.list, nlist, ws.probes);
+        nf += nA + nB;
+        // look up the buffered features after the last pair or before the
+        // buffer could overflow (one call site keeps the loop compact)
+        if (nf && (p + 2 >= nwt || nf + 2 * a.s > kMaxFeat)) {
+            ws.features += nf;
+            fits = lookup<LCAP>(a, L.feats, nf, L.ring, L.list, nlist, ws.probes);
+            nf = 0;
+        }
     }
     if (!fits) {
         if (!big) {
