@@ -507,12 +507,15 @@ __device__ __forceinline__ void sketch_pair(const Word* WA, uint32_t xA, uint32_
     // rare: the keys of an undecided window are recomputed from the staged words
     if (!okA) {
         wave_lds_sync();
-        nA = sketch_window_rare<KPL>(WA, xA, nkA, k, s, skA, scratch);
+        nA = uniform(sketch_window_rare<KPL>(WA, xA, nkA, k, s, skA, scratch));
     }
     if (!okB) {
         wave_lds_sync();
-        nB = sketch_window_rare<KPL>(WB, xB, nkB, k, s, skB, scratch);
+        nB = uniform(sketch_window_rare<KPL>(WB, xB, nkB, k, s, skB, scratch));
     }
+    // the counts are wave-uniform; saying so keeps the callers' loops scalar
+    nA = uniform(nA);
+    nB = uniform(nB);
 }
 
 // Stage the bytes [lo, hi) into words relative to A0 = lo & ~15, one word per

@@ -58,6 +58,10 @@ __device__ bool lookup(const QueryArgs& a, const uint32_t* F, uint32_t nf, uint2
     const unsigned long long* slot = a.table + (lane & 15u);
     uint32_t head = 0, tail = nf;
     while (head < tail) {
+        // every line issued so far has been used; saying so here lets this
+        // batch's loads go out back to back (the compiler cannot tell which
+        // of the previous batch's loads were issued)
+        __builtin_amdgcn_s_waitcnt(kWaitVmem0);
         const uint32_t c = min(tail - head, 4u * NB);
         uint32_t f[NB], b[NB];
         uint64_t sl[NB];
@@ -95,9 +99,6 @@ __device__ bool lookup(const QueryArgs& a, const uint32_t* F, uint32_t nf, uint2
                 tail += popc64(full);
             }
         }
-        // every issued line has been used by now; saying so lets the next
-        // batch's loads go out without waiting on the lines of unused groups
-        __builtin_amdgcn_s_waitcnt(kWaitVmem0);
         wave_lds_sync();
     }
     return true;
