@@ -56,6 +56,24 @@ def parse():
     return ap.parse_args()
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE / WRITE_SIZE counters
+    (scaled by the copy-kernel calibration), or None if they were taken on other sources."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_k_classify_scale_10M_reads.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel") != kernel:
+        return None
+    h = hashlib.sha256()
+    for name in t["sources"]:
+        with open(os.path.join(ROOT, "paper_2106_08150_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return t["traffic_bytes"] if h.hexdigest() == t["sources_sha256"] else None
+
+
 def cpu_baseline(g, reads, n_sample, threads, gpu_labels):
     """Oracle timing on a read sample: the oracle indexes only the features the
     sample looks up (exact for the sample), then classifies it."""
@@ -353,10 +371,13 @@ def main():
         "sketch": {"name": "k_sketch<2,true>", "avg_ms": avg_ms("sketch"),
                    "algorithmic_bytes": total_bp + 8.0 * slots,
                    "per_unit": "1 B of text per base read + 8 B per sketch slot written"},
-        "scatter": {"name": "k_scan_parts + k_scatter", "avg_ms": avg_ms("scatter"),
-                    "algorithmic_bytes": 8.0 * slots + 8.0 * pairs,
-                    "per_unit": "8 B per slot read + 8 B per pair written"},
-        "insert": {"name": "k_insert", "avg_ms": avg_ms("insert"),
+        "scatter": {"name": "k_scan_parts + k_scatter + k_hist2 + k_scan2 + k_scatter2",
+                    "avg_ms": avg_ms("scatter"),
+                    "algorithmic_bytes": 8.0 * slots + 8.0 * pairs + 24.0 * pairs,
+                    "per_unit": ("8 B per slot read + 8 B per pair written (partitions), 8 B per "
+                                 "pair read (slice histogram), 8 B read + 8 B written per pair "
+                                 "(slices)")},
+        "insert": {"name": "k_insert_slices + k_insert (deferred)", "avg_ms": avg_ms("insert"),
                    "algorithmic_bytes": 16.0 * pairs,
                    "per_unit": "8 B per pair read + 8 B per pair stored"},
         "classify": {"name": "k_classify<512,4,2>", "avg_ms": avg_ms("classify"),
@@ -372,7 +393,7 @@ def main():
     achieved = dom["achieved_gbs"]
     roofline = {"bound": "hbm", "kernel": dom["name"], "achieved": achieved,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                "traffic": None}
+                "traffic": measured_traffic(dom["name"])}
 
     out = {
         "metric": METRIC,
