@@ -201,7 +201,9 @@ __device__ __forceinline__ Word encode16(uint32_t x0, uint32_t x1, uint32_t x2, 
 // overlap is not read at all.
 __device__ __forceinline__ Word load_word(uintptr_t a, uintptr_t vlo, uintptr_t vhi) {
     if (a + 16 <= vlo || a >= vhi) return Word{0u, 0xFFFFu};
-    uint4 v = *reinterpret_cast<const uint4*>(a);
+    // the address is global memory; saying so gives a global (not flat) load
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4 v = *reinterpret_cast<const __attribute__((address_space(1))) u32x4*>(a);
     Word w = encode16(v.x, v.y, v.z, v.w);
     // bytes [lo, hi) of the word lie inside [vlo, vhi)
     const uint32_t lo = vlo > a ? (uint32_t)(vlo - a) : 0u;
@@ -390,13 +392,23 @@ __device__ __forceinline__ uint32_t sketch_window(const Word* W, uint32_t x0, ui
 }
 
 // Out-of-line copy for rare paths, so that the hot loops stay small in the
-// instruction cache.
+// instruction cache. Its pointers are LDS pointers (address space 3), so that
+// the out-of-line code still uses LDS instructions rather than flat ones.
+#define MC_LDS __attribute__((address_space(3)))
 template <int KPL>
-__device__ __attribute__((noinline)) uint32_t sketch_window_rare(const Word* W, uint32_t x0,
-                                                                 uint32_t nk, uint32_t k,
-                                                                 uint32_t s, uint32_t* sk,
-                                                                 uint32_t* scratch) {
-    return sketch_window<KPL>(W, x0, nk, k, s, sk, scratch);
+__device__ __attribute__((noinline)) uint32_t sketch_window_lds(const MC_LDS Word* W, uint32_t x0,
+                                                                uint32_t nk, uint32_t k,
+                                                                uint32_t s, MC_LDS uint32_t* sk,
+                                                                MC_LDS uint32_t* scratch) {
+    return sketch_window<KPL>((const Word*)W, x0, nk, k, s, (uint32_t*)sk, (uint32_t*)scratch);
+}
+
+template <int KPL>
+__device__ __forceinline__ uint32_t sketch_window_rare(const Word* W, uint32_t x0, uint32_t nk,
+                                                       uint32_t k, uint32_t s, uint32_t* sk,
+                                                       uint32_t* scratch) {
+    return sketch_window_lds<KPL>((const MC_LDS Word*)W, x0, nk, k, s, (MC_LDS uint32_t*)sk,
+                                  (MC_LDS uint32_t*)scratch);
 }
 
 // Ascending bitonic sort of each 32-lane half of the wave (one key per lane).
@@ -456,7 +468,7 @@ __device__ __forceinline__ uint32_t half_candidates(const uint32_t (&key)[KPL], 
 // candidates of A fill lanes 0..31 and those of B lanes 32..63, one 32-wide
 // sort orders both halves, and one ballot ranks the distinct values of both.
 // A window whose candidates do not decide its sketch is redone alone (its
-// staged words must still be in place). Writes
+// staged words must still be in place). All pointers are to LDS. Writes
 // skA[0..nA) and skB[0..nB). scratch: 64 words of LDS owned by the wave.
 template <int KPL>
 __device__ __forceinline__ void sketch_pair(const Word* WA, uint32_t xA, uint32_t nkA,

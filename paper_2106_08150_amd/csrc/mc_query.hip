@@ -146,18 +146,27 @@ __device__ void sort_lds(uint32_t* list, uint32_t n, uint32_t P) {
     }
 }
 
+// Lists of more than 128 locations: out of line, with an LDS pointer so that
+// the out-of-line code keeps LDS instructions.
 template <uint32_t LCAP>
-__device__ void sort_list(uint32_t* list, uint32_t n) {
-    uint32_t P = 64;
+__device__ __attribute__((noinline)) void sort_list_long(MC_LDS uint32_t* lds_list, uint32_t n) {
+    uint32_t* list = (uint32_t*)lds_list;
+    uint32_t P = 256;
     while (P < n) P <<= 1;
     switch (P) {
-        case 64: sort_regs<1>(list, n); break;
-        case 128: sort_regs<2>(list, n); break;
         case 256: sort_regs<4>(list, n); break;
         case 512: sort_regs<8>(list, n); break;
         case 1024: if (LCAP >= 1024) sort_regs<16>(list, n); break;
         default: sort_lds(list, n, P); break;
     }
+}
+
+// Ascending sort of list[0..n) in LDS.
+template <uint32_t LCAP>
+__device__ __forceinline__ void sort_list(uint32_t* list, uint32_t n) {
+    if (n <= 64) sort_regs<1>(list, n);
+    else if (n <= 128) sort_regs<2>(list, n);
+    else sort_list_long<LCAP>((MC_LDS uint32_t*)list, n);
 }
 
 // Label and top-m list of a record (lane x writes the x-th top hit).
