@@ -154,44 +154,41 @@ __device__ __forceinline__ uint64_t next_bucket(uint64_t b, uint64_t nb) {
 }
 
 // ------------------------------------------------------------- encoding --
-// 16 bases packed as 2-bit codes (first base in bits 31..30) plus a 16-bit
-// invalid mask (first base in bit 15). A=0 C=1 G=2 T=3, case-insensitive;
-// every other byte is invalid.
+// 16 bases packed as 2-bit codes (first base in bits 31..30) plus an invalid
+// mask with the same layout (0b11 in the two bits of every invalid base).
+// A=0 C=1 G=2 T=3, case-insensitive; every other byte is invalid.
 struct Word {
     uint32_t code;
     uint32_t mask;
 };
 
-__device__ __forceinline__ uint32_t zero_bytes(uint32_t y) {   // 0x80 where byte == 0
-    uint32_t t = (y & 0x7F7F7F7Fu) + 0x7F7F7F7Fu;
-    return ~(t | y | 0x7F7F7F7Fu);
+// Four 2-bit fields held in bits 8i..8i+1 (i = byte) packed into one byte,
+// byte 0's field in bits 7..6: reverse the bytes, then fold pairs twice.
+__device__ __forceinline__ uint32_t pack_fields(uint32_t v) {
+    const uint32_t r = __builtin_amdgcn_perm(0u, v, 0x00010203u);
+    const uint32_t t = r | (r >> 6);
+    return (t | (t >> 12)) & 0xFFu;
 }
 
-// Encode 4 ASCII bytes (byte 0 = first base): 8 code bits and 4 mask bits.
-__device__ __forceinline__ void encode4(uint32_t x, uint32_t& c8, uint32_t& m4) {
-    uint32_t l = x | 0x20202020u;
-    uint32_t ok = zero_bytes(l ^ 0x61616161u) | zero_bytes(l ^ 0x63636363u) |
-                  zero_bytes(l ^ 0x67676767u) | zero_bytes(l ^ 0x74747474u);
-    uint32_t g = (l >> 1) & 0x03030303u;          // a0 c1 g3 t2
-    uint32_t cd = g ^ ((g >> 1) & 0x01010101u);    // a0 c1 g2 t3
-    cd &= (ok >> 7) * 3u;
-    c8 = ((cd & 0xFFu) << 6) | (((cd >> 8) & 0xFFu) << 4) | (((cd >> 16) & 0xFFu) << 2) |
-         (cd >> 24);
-    uint32_t bad = ~ok & 0x80808080u;
-    m4 = (((bad >> 7) & 1u) << 3) | (((bad >> 15) & 1u) << 2) | (((bad >> 23) & 1u) << 1) |
-         (bad >> 31);
+// Encode 4 ASCII bytes x (byte 0 = first base); ok: 0x80 in each byte that
+// lies inside the sequence. Bits 1..2 of a letter give its code,
+// ((x >> 1) ^ (x >> 2)) & 3 maps A/a C/c G/g T/t to 0 1 2 3; a byte is a base
+// iff it equals "acgt"[code] once lower-cased (v_perm looks the letter up).
+// c8: the 4 codes (those of invalid bases are arbitrary), first base in bits
+// 7..6; m8: 0b11 in the positions of invalid bases.
+__device__ __forceinline__ void encode4(uint32_t x, uint32_t ok, uint32_t& c8, uint32_t& m8) {
+    const uint32_t c = ((x >> 1) ^ (x >> 2)) & 0x03030303u;
+    const uint32_t expect = __builtin_amdgcn_perm(0u, 0x74676361u, c);
+    const uint32_t diff = (x | 0x20202020u) ^ expect;           // zero byte: a base
+    const uint32_t t = (diff & 0x7F7F7F7Fu) + 0x7F7F7F7Fu;
+    const uint32_t inv = (t | diff | ~ok) & 0x80808080u;         // 0x80 per invalid base
+    c8 = pack_fields(c);
+    m8 = pack_fields((inv >> 6) | (inv >> 7));
 }
 
-__device__ __forceinline__ Word encode16(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3) {
-    uint32_t c0, c1, c2, c3, m0, m1, m2, m3;
-    encode4(x0, c0, m0);
-    encode4(x1, c1, m1);
-    encode4(x2, c2, m2);
-    encode4(x3, c3, m3);
-    Word w;
-    w.code = (c0 << 24) | (c1 << 16) | (c2 << 8) | c3;
-    w.mask = (m0 << 12) | (m1 << 8) | (m2 << 4) | m3;
-    return w;
+// 0x80 in the bytes [lo, hi) of a dword (0 <= lo < hi <= 4).
+__device__ __forceinline__ uint32_t inside_bytes(uint32_t lo, uint32_t hi) {
+    return (0x80808080u << (8 * lo)) & (0x80808080u >> (8 * (4 - hi)));
 }
 
 // Word covering absolute bytes [a, a+16), a 16-byte aligned. Bytes outside
@@ -200,17 +197,45 @@ __device__ __forceinline__ Word encode16(uint32_t x0, uint32_t x1, uint32_t x2, 
 // in the same mapped page as the valid byte it contains. A word that does not
 // overlap is not read at all.
 __device__ __forceinline__ Word load_word(uintptr_t a, uintptr_t vlo, uintptr_t vhi) {
-    if (a + 16 <= vlo || a >= vhi) return Word{0u, 0xFFFFu};
+    if (a + 16 <= vlo || a >= vhi) return Word{0u, 0xFFFFFFFFu};
     // the address is global memory; saying so gives a global (not flat) load
     typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
     const u32x4 v = *reinterpret_cast<const __attribute__((address_space(1))) u32x4*>(a);
-    Word w = encode16(v.x, v.y, v.z, v.w);
     // bytes [lo, hi) of the word lie inside [vlo, vhi)
     const uint32_t lo = vlo > a ? (uint32_t)(vlo - a) : 0u;
     const uint32_t hi = vhi - a < 16 ? (uint32_t)(vhi - a) : 16u;
-    const uint32_t inside = ((0xFFFFu >> lo) & (0xFFFFu << (16 - hi))) & 0xFFFFu;
-    w.mask |= ~inside & 0xFFFFu;
+    uint32_t c[4], m[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t dlo = lo > 4u * i ? min(lo - 4u * i, 4u) : 0u;
+        const uint32_t dhi = hi > 4u * i ? min(hi - 4u * i, 4u) : 0u;
+        const uint32_t ok = dlo < dhi ? inside_bytes(dlo, dhi) : 0u;
+        encode4(i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w, ok, c[i], m[i]);
+    }
+    Word w;
+    w.code = (c[0] << 24) | (c[1] << 16) | (c[2] << 8) | c[3];
+    w.mask = (m[0] << 24) | (m[1] << 16) | (m[2] << 8) | m[3];
     return w;
+}
+
+// Stage one dword (4 bases) of a word covering [A0, ...), A0 16-byte aligned:
+// dword d of word d >> 2 goes to byte 3 - (d & 3) of that word's code and mask
+// (first base in the top byte). Bytes outside [vlo, vhi) count as invalid; a
+// dword that does not overlap them is not read. Aligned 4-byte loads never
+// cross a page.
+__device__ __forceinline__ void stage_dword(Word* W, uintptr_t A0, uint32_t d, uintptr_t vlo,
+                                            uintptr_t vhi) {
+    const uintptr_t a = A0 + 4u * d;
+    uint32_t c8 = 0u, m8 = 0xFFu;
+    if (a + 4 > vlo && a < vhi) {
+        const uint32_t x = *reinterpret_cast<const __attribute__((address_space(1))) uint32_t*>(a);
+        const uint32_t lo = vlo > a ? (uint32_t)(vlo - a) : 0u;
+        const uint32_t hi = vhi - a < 4 ? (uint32_t)(vhi - a) : 4u;
+        encode4(x, inside_bytes(lo, hi), c8, m8);
+    }
+    uint8_t* w = reinterpret_cast<uint8_t*>(W + (d >> 2));
+    w[3 - (d & 3u)] = (uint8_t)c8;
+    w[7 - (d & 3u)] = (uint8_t)m8;
 }
 
 // Canonical k-mer starting x bases after the first staged word (k <= 16).
@@ -220,8 +245,8 @@ __device__ __forceinline__ bool kmer_at(const Word* W, uint32_t x, uint32_t k, u
     Word a = W[q], b = W[q + 1];
     uint64_t v = ((uint64_t)a.code << 32) | b.code;
     uint32_t fwd = (uint32_t)((v << (2 * o)) >> (64 - 2 * k));
-    uint32_t m = (a.mask << 16) | b.mask;
-    bool bad = ((m << o) >> (32 - k)) != 0u;
+    uint64_t mv = ((uint64_t)a.mask << 32) | b.mask;
+    bool bad = ((mv << (2 * o)) >> (64 - 2 * k)) != 0ull;
     // reverse complement: complement, align to the top, reverse 2-bit groups
     uint32_t r = __builtin_bitreverse32((~fwd) << (32 - 2 * k));
     r = ((r >> 1) & 0x55555555u) | ((r & 0x55555555u) << 1);

@@ -209,16 +209,23 @@ __device__ __forceinline__ WinRef window_ref(const QueryArgs& a, uint64_t i, uin
     return r;
 }
 
-// Stage two windows at once: lanes 0..kStageWords-1 take the words of A into
-// W[0..), the next kStageWords lanes those of B into W[kStageWords..).
+// Words staged for a window: its bytes from the 16-byte boundary below it, plus
+// one look-ahead word.
+__device__ __forceinline__ uint32_t staged_words(const WinRef& r) {
+    return r.nk ? (uint32_t)((r.hi - (r.lo & ~(uintptr_t)15) + 15) / 16) + 1u : 0u;
+}
+
+// Stage two windows at once, A's words into W[0..) and B's into
+// W[kStageWords..), one dword (4 bases) per lane: a 150-base read's two
+// windows take a single pass of the wave.
 __device__ __forceinline__ void stage_pair(Word* W, const WinRef& A, const WinRef& B, int lane) {
-    const bool second = lane >= kStageWords;
-    const WinRef& r = second ? B : A;
-    const int q = second ? lane - kStageWords : lane;
-    if (r.nk == 0 || q >= kStageWords) return;
-    const uintptr_t A0 = r.lo & ~(uintptr_t)15;
-    const int nw = (int)((r.hi - A0 + 15) / 16) + 1;
-    if (q < nw) W[lane] = load_word(A0 + 16 * (uintptr_t)q, r.vlo, r.vhi);
+    const uint32_t ndA = 4u * staged_words(A), nd = ndA + 4u * staged_words(B);
+    for (uint32_t q = (uint32_t)lane; q < nd; q += kWave) {
+        const bool second = q >= ndA;
+        const WinRef& r = second ? B : A;
+        stage_dword(W + (second ? kStageWords : 0), r.lo & ~(uintptr_t)15, second ? q - ndA : q,
+                    r.vlo, r.vhi);
+    }
 }
 
 struct WaveStats {
