@@ -137,16 +137,20 @@ __device__ __forceinline__ uint32_t h1(uint32_t x) {
 }
 
 // Slot hash h2 (Sec. 4.1 uses a second hash so that the skewed sketch values
-// spread over the table): SplitMix64's finalizer of the feature.
-__device__ __forceinline__ uint64_t h2(uint32_t f) {
-    uint64_t z = (uint64_t)f + 0x9e3779b97f4a7c15ull;
-    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
-    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
-    return z ^ (z >> 31);
+// spread over the table): the two-round xorshift-multiply mixer published as
+// "lowbias32" (C. Wellons, hash prospector), a bijection unrelated to h1.
+__device__ __forceinline__ uint32_t h2(uint32_t f) {
+    f ^= f >> 16;
+    f *= 0x7feb352du;
+    f ^= f >> 15;
+    f *= 0x846ca68bu;
+    f ^= f >> 16;
+    return f;
 }
 
+// Home bucket: floor(h2 * nb / 2^32) (tables have fewer than 2^32 buckets).
 __device__ __forceinline__ uint64_t home_bucket(uint32_t f, uint64_t nb) {
-    return __umul64hi(h2(f), nb);
+    return __umulhi(h2(f), (uint32_t)nb);
 }
 
 __device__ __forceinline__ uint64_t next_bucket(uint64_t b, uint64_t nb) {

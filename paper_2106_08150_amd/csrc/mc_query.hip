@@ -16,16 +16,27 @@ constexpr int kStageWords = 20;    // one window of at most 271 bases (19 words)
 constexpr uint32_t kMaxFeat = 128; // sketch elements buffered before lookups
 
 constexpr uint32_t kRing = kMaxFeat;   // lookup work items: at most one per feature
+// Entries [kRing, kRing + kRingMirror) repeat entries [0, kRingMirror), so that
+// the 32 items of a batch are read without wrapping (immediate LDS offsets).
+constexpr uint32_t kRingMirror = 32;
 
+// LDS of one wave. The sketch area serves a record's sketches and lookups, the
+// rank area its run-length and scoring after the last lookup; they overlap.
 template <uint32_t LCAP>
 struct QueryLds {
-    Word stage[2 * kStageWords];
-    uint32_t scratch[kWave];
-    uint32_t feats[kMaxFeat];
-    uint2 ring[kRing];                // (feature, bucket) lookup work items
+    uint2 ring[kRing + kRingMirror];  // (feature, bucket) lookup work items
     uint32_t list[LCAP + kWave];      // one item batch may overshoot LCAP by < 64
-    uint16_t uidx[LCAP + 2];
-    uint16_t score[LCAP];
+    union {
+        struct {
+            Word stage[2 * kStageWords];
+            uint32_t scratch[kWave];
+            uint32_t feats[kMaxFeat];
+        } sk;
+        struct {
+            uint16_t uidx[LCAP + 2];
+            uint16_t score[LCAP];
+        } rk;
+    };
     uint32_t sel_t[kMaxTopM], sel_s[kMaxTopM], sel_b[kMaxTopM];   // top-m list
 };
 
@@ -43,8 +54,10 @@ constexpr uint64_t kLastSlots = 0x8000800080008000ull;
 // a bucket is full exactly when its last slot is occupied: a full bucket
 // queues the feature's next bucket as a new item, and a feature's chain ends
 // at its first bucket that is not full (inserts never pass such a bucket).
-// Items wait in a ring in LDS, at most one per feature. Returns false once the
-// list outgrew LCAP.
+// Items wait in a ring in LDS, at most one per feature; every ring entry
+// always holds some item of the launch (the ring is cleared to bucket 0 when a
+// wave starts), so groups past a batch's last item may read any entry and
+// their lines are simply ignored. Returns false once the list outgrew LCAP.
 template <uint32_t LCAP>
 __device__ bool lookup(const QueryArgs& a, const uint32_t* F, uint32_t nf, uint2* ring,
                        uint32_t* list, uint32_t& nlist, uint32_t& probes) {
@@ -52,8 +65,11 @@ __device__ bool lookup(const QueryArgs& a, const uint32_t* F, uint32_t nf, uint2
     const uint32_t lane = (uint32_t)lane_id();
     const uint32_t g = lane >> 4;
     const uint32_t nb = (uint32_t)a.nb;
-    for (uint32_t i = lane; i < nf; i += kWave)
-        ring[i] = make_uint2(F[i], (uint32_t)home_bucket(F[i], a.nb));
+    for (uint32_t i = lane; i < nf; i += kWave) {
+        const uint2 it = make_uint2(F[i], (uint32_t)home_bucket(F[i], a.nb));
+        ring[i] = it;
+        if (i < kRingMirror) ring[i + kRing] = it;
+    }
     wave_lds_sync();
     const unsigned long long* slot = a.table + (lane & 15u);
     uint32_t head = 0, tail = nf;
@@ -65,9 +81,10 @@ __device__ bool lookup(const QueryArgs& a, const uint32_t* F, uint32_t nf, uint2
         const uint32_t c = min(tail - head, 4u * NB);
         uint32_t f[NB], b[NB];
         uint64_t sl[NB];
+        const uint2* batch = ring + ((head & (kRing - 1u)) + g);   // item 4q + g at batch[4q]
 #pragma unroll
-        for (int q = 0; q < NB; ++q) {   // groups past the last item take the last item
-            const uint2 it = ring[(head + min(4u * q + g, c - 1u)) & (kRing - 1u)];
+        for (int q = 0; q < NB; ++q) {
+            const uint2 it = batch[4 * q];
             f[q] = it.x;
             b[q] = it.y;
         }
@@ -94,7 +111,9 @@ __device__ bool lookup(const QueryArgs& a, const uint32_t* F, uint32_t nf, uint2
             if (full) {
                 if (occupied && (lane & 15u) == 15u) {
                     const uint32_t nxt = b[q] + 1u == nb ? 0u : b[q] + 1u;
-                    ring[(tail + rank_below(full)) & (kRing - 1u)] = make_uint2(f[q], nxt);
+                    const uint32_t pos = (tail + rank_below(full)) & (kRing - 1u);
+                    ring[pos] = make_uint2(f[q], nxt);
+                    if (pos < kRingMirror) ring[pos + kRing] = make_uint2(f[q], nxt);
                 }
                 tail += popc64(full);
             }
@@ -263,16 +282,16 @@ __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>
         WinRef wr[2];
         for (int h = 0; h < 2; ++h) wr[h] = window_ref(a, p + h, nwt, nws[0], o0, o1, len);
         wave_lds_sync();
-        stage_pair(L.stage, wr[0], wr[1], lane);
+        stage_pair(L.sk.stage, wr[0], wr[1], lane);
         wave_lds_sync();
         uint32_t nA, nB;
-        sketch_pair<KPL>(L.stage, wr[0].x0, wr[0].nk, L.stage + kStageWords, wr[1].x0, wr[1].nk,
-                         a.k, a.s, L.feats + nf, L.feats + nf + a.s, L.scratch, nA, nB);
+        sketch_pair<KPL>(L.sk.stage, wr[0].x0, wr[0].nk, L.sk.stage + kStageWords, wr[1].x0, wr[1].nk,
+                         a.k, a.s, L.sk.feats + nf, L.sk.feats + nf + a.s, L.sk.scratch, nA, nB);
         wave_lds_sync();
         if (nA < a.s && nB) {      // close the gap after A's features
-            const uint32_t f = (uint32_t)lane < nB ? L.feats[nf + a.s + lane] : 0u;
+            const uint32_t f = (uint32_t)lane < nB ? L.sk.feats[nf + a.s + lane] : 0u;
             wave_lds_sync();
-            if ((uint32_t)lane < nB) L.feats[nf + nA + lane] = f;
+            if ((uint32_t)lane < nB) L.sk.feats[nf + nA + lane] = f;
             wave_lds_sync();
         }
         nf += nA + nB;
@@ -280,7 +299,7 @@ __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>
         // buffer could overflow (one call site keeps the loop compact)
         if (nf && (p + 2 >= nwt || nf + 2 * a.s > kMaxFeat)) {
             ws.features += nf;
-            fits = lookup<LCAP>(a, L.feats, nf, L.ring, L.list, nlist, ws.probes);
+            fits = lookup<LCAP>(a, L.sk.feats, nf, L.ring, L.list, nlist, ws.probes);
             nf = 0;
         }
     }
@@ -308,23 +327,23 @@ __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>
         bool first = false;
         if (i < n) first = (i == 0) || (L.list[i] != L.list[i - 1]);
         uint64_t mb = ballot(first);
-        if (first) L.uidx[U + rank_below(mb)] = (uint16_t)i;
+        if (first) L.rk.uidx[U + rank_below(mb)] = (uint16_t)i;
         U += popc64(mb);
     }
-    if (lane == 0) L.uidx[U] = (uint16_t)n;
+    if (lane == 0) L.rk.uidx[U] = (uint16_t)n;
     wave_lds_sync();
 
     // score of the range of sws windows starting at each distinct location
     for (uint32_t u = (uint32_t)lane; u < U; u += kWave) {
-        const uint32_t loc = L.list[L.uidx[u]];
+        const uint32_t loc = L.list[L.rk.uidx[u]];
         const uint32_t t = loc >> kWindowBits, w_end = (loc & kWindowMask) + sws;
         uint32_t score = 0;
         for (uint32_t v = u; v < U; ++v) {
-            const uint32_t l2 = L.list[L.uidx[v]];
+            const uint32_t l2 = L.list[L.rk.uidx[v]];
             if ((l2 >> kWindowBits) != t || (l2 & kWindowMask) >= w_end) break;
-            score += (uint32_t)L.uidx[v + 1] - (uint32_t)L.uidx[v];
+            score += (uint32_t)L.rk.uidx[v + 1] - (uint32_t)L.rk.uidx[v];
         }
-        L.score[u] = (uint16_t)score;
+        L.rk.score[u] = (uint16_t)score;
     }
     wave_lds_sync();
 
@@ -338,13 +357,13 @@ __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>
     if (U <= (uint32_t)kWave) {          // one distinct location per lane
         uint32_t key = 0, t = kNone;
         if ((uint32_t)lane < U) {
-            t = L.list[L.uidx[lane]] >> kWindowBits;
-            key = ((uint32_t)L.score[lane] << 16) | (0xFFFFu - (uint32_t)lane);
+            t = L.list[L.rk.uidx[lane]] >> kWindowBits;
+            key = ((uint32_t)L.rk.score[lane] << 16) | (0xFFFFu - (uint32_t)lane);
         }
         for (uint32_t m = 0; m < a.top_m; ++m) {
             const uint32_t k = wave_max_u32(key);
             if (k == 0) break;
-            const uint32_t loc = L.list[L.uidx[0xFFFFu - (k & 0xFFFFu)]];
+            const uint32_t loc = L.list[L.rk.uidx[0xFFFFu - (k & 0xFFFFu)]];
             if (lane == 0) {
                 L.sel_t[m] = loc >> kWindowBits;
                 L.sel_s[m] = k >> 16;
@@ -358,15 +377,15 @@ __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>
         for (uint32_t m = 0; m < a.top_m; ++m) {
             uint32_t key = 0;
             for (uint32_t u = (uint32_t)lane; u < U; u += kWave) {
-                const uint32_t t = L.list[L.uidx[u]] >> kWindowBits;
+                const uint32_t t = L.list[L.rk.uidx[u]] >> kWindowBits;
                 bool excluded = false;
                 for (uint32_t x = 0; x < m; ++x) excluded |= (L.sel_t[x] == t);
-                const uint32_t ku = ((uint32_t)L.score[u] << 16) | (0xFFFFu - u);
+                const uint32_t ku = ((uint32_t)L.rk.score[u] << 16) | (0xFFFFu - u);
                 if (!excluded && ku > key) key = ku;
             }
             const uint32_t k = wave_max_u32(key);
             if (k == 0) break;
-            const uint32_t loc = L.list[L.uidx[0xFFFFu - (k & 0xFFFFu)]];
+            const uint32_t loc = L.list[L.rk.uidx[0xFFFFu - (k & 0xFFFFu)]];
             if (lane == 0) {
                 L.sel_t[m] = loc >> kWindowBits;
                 L.sel_s[m] = k >> 16;
@@ -396,6 +415,9 @@ template <uint32_t LCAP, int WPB, int KPL>
 __global__ __launch_bounds__(WPB * 64) void k_classify(QueryArgs a, int big) {
     __shared__ QueryLds<LCAP> L[WPB];
     const int wave = (int)uniform(threadIdx.x >> 6);
+    for (uint32_t i = (uint32_t)lane_id(); i < kRing + kRingMirror; i += kWave)
+        L[wave].ring[i] = make_uint2(0u, 0u);   // any item must name a bucket of the table
+    wave_lds_sync();
     const uint32_t n_iter = big ? uniform(a.counters[kQOverflow]) : a.n_records;
     WaveStats ws;
     for (uint32_t it = blockIdx.x * WPB + wave; it < n_iter; it += gridDim.x * WPB) {
