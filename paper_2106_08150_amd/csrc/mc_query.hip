@@ -411,8 +411,11 @@ __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>
     write_result(a, rec, label, L, nsel);
 }
 
+// Seven waves per SIMD (at most 72 VGPRs): the lookups' memory latency is
+// hidden by other waves' work, so occupancy pays for a few spilled registers.
 template <uint32_t LCAP, int WPB, int KPL>
-__global__ __launch_bounds__(WPB * 64) void k_classify(QueryArgs a, int big) {
+__global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(7)))
+void k_classify(QueryArgs a, int big) {
     __shared__ QueryLds<LCAP> L[WPB];
     const int wave = (int)uniform(threadIdx.x >> 6);
     for (uint32_t i = (uint32_t)lane_id(); i < kRing + kRingMirror; i += kWave)
