@@ -133,7 +133,7 @@ def uneven_leg(args, g, gtext, torch, mc, synth):
 
     default_ms = timed(lambda: mc.mc_classify_ex(db.h, r, o, n, opts, labels))
     ref = labels.clone()
-    m = min(n, 500_000)
+    m = min(n, 2_000_000)
     sub_o = o[:2 * m + 1].contiguous()
     cfg, _ = mc.mc_db_autotune(db.h, r, sub_o, m, opts, labels)
     graph = mc.ClassifyGraph(db.h, r, o, n, opts, labels)

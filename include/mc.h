@@ -191,9 +191,11 @@ int mc_db_set_launch_config(mc_db* db, const mc_launch_config* cfg);
 int mc_db_get_launch_config(mc_db* db, mc_launch_config* cfg);
 
 /* Autotuner: classifies the given batch (device buffers, as mc_classify_ex)
- * with every supported launch shape, checks that all give identical labels
+ * with the current and every supported launch shape (best of three timed
+ * runs after a warm-up each), checks that all give identical labels
  * (MC_ERR_STATE otherwise), keeps the fastest in the handle for later calls
- * and reports it (best and best_ms may be NULL). Synchronous on `stream`. */
+ * (the current shape stays unless another is more than 2% faster) and reports
+ * it (best and best_ms may be NULL). Synchronous on `stream`. */
 int mc_db_autotune(mc_db* db, const char* reads, const uint64_t* offsets, uint32_t n_records,
                    const mc_query_opts* opts, uint32_t* out_labels, void* stream,
                    mc_launch_config* best, double* best_ms);
