@@ -303,6 +303,23 @@ def test_clustered_midsize(torch):
     assert_same_results(gl, gt, ol, ot)
 
 
+def test_insert_modes_agree(torch, monkeypatch):
+    """The slice-local insert (default) and the global-counter insert used for
+    tables too large for LDS slices (forced here, with 1 MiB partitions) store
+    the same pairs, which are the oracle's."""
+    g = synth.clustered_genomes(4, 5, 2e6, seed=47, median_bp=1e5, clip=(3e3, 3e5))
+    slice_db, odb = build_both(torch, g, splits=[(0, 7), (7, 20)])
+    monkeypatch.setenv("MC_INSERT", "global")
+    monkeypatch.setenv("MC_PART_MB", "1")
+    global_db, _ = build_both(torch, g, splits=[(0, 7), (7, 20)])
+    assert_same_table(slice_db, odb)
+    assert_same_table(global_db, odb)
+    reads = synth.sample_reads(g, 3000, 150, seed=48)
+    for db in (slice_db, global_db):
+        gl, gt, ol, ot = classify_both(torch, db, odb, reads)
+        assert_same_results(gl, gt, ol, ot)
+
+
 def test_invalid_taxonomy_and_state(torch):
     db = mc.Database()
     with pytest.raises(mc.MCError):
