@@ -5,12 +5,27 @@
 // `sws` consecutive windows per target, keeps the top m targets and labels the
 // record, by LCA when the top scores are close. Records whose list does not
 // fit the fast path's LDS are queued for a second pass with a larger list.
+#include <cstddef>
+
 #include "mc_device.hpp"
 #include "mc_internal.hpp"
 
 namespace mc {
 
 namespace {
+
+// Kernel arguments used once per record or on rare paths are read where they
+// are used (a scalar load from the argument segment at an offset the compiler
+// treats as unknown), so they do not occupy scalar registers across the record
+// loop; the hot loop needs every scalar register it can get.
+template <typename T>
+__device__ __forceinline__ T arg_at_use(uint32_t off) {
+    asm volatile("" : "+s"(off));
+    const __attribute__((address_space(4))) char* base =
+        (const __attribute__((address_space(4))) char*)__builtin_amdgcn_kernarg_segment_ptr();
+    return *(const __attribute__((address_space(4))) T*)(base + off);
+}
+#define MC_COLD(field) arg_at_use<decltype(QueryArgs::field)>((uint32_t)offsetof(QueryArgs, field))
 
 constexpr int kStageWords = 20;    // one window of at most 271 bases (19 words)
 constexpr uint32_t kMaxFeat = 128; // sketch elements buffered before lookups
@@ -194,9 +209,11 @@ __device__ __forceinline__ void write_result(const QueryArgs& a, uint32_t rec, u
                                              const Lds& L, uint32_t nsel) {
     const uint32_t lane = (uint32_t)lane_id();
     if (lane == 0) a.out_labels[rec] = label;
-    if (a.out_top && lane < a.top_m) {
+    uint32_t* const out_top = MC_COLD(out_top);
+    const uint32_t top_m = MC_COLD(top_m);
+    if (out_top && lane < top_m) {
         const bool h = lane < nsel;
-        uint32_t* o = a.out_top + ((uint64_t)rec * a.top_m + lane) * 3;
+        uint32_t* o = out_top + ((uint64_t)rec * top_m + lane) * 3;
         o[0] = h ? L.sel_t[lane] : kNone;
         o[1] = h ? L.sel_s[lane] : 0u;
         o[2] = h ? L.sel_b[lane] : 0u;
@@ -306,11 +323,11 @@ __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>
     if (!fits) {
         if (!big) {
             if (lane == 0) {
-                uint32_t qi = atomicAdd(&a.counters[kQOverflow], 1u);
-                a.queue[qi] = rec;
+                uint32_t qi = atomicAdd(&MC_COLD(counters)[kQOverflow], 1u);
+                MC_COLD(queue)[qi] = rec;
             }
         } else {
-            if (lane == 0) atomicAdd(&a.counters[kQTooLong], 1u);
+            if (lane == 0) atomicAdd(&MC_COLD(counters)[kQTooLong], 1u);
             write_result(a, rec, kNone, L, 0);
         }
         return;
@@ -354,13 +371,14 @@ __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>
     // scores, the smallest location (smallest target, then window). Each of
     // the m rounds takes one wave maximum and then drops the chosen target.
     uint32_t nsel = 0;
+    const uint32_t top_m = MC_COLD(top_m);
     if (U <= (uint32_t)kWave) {          // one distinct location per lane
         uint32_t key = 0, t = kNone;
         if ((uint32_t)lane < U) {
             t = L.list[L.rk.uidx[lane]] >> kWindowBits;
             key = ((uint32_t)L.rk.score[lane] << 16) | (0xFFFFu - (uint32_t)lane);
         }
-        for (uint32_t m = 0; m < a.top_m; ++m) {
+        for (uint32_t m = 0; m < top_m; ++m) {
             const uint32_t k = wave_max_u32(key);
             if (k == 0) break;
             const uint32_t loc = L.list[L.rk.uidx[0xFFFFu - (k & 0xFFFFu)]];
@@ -374,7 +392,7 @@ __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>
         }
         wave_lds_sync();
     } else {
-        for (uint32_t m = 0; m < a.top_m; ++m) {
+        for (uint32_t m = 0; m < top_m; ++m) {
             uint32_t key = 0;
             for (uint32_t u = (uint32_t)lane; u < U; u += kWave) {
                 const uint32_t t = L.list[L.rk.uidx[u]] >> kWindowBits;
@@ -399,13 +417,15 @@ __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>
     // label: the best target's taxon on a clear lead, else the LCA of the
     // taxa of the listed targets within hit_diff of the best score
     uint32_t label = kNone;
-    if (nsel > 0 && L.sel_s[0] >= a.min_hits) {
+    if (nsel > 0 && L.sel_s[0] >= MC_COLD(min_hits)) {
         const uint32_t c1 = L.sel_s[0], c2 = nsel > 1 ? L.sel_s[1] : 0u;
-        label = uniform(a.target_taxon[L.sel_t[0]]);
-        if (c1 - c2 <= a.hit_diff) {
+        const uint32_t* const taxon = MC_COLD(target_taxon);
+        const uint32_t hit_diff = MC_COLD(hit_diff);
+        label = uniform(taxon[L.sel_t[0]]);
+        if (c1 - c2 <= hit_diff) {
             for (uint32_t x = 1; x < nsel; ++x)
-                if ((uint64_t)L.sel_s[x] + a.hit_diff >= c1)
-                    label = uniform(lca(label, a.target_taxon[L.sel_t[x]], a.parents, a.depth));
+                if ((uint64_t)L.sel_s[x] + hit_diff >= c1)
+                    label = uniform(lca(label, taxon[L.sel_t[x]], MC_COLD(parents), MC_COLD(depth)));
         }
     }
     write_result(a, rec, label, L, nsel);
