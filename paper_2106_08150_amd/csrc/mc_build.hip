@@ -2,6 +2,7 @@
 // h1 + bottom-s sketch per window + insertion into the bucketed multi-value
 // table, the deterministic per-feature cap, table growth and test exports.
 #include <algorithm>
+#include <cstdlib>
 
 #include "mc_device.hpp"
 #include "mc_internal.hpp"
@@ -393,57 +394,243 @@ __global__ __launch_bounds__(kBuildThreads) void k_insert(BuildArgs a,
 }
 
 // B5, slice mode: workgroup z inserts the pairs of slice z (buckets
-// [z << slice_shift, (z + 1) << slice_shift), the pairs in slice order), with
-// the slice's fill counters held in LDS; no other workgroup touches those
-// buckets meanwhile. The entry goes to the claimed slot of the global table as
-// with global counters. An entry whose chain runs past the end of its slice
-// is deferred to the global pass (k_insert), which runs once every slice has
-// stored its counters back.
-__global__ __launch_bounds__(kBuildThreads) void k_insert_slices(BuildArgs a) {
-    extern __shared__ uint32_t cnt[];     // 2^slice_shift counters
-    __shared__ uint32_t red[3 * kWavesPerBuild];
+// [z << slice_shift, (z + 1) << slice_shift), the pairs in slice order); no
+// other workgroup touches those buckets meanwhile. The workgroup reads the
+// slice's pairs once into registers, ranks each within its home bucket with
+// an LDS counter, and places them as the global-counter insert would (each
+// pair in the first bucket from its home with a free slot, the slots of a
+// bucket filled in order): with d(r) = pairs homed at r minus free slots of
+// r, the pairs carried past bucket r are carry(r) = max(0, carry(r-1) + d(r)),
+// a max-plus scan across the slice, and buckets <= r hold the first
+// N(r) - carry(r) pairs in home order (N = inclusive count). The placed pairs
+// are staged in LDS in home order and every bucket that gains pairs is
+// written as one whole 128-byte line (old slots, new pairs, empty slots), so
+// the table sees full-line writes only. Pairs carried past the slice end are
+// deferred to the global pass (k_insert). A slice with more pairs than the
+// registers hold takes the direct path: LDS fill counters, one store a pair.
+constexpr int kLineThreads = 1024;
+constexpr int kLineWaves = kLineThreads / kWave;
+constexpr int kLinePer = 24;                        // pairs per thread held in registers
+constexpr uint32_t kLineCap = (uint32_t)kLineThreads * kLinePer;
+constexpr uint32_t kNoKey = 0xFFFFFFFFu;
+static_assert(kLineCap < 0x10000, "sorted positions are kept in 16 bits");
+
+__device__ __forceinline__ void defer_pair(BuildArgs& a, unsigned long long e) {
+    const unsigned long long q = atomicAdd(&a.counters[kCntDefer], 1ull);
+    a.parted[q] = e;
+}
+
+__device__ __forceinline__ uint32_t free_slots(uint8_t c) { return (uint32_t)kSlots - c; }
+
+// Direct path of one slice: LDS fill counters, each pair claims a slot.
+__device__ __forceinline__ void insert_slice_direct(BuildArgs& a, uint32_t* cnt, uint64_t b0,
+                                                    uint32_t nbk, uint64_t p0, uint64_t p1,
+                                                    uint32_t& ins, uint32_t& probe) {
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t i = tid; i < nbk; i += kLineThreads) cnt[i] = a.bcount[b0 + i];
+    __syncthreads();
+    for (uint64_t i = p0 + tid; i < p1; i += kLineThreads) {
+        const unsigned long long e = a.pairs[i];
+        const uint32_t f = (uint32_t)(e >> 32);
+        const uint32_t h = (uint32_t)(home_bucket(f, a.nb) - b0);
+        uint32_t r = h;
+        bool done = false;
+        for (; r < nbk && !done; ++r) {
+            if (cnt[r] < (uint32_t)kSlots) {
+                const uint32_t pos = atomicAdd(&cnt[r], 1u);
+                if (pos < (uint32_t)kSlots) {
+                    a.table[(b0 + r) * kSlots + pos] = e;
+                    done = true;
+                }
+            }
+        }
+        if (done) {
+            const uint32_t dist = r - 1 - h;
+            ins += 1;
+            probe += dist;
+            if (dist >= a.cap_dist) push_candidate(a, f);
+        } else {
+            defer_pair(a, e);
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < nbk; i += kLineThreads) a.bcount[b0 + i] = cnt[i];
+}
+
+__global__ __launch_bounds__(kLineThreads) void k_insert_slices(BuildArgs a, uint32_t buf_cap,
+                                                                uint32_t line_cap) {
+    // dynamic LDS: buf[buf_cap] u64 (counters while counting, staged pairs
+    // while writing), then per bucket: Te u16, Tp u16, c8 u8
+    extern __shared__ unsigned long long buf[];
+    __shared__ uint32_t wsum[kLineWaves];
+    __shared__ int wA[kLineWaves], wD[kLineWaves];
+    __shared__ uint32_t red[2 * kLineWaves];
+    const uint32_t SB = 1u << a.slice_shift;
+    uint32_t* const cnt = reinterpret_cast<uint32_t*>(buf);
+    uint16_t* const Te = reinterpret_cast<uint16_t*>(buf + buf_cap);   // first position homed at r
+    uint16_t* const Tp = Te + SB;                                      // pairs placed in buckets <= r
+    uint8_t* const c8 = reinterpret_cast<uint8_t*>(Tp + SB);           // slots in use before
+    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint32_t n_slices = a.n_parts << a.fine_bits;
-    const uint64_t sb = 1ull << a.slice_shift;
-    uint32_t ins = 0, probe = 0, full = 0;
+    const int kNone = -(1 << 30);
+    uint32_t ins = 0, probe = 0;
     for (uint32_t z = blockIdx.x; z < n_slices; z += gridDim.x) {
         const uint64_t b0 = (uint64_t)z << a.slice_shift;
         if (b0 >= a.nb) break;            // slices past the table are empty
-        const uint32_t nbk = (uint32_t)(b0 + sb <= a.nb ? sb : a.nb - b0);
+        const uint32_t nbk = (uint32_t)(b0 + SB <= a.nb ? SB : a.nb - b0);
         const uint64_t p0 = a.slice_start[z], p1 = a.slice_start[z + 1];
-        if (p0 == p1) continue;
+        const uint32_t np = (uint32_t)(p1 - p0);
+        if (np == 0) continue;
+        __syncthreads();                  // LDS of the previous slice is free
+        if (np > line_cap) {
+            insert_slice_direct(a, cnt, b0, nbk, p0, p1, ins, probe);
+            continue;
+        }
+        // per-thread indices recomputed each slice (not held across the loop)
+        uint32_t t = tid;
+        asm volatile("" : "+v"(t));
+        const uint32_t ln = t & 63;
+        for (uint32_t i = tid; i < nbk; i += kLineThreads) {
+            cnt[i] = 0u;
+            c8[i] = (uint8_t)min(a.bcount[b0 + i], (uint32_t)kSlots);
+        }
         __syncthreads();
-        for (uint32_t i = threadIdx.x; i < nbk; i += kBuildThreads) cnt[i] = a.bcount[b0 + i];
-        __syncthreads();
-        for (uint64_t i = p0 + threadIdx.x; i < p1; i += kBuildThreads) {
-            const unsigned long long e = a.pairs[i];
-            const uint32_t f = (uint32_t)(e >> 32);
-            const uint64_t home = home_bucket(f, a.nb);
-            uint32_t r = (uint32_t)(home - b0);   // bucket within the slice
-            bool done = false;
-            for (; r < nbk; ++r) {
-                if (cnt[r] < (uint32_t)kSlots) {
-                    const uint32_t pos = atomicAdd(&cnt[r], 1u);
-                    if (pos < (uint32_t)kSlots) {
-                        a.table[(b0 + r) * kSlots + pos] = e;
-                        done = true;
-                        break;
-                    }
+        // the slice's pairs, each ranked within its home bucket
+        unsigned long long e[kLinePer];
+        uint32_t key[kLinePer];
+#pragma unroll
+        for (int k = 0; k < kLinePer; ++k) {   // past the end: a repeat of the last pair, no key
+            const uint32_t i = t + (uint32_t)k * kLineThreads;
+            e[k] = a.pairs[p0 + min(i, np - 1)];
+            key[k] = i < np ? 0u : kNoKey;
+        }
+#pragma unroll
+        for (int k = 0; k < kLinePer; ++k) {
+            if (key[k] == 0u) {
+                const uint32_t r = (uint32_t)(home_bucket((uint32_t)(e[k] >> 32), a.nb) - b0);
+                if (r < nbk) {
+                    key[k] = (r << 16) | atomicAdd(&cnt[r], 1u);
+                } else {
+                    key[k] = kNoKey;
+                    defer_pair(a, e[k]);    // not homed in this slice (does not occur)
                 }
-            }
-            if (done) {
-                const uint32_t d = r - (uint32_t)(home - b0);
-                ins += 1;
-                probe += d;
-                if (d >= a.cap_dist) push_candidate(a, f);
-            } else {
-                const unsigned long long q = atomicAdd(&a.counters[kCntDefer], 1ull);
-                a.parted[q] = e;
             }
         }
         __syncthreads();
-        for (uint32_t i = threadIdx.x; i < nbk; i += kBuildThreads) a.bcount[b0 + i] = cnt[i];
+        // per-thread run of buckets: count sum and carry function max(A, x + D)
+        const uint32_t per = (nbk + kLineThreads - 1) / kLineThreads;
+        const uint32_t r0 = min(nbk, t * per), r1 = min(nbk, r0 + per);
+        uint32_t S = 0;
+        int A = kNone, D = 0;
+        for (uint32_t r = r0; r < r1; ++r) {
+            const int d = (int)cnt[r] - (int)free_slots(c8[r]);
+            S += cnt[r];
+            A = max(0, A + d);
+            D += d;
+        }
+        // inclusive scan within the wave (a later run composed after an earlier one)
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const int src = ln >= (uint32_t)d ? (int)ln - d : (int)ln;
+            const uint32_t pS = shfl_idx(S, src);
+            const int pA = (int)shfl_idx((uint32_t)A, src), pD = (int)shfl_idx((uint32_t)D, src);
+            if (ln >= (uint32_t)d) {
+                S += pS;
+                A = max(A, pA + D);
+                D += pD;
+            }
+        }
+        const int up = ln ? (int)ln - 1 : 0;
+        uint32_t eS = shfl_idx(S, up);
+        int eA = (int)shfl_idx((uint32_t)A, up), eD = (int)shfl_idx((uint32_t)D, up);
+        if (ln == 0) {
+            eS = 0;
+            eA = kNone;
+            eD = 0;
+        }
+        if (ln == kWave - 1) {
+            wsum[w] = S;
+            wA[w] = A;
+            wD[w] = D;
+        }
+        __syncthreads();
+        uint32_t PS = 0;
+        int PA = kNone, PD = 0;
+        for (uint32_t i = 0; i < w; ++i) {
+            PS += wsum[i];
+            PA = max(wA[i], PA + wD[i]);
+            PD += wD[i];
+        }
+        uint32_t run = PS + eS;                          // pairs homed before r0
+        int carry = max(0, max(max(eA, PA + eD), PD + eD));   // carried into r0
+        for (uint32_t r = r0; r < r1; ++r) {
+            const uint32_t n = cnt[r];
+            Te[r] = (uint16_t)run;
+            run += n;
+            carry = max(0, carry + (int)n - (int)free_slots(c8[r]));
+            Tp[r] = (uint16_t)(run - (uint32_t)carry);
+        }
+        __syncthreads();
+        const uint32_t placed_all = Tp[nbk - 1];
+        // home-order positions; pairs beyond the placed ones leave the slice
+#pragma unroll
+        for (int k = 0; k < kLinePer; ++k) {
+            if (key[k] != kNoKey) {
+                const uint32_t j = Te[key[k] >> 16] + (key[k] & 0xFFFFu);
+                key[k] = j;
+                if (j >= placed_all) {
+                    defer_pair(a, e[k]);
+                    key[k] = kNoKey;
+                }
+            }
+        }
+        // rounds: positions [W, W + buf_cap) staged; buckets starting in [W, W + step)
+        const uint32_t step = buf_cap - kSlots;
+        for (uint32_t W = 0; W < placed_all; W += step) {
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < kLinePer; ++k)
+                if (key[k] - W < buf_cap) buf[key[k] - W] = e[k];   // kNoKey never
+            __syncthreads();
+            const uint32_t sl = tid & (kSlots - 1);
+            for (uint32_t r = tid / kSlots; r < nbk; r += kLineThreads / kSlots) {
+                const uint32_t st = r ? Tp[r - 1] : 0u, placed = Tp[r] - st;
+                if (placed == 0 || st - W >= step) continue;
+                const uint32_t c = c8[r];
+                unsigned long long* slot = a.table + (b0 + r) * kSlots + sl;
+                unsigned long long v = kEmpty;
+                if (sl < c) {
+                    v = *slot;
+                } else if (sl - c < placed) {
+                    v = buf[st - W + sl - c];
+                    const uint32_t f = (uint32_t)(v >> 32);
+                    const uint32_t dist = r - (uint32_t)(home_bucket(f, a.nb) - b0);
+                    ins += 1;
+                    probe += dist;
+                    if (dist >= a.cap_dist) push_candidate(a, f);
+                }
+                *slot = v;
+                if (sl == 0) a.bcount[b0 + r] = c + placed;
+            }
+        }
     }
-    add_insert_stats(a, ins, probe, full, red);
+    // statistics
+#pragma unroll
+    for (int m = 1; m < kWave; m <<= 1) {
+        ins += shfl_xor(ins, m);
+        probe += shfl_xor(probe, m);
+    }
+    __syncthreads();
+    if (lane == 0) {
+        red[w] = ins;
+        red[kLineWaves + w] = probe;
+    }
+    __syncthreads();
+    if (tid < 2) {
+        uint32_t v = 0;
+        for (int i = 0; i < kLineWaves; ++i) v += red[tid * kLineWaves + i];
+        if (v) atomicAdd(&a.counters[tid == 0 ? kCntInserted : kCntProbe], (unsigned long long)v);
+    }
 }
 
 // ---------------------------------------------------------------- cap -----
@@ -622,7 +809,28 @@ hipError_t launch_sketch(const BuildArgs& a, bool pairs, hipStream_t st) {
     return hipGetLastError();
 }
 
-bool slice_mode_fits(uint32_t slice_shift) { return slice_shift <= kMaxSliceShift; }
+// Staging entries of the slice insert for 2^slice_shift buckets: the dynamic
+// LDS left (at most 160 KiB a workgroup, less its static arrays) after 5 bytes
+// a bucket; 0 if that is too few for the direct path's counters or a round.
+uint32_t slice_buf_cap(uint32_t slice_shift) {
+    static int max_lds = -1;
+    if (max_lds < 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            v = 0;
+        max_lds = v;
+    }
+    const int64_t avail = (int64_t)std::min(max_lds, 160 * 1024) - 1024 - ((int64_t)5 << slice_shift);
+    if (avail <= 0) return 0;
+    const uint32_t cap = (uint32_t)std::min<int64_t>(avail / 8, kLineCap) & ~7u;
+    if ((uint64_t)cap * 8 < ((uint64_t)4 << slice_shift) || cap < 4 * kSlots) return 0;
+    return cap;
+}
+
+bool slice_mode_fits(uint32_t slice_shift) {
+    return slice_shift <= kMaxSliceShift && slice_buf_cap(slice_shift) != 0;
+}
 
 hipError_t launch_partition(const BuildArgs& a, uint64_t n_slots, hipStream_t st) {
     hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kMaxParts), 0, st, a);
@@ -670,8 +878,20 @@ hipError_t launch_insert(const BuildArgs& a, uint64_t max_items, hipStream_t st)
         return hipGetLastError();
     }
     const uint32_t n_slices = a.n_parts << a.fine_bits;
-    const size_t lds = ((size_t)1 << a.slice_shift) * sizeof(uint32_t);
-    hipLaunchKernelGGL(k_insert_slices, dim3(n_slices), dim3(kBuildThreads), lds, st, a);
+    uint32_t buf_cap = slice_buf_cap(a.slice_shift), line_cap = kLineCap;
+    if (buf_cap == 0) return hipErrorInvalidConfiguration;
+    // test overrides: a smaller staging buffer (more rounds a slice), or the
+    // direct path for slices of more than MC_SLICE_DIRECT pairs
+    if (const char* env = getenv("MC_SLICE_STAGE")) {
+        const uint64_t lo = std::max<uint64_t>(4 * kSlots, (uint64_t)1 << (a.slice_shift - 1));
+        const uint64_t v = std::max<uint64_t>(lo, (uint64_t)atoll(env));
+        buf_cap = (uint32_t)std::min<uint64_t>(buf_cap, (v + 7) & ~7ull);
+    }
+    if (const char* env = getenv("MC_SLICE_DIRECT"))
+        line_cap = (uint32_t)std::min<long long>(line_cap, std::max(0ll, atoll(env)));
+    const size_t lds = (size_t)buf_cap * 8 + ((size_t)5 << a.slice_shift);
+    hipLaunchKernelGGL(k_insert_slices, dim3(n_slices), dim3(kLineThreads), lds, st, a, buf_cap,
+                       line_cap);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // deferred entries (count known on the device only): a small persistent grid

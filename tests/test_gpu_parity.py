@@ -303,21 +303,30 @@ def test_clustered_midsize(torch):
     assert_same_results(gl, gt, ol, ot)
 
 
-def test_insert_modes_agree(torch, monkeypatch):
-    """The slice-local insert (default) and the global-counter insert used for
-    tables too large for LDS slices (forced here, with 1 MiB partitions) store
-    the same pairs, which are the oracle's."""
+INSERT_MODES = {
+    "slices": {},
+    "staged": {"MC_SLICE_STAGE": "512"},
+    "direct": {"MC_SLICE_DIRECT": "0"},
+    "global": {"MC_INSERT": "global", "MC_PART_MB": "1"},
+}
+
+
+@pytest.mark.parametrize("mode", list(INSERT_MODES))
+def test_insert_modes_agree(torch, monkeypatch, mode):
+    """Every insert path stores the oracle's pairs, over two add calls (the
+    second fills buckets the first left partly full): the slice-local insert
+    (default), the same with a 512-pair staging buffer (many rounds a slice),
+    its direct path (LDS fill counters, one store a pair), and the
+    global-counter insert used for tables too large for LDS slices (1 MiB
+    partitions)."""
+    for k, v in INSERT_MODES[mode].items():
+        monkeypatch.setenv(k, v)
     g = synth.clustered_genomes(4, 5, 2e6, seed=47, median_bp=1e5, clip=(3e3, 3e5))
-    slice_db, odb = build_both(torch, g, splits=[(0, 7), (7, 20)])
-    monkeypatch.setenv("MC_INSERT", "global")
-    monkeypatch.setenv("MC_PART_MB", "1")
-    global_db, _ = build_both(torch, g, splits=[(0, 7), (7, 20)])
-    assert_same_table(slice_db, odb)
-    assert_same_table(global_db, odb)
+    db, odb = build_both(torch, g, splits=[(0, 7), (7, 20)])
+    assert_same_table(db, odb)
     reads = synth.sample_reads(g, 3000, 150, seed=48)
-    for db in (slice_db, global_db):
-        gl, gt, ol, ot = classify_both(torch, db, odb, reads)
-        assert_same_results(gl, gt, ol, ot)
+    gl, gt, ol, ot = classify_both(torch, db, odb, reads)
+    assert_same_results(gl, gt, ol, ot)
 
 
 def test_invalid_taxonomy_and_state(torch):
