@@ -83,6 +83,8 @@ struct mc_db {
     uint32_t* bcount = nullptr;       // fill counter per bucket
     uint64_t nb = 0;
     uint64_t slots_used = 0;          // occupied slots (stored + tombstones) since the last rehash
+    bool touched = false;             // an insert ran on this table (it may hold entries)
+    bool fill_pending = false;        // table and counters not yet cleared (left to the insert)
     unsigned long long* counters = nullptr;   // kNumBuildCounters
     uint32_t* cand = nullptr;
     uint64_t cand_cap = 0;
@@ -136,7 +138,20 @@ int dev_alloc(T** p, uint64_t n) {
 
 // Make room for `extra` more occupied slots at the handle's load factor,
 // re-inserting the current entries into a larger table when needed.
-int ensure_capacity(mc_db* db, uint64_t extra, hipStream_t st) {
+// Clear a table whose clearing was left to the insert (empty slots, zero counters).
+int materialize(mc_db* db, hipStream_t st) {
+    if (!db->fill_pending) return MC_OK;
+    HIP_TRY(launch_fill_u64(db->table, db->nb * kSlots, ~0ull, st));
+    HIP_TRY(launch_fill_u32(db->bcount, db->nb, 0u, st));
+    db->fill_pending = false;
+    return MC_OK;
+}
+
+// Grow the table for `extra` more slots at the load factor. A table that an
+// insert has touched is rehashed into the new one; an untouched one is simply
+// replaced, and with defer_fill the new table is left uncleared for the next
+// slice-mode insert to write whole (materialize() clears it otherwise).
+int ensure_capacity(mc_db* db, uint64_t extra, hipStream_t st, bool defer_fill = false) {
     const double slots_per_bucket = (double)kSlots;
     uint64_t need = db->slots_used + extra;
     if (db->table && (double)need <= db->load * slots_per_bucket * (double)db->nb) return MC_OK;
@@ -152,9 +167,10 @@ int ensure_capacity(mc_db* db, uint64_t extra, hipStream_t st) {
     if (rc) return rc;
     rc = dev_alloc(&cnt, nb);
     if (rc) { (void)hipFree(t); return rc; }
-    HIP_TRY(launch_fill_u64(t, nb * kSlots, ~0ull, st));
-    HIP_TRY(launch_fill_u32(cnt, nb, 0u, st));
-    if (db->table) {
+    const bool grow = db->table != nullptr;
+    if (grow && db->touched) {
+        HIP_TRY(launch_fill_u64(t, nb * kSlots, ~0ull, st));
+        HIP_TRY(launch_fill_u32(cnt, nb, 0u, st));
         HIP_TRY(launch_fill_u64(db->counters, kNumBuildCounters, 0ull, st));
         HIP_TRY(launch_rehash(db->table, db->nb, t, cnt, nb, db->counters, st));
         unsigned long long c[kNumBuildCounters];
@@ -166,9 +182,21 @@ int ensure_capacity(mc_db* db, uint64_t extra, hipStream_t st) {
             return fail(MC_ERR_TABLE_FULL, "rehash found no free slot for %llu entries",
                         (unsigned long long)c[kCntFull]);
         }
+        db->slots_used = c[kCntMoved];
+        db->touched = c[kCntMoved] != 0;
+        db->fill_pending = false;
+    } else {
+        db->slots_used = 0;
+        db->touched = false;
+        db->fill_pending = defer_fill;
+        if (!defer_fill) {
+            HIP_TRY(launch_fill_u64(t, nb * kSlots, ~0ull, st));
+            HIP_TRY(launch_fill_u32(cnt, nb, 0u, st));
+        }
+    }
+    if (grow) {
         HIP_TRY(hipFree(db->table));
         HIP_TRY(hipFree(db->bcount));
-        db->slots_used = c[kCntMoved];
         db->st.n_rehash += 1;
     }
     db->bcount = cnt;
@@ -343,6 +371,11 @@ int build_chunk(mc_db* db, const uint8_t* genomes, const std::vector<TargetDesc>
     a.pairs = db->pairs;
     a.parted = db->parted;
     plan_partitions(db, a);
+    if (!a.slice_mode) {
+        rc = materialize(db, st);
+        if (rc) return rc;
+    }
+    a.fresh = db->fill_pending ? 1u : 0u;   // the slice insert writes every bucket
     a.hist = db->hist;
     a.part_start = db->part_start;
     a.cursor = db->cursor;
@@ -358,6 +391,8 @@ int build_chunk(mc_db* db, const uint8_t* genomes, const std::vector<TargetDesc>
     HIP_TRY(timed_launch(db, db->timers[MC_K_SCATTER], st,
                          [&] { return launch_partition(a, slots, st); }));
     HIP_TRY(timed_launch(db, db->timers[MC_K_INSERT], st, [&] { return launch_insert(a, slots, st); }));
+    db->fill_pending = false;
+    db->touched = true;
     return MC_OK;
 }
 
@@ -380,8 +415,7 @@ int add_targets_dev(mc_db* db, const uint8_t* genomes, const uint64_t* lengths,
         wins += nw;
     }
     const uint64_t upper = wins * db->s;
-    int rc = ensure_capacity(db, upper, st);
-    if (rc) return rc;
+    int rc = MC_OK;
     uint64_t cand_need = std::min<uint64_t>(std::max<uint64_t>(upper, 1), kCandCapMax);
     if (cand_need > db->cand_cap) {
         if (db->cand) HIP_TRY(hipFree(db->cand));
@@ -391,19 +425,29 @@ int add_targets_dev(mc_db* db, const uint8_t* genomes, const uint64_t* lengths,
         if (rc) return rc;
         db->cand_cap = cand_need;
     }
-    HIP_TRY(launch_fill_u64(db->counters, kNumBuildCounters, 0ull, st));
-    // chunks of whole targets with at most kMaxSlotsPerChunk pair slots
-    for (uint32_t t0 = 0; t0 < n;) {
-        uint32_t t1 = t0;
-        uint64_t slots = 0;
-        while (t1 < n && (t1 == t0 || slots + (uint64_t)td[t1].nw * db->s <= kMaxSlotsPerChunk)) {
-            slots += (uint64_t)td[t1].nw * db->s;
-            ++t1;
+    rc = ensure_capacity(db, upper, st, true);
+    if (rc) return rc;
+    auto insert_all = [&]() -> int {
+        HIP_TRY(launch_fill_u64(db->counters, kNumBuildCounters, 0ull, st));
+        // chunks of whole targets with at most kMaxSlotsPerChunk pair slots
+        for (uint32_t t0 = 0; t0 < n;) {
+            uint32_t t1 = t0;
+            uint64_t slots = 0;
+            while (t1 < n &&
+                   (t1 == t0 || slots + (uint64_t)td[t1].nw * db->s <= kMaxSlotsPerChunk)) {
+                slots += (uint64_t)td[t1].nw * db->s;
+                ++t1;
+            }
+            if (int r = build_chunk(db, genomes, td, t0, t1, st)) return r;
+            t0 = t1;
         }
-        rc = build_chunk(db, genomes, td, t0, t1, st);
-        if (rc) return rc;
-        t0 = t1;
-    }
+        return MC_OK;
+    };
+    rc = insert_all();
+    // a table still uncleared (no insert ran, or one failed first) is cleared now
+    const int rc_clear = materialize(db, st);
+    if (rc) return rc;
+    if (rc_clear) return rc_clear;
     unsigned long long c[kNumBuildCounters];
     HIP_TRY(hipMemcpyAsync(c, db->counters, sizeof c, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));

@@ -427,7 +427,7 @@ __device__ __forceinline__ void insert_slice_direct(BuildArgs& a, uint32_t* cnt,
                                                     uint32_t nbk, uint64_t p0, uint64_t p1,
                                                     uint32_t& ins, uint32_t& probe) {
     const uint32_t tid = threadIdx.x;
-    for (uint32_t i = tid; i < nbk; i += kLineThreads) cnt[i] = a.bcount[b0 + i];
+    for (uint32_t i = tid; i < nbk; i += kLineThreads) cnt[i] = a.fresh ? 0u : a.bcount[b0 + i];
     __syncthreads();
     for (uint64_t i = p0 + tid; i < p1; i += kLineThreads) {
         const unsigned long long e = a.pairs[i];
@@ -455,6 +455,17 @@ __device__ __forceinline__ void insert_slice_direct(BuildArgs& a, uint32_t* cnt,
     }
     __syncthreads();
     for (uint32_t i = tid; i < nbk; i += kLineThreads) a.bcount[b0 + i] = cnt[i];
+    if (a.fresh) {   // slots no pair claimed (disjoint from the stores above)
+        for (uint32_t i = tid; i < nbk * kSlots; i += kLineThreads)
+            if (i % kSlots >= min(cnt[i / kSlots], (uint32_t)kSlots))
+                a.table[b0 * kSlots + i] = kEmpty;
+    }
+}
+
+// A fresh slice without pairs: empty lines, zero counters.
+__device__ __forceinline__ void clear_slice(BuildArgs& a, uint64_t b0, uint32_t nbk) {
+    for (uint32_t i = threadIdx.x; i < nbk * kSlots; i += kLineThreads) a.table[b0 * kSlots + i] = kEmpty;
+    for (uint32_t i = threadIdx.x; i < nbk; i += kLineThreads) a.bcount[b0 + i] = 0u;
 }
 
 __global__ __launch_bounds__(kLineThreads) void k_insert_slices(BuildArgs a, uint32_t buf_cap,
@@ -480,7 +491,10 @@ __global__ __launch_bounds__(kLineThreads) void k_insert_slices(BuildArgs a, uin
         const uint32_t nbk = (uint32_t)(b0 + SB <= a.nb ? SB : a.nb - b0);
         const uint64_t p0 = a.slice_start[z], p1 = a.slice_start[z + 1];
         const uint32_t np = (uint32_t)(p1 - p0);
-        if (np == 0) continue;
+        if (np == 0) {
+            if (a.fresh) clear_slice(a, b0, nbk);
+            continue;
+        }
         __syncthreads();                  // LDS of the previous slice is free
         if (np > line_cap) {
             insert_slice_direct(a, cnt, b0, nbk, p0, p1, ins, probe);
@@ -492,7 +506,7 @@ __global__ __launch_bounds__(kLineThreads) void k_insert_slices(BuildArgs a, uin
         const uint32_t ln = t & 63;
         for (uint32_t i = tid; i < nbk; i += kLineThreads) {
             cnt[i] = 0u;
-            c8[i] = (uint8_t)min(a.bcount[b0 + i], (uint32_t)kSlots);
+            c8[i] = a.fresh ? (uint8_t)0 : (uint8_t)min(a.bcount[b0 + i], (uint32_t)kSlots);
         }
         __syncthreads();
         // the slice's pairs, each ranked within its home bucket
@@ -584,6 +598,14 @@ __global__ __launch_bounds__(kLineThreads) void k_insert_slices(BuildArgs a, uin
                 }
             }
         }
+        const uint32_t sl = tid & (kSlots - 1);
+        if (a.fresh) {   // buckets that gain no pair: empty lines, zero counters
+            for (uint32_t r = tid / kSlots; r < nbk; r += kLineThreads / kSlots) {
+                if (Tp[r] != (r ? Tp[r - 1] : 0u)) continue;
+                a.table[(b0 + r) * kSlots + sl] = kEmpty;
+                if (sl == 0) a.bcount[b0 + r] = 0u;
+            }
+        }
         // rounds: positions [W, W + buf_cap) staged; buckets starting in [W, W + step)
         const uint32_t step = buf_cap - kSlots;
         for (uint32_t W = 0; W < placed_all; W += step) {
@@ -592,7 +614,6 @@ __global__ __launch_bounds__(kLineThreads) void k_insert_slices(BuildArgs a, uin
             for (int k = 0; k < kLinePer; ++k)
                 if (key[k] - W < buf_cap) buf[key[k] - W] = e[k];   // kNoKey never
             __syncthreads();
-            const uint32_t sl = tid & (kSlots - 1);
             for (uint32_t r = tid / kSlots; r < nbk; r += kLineThreads / kSlots) {
                 const uint32_t st = r ? Tp[r - 1] : 0u, placed = Tp[r] - st;
                 if (placed == 0 || st - W >= step) continue;

@@ -68,6 +68,8 @@ struct BuildArgs {
     unsigned long long* cursor2;        // n_parts << fine_bits scatter cursors
     unsigned long long* chunk_first;    // [0, n_parts]: prefix of histogram chunks per
                                         // partition; [kMaxParts + 1, ...]: scatter chunks
+    uint32_t fresh;                     // slice mode: table and counters uncleared; the
+                                        // insert writes every bucket of every slice
 };
 
 constexpr uint32_t kMaxParts = 256;         // partitions (8 bits)

@@ -329,6 +329,34 @@ def test_insert_modes_agree(torch, monkeypatch, mode):
     assert_same_results(gl, gt, ol, ot)
 
 
+@pytest.mark.parametrize("mode", ["slices", "direct"])
+def test_sparse_fresh_table(torch, monkeypatch, mode):
+    """A first insert into a table far larger than its pairs (load factor
+    1e-4, so most slices hold no pair): the insert that clears the new table
+    as it writes must leave every other slot empty and every other counter
+    zero; a second add then grows the table by a rehash."""
+    for k, v in INSERT_MODES[mode].items():
+        monkeypatch.setenv(k, v)
+    g = synth.tiny_genomes(length=30_000)
+    gdb = mc.Database(16, 128, 16, 254)
+    gdb.reserve(0, 1e-4)
+    odb = orc.OracleDB(16, 128, 16, 254)
+    off = g.offsets
+    for a, b in [(0, 5), (5, g.lengths.size)]:
+        txt = g.text[int(off[a]):int(off[b])]
+        gdb.add_targets(dev_u8(torch, txt), g.lengths[a:b], g.taxa[a:b])
+        odb.add_targets(txt, g.lengths[a:b], g.taxa[a:b], threads=8)
+        of, _ = odb.dump()
+        assert gdb.stats()["n_pairs_stored"] == of.size
+    assert gdb.stats()["n_buckets"] > 1 << 20
+    gdb.set_taxonomy(g.parents)
+    odb.set_taxonomy(g.parents)
+    assert_same_table(gdb, odb)
+    reads = synth.sample_reads(g, 1000, 100, seed=5)
+    gl, gt, ol, ot = classify_both(torch, gdb, odb, reads, min_hits=1)
+    assert_same_results(gl, gt, ol, ot)
+
+
 def test_invalid_taxonomy_and_state(torch):
     db = mc.Database()
     with pytest.raises(mc.MCError):
