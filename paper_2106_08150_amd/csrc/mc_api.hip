@@ -111,7 +111,7 @@ struct mc_db {
     uint32_t* hist2 = nullptr;                  // slice-mode insert: kMaxSlices
     unsigned long long* slice_start = nullptr;  // kMaxSlices + 1
     unsigned long long* cursor2 = nullptr;      // kMaxSlices
-    unsigned long long* chunk_first = nullptr;  // 2 * (kMaxParts + 1)
+    unsigned long long* chunk_first = nullptr;  // kChunkFirstLen
     // fast-path launch shape (set by mc_db_set_launch_config / mc_db_autotune)
     ClassifyConfig cfg;
     // bumped whenever device arrays a captured graph refers to may have moved
@@ -261,13 +261,13 @@ hipError_t drain(Timed& t, double* ms, uint64_t* n) {
 
 int ensure_scratch(mc_db* db, uint64_t slots) {
     if (!db->hist) {
-        int rc = dev_alloc(&db->hist, kMaxParts);
+        int rc = dev_alloc(&db->hist, kScatGroups * kMaxParts);
         if (!rc) rc = dev_alloc(&db->part_start, kMaxParts + 1);
-        if (!rc) rc = dev_alloc(&db->cursor, kMaxParts);
+        if (!rc) rc = dev_alloc(&db->cursor, kScatGroups * kMaxParts);
         if (!rc) rc = dev_alloc(&db->hist2, kMaxSlices);
         if (!rc) rc = dev_alloc(&db->slice_start, kMaxSlices + 1);
         if (!rc) rc = dev_alloc(&db->cursor2, kMaxSlices);
-        if (!rc) rc = dev_alloc(&db->chunk_first, 2 * (kMaxParts + 1));
+        if (!rc) rc = dev_alloc(&db->chunk_first, kChunkFirstLen);
         if (rc) return rc;
     }
     if (slots <= db->pairs_cap) return MC_OK;
@@ -343,7 +343,11 @@ int build_chunk(mc_db* db, const uint8_t* genomes, const std::vector<TargetDesc>
     uint64_t* d_tf = nullptr;
     rc = dev_alloc(&d_td, n);
     if (rc) return rc;
-    rc = dev_alloc(&d_tf, n + 1);
+    // tile_first (n + 1), then the first slot of each level-1 scatter chunk
+    // and the end of the slots (written by the sketch kernel)
+    const uint32_t chunk_tiles = scatter_chunk_tiles(db->s);
+    const uint64_t n_chunks = (tile_first[n] + chunk_tiles - 1) / chunk_tiles;
+    rc = dev_alloc(&d_tf, n + 1 + n_chunks + 1);
     if (rc) { (void)hipFree(d_td); return rc; }
     struct Free {
         void* a; void* b;
@@ -351,7 +355,7 @@ int build_chunk(mc_db* db, const uint8_t* genomes, const std::vector<TargetDesc>
     } guard{d_td, d_tf};
     HIP_TRY(hipMemcpyAsync(d_td, td.data(), n * sizeof(TargetDesc), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(d_tf, tile_first.data(), (n + 1) * 8, hipMemcpyHostToDevice, st));
-    HIP_TRY(launch_fill_u32(db->hist, kMaxParts, 0u, st));
+    HIP_TRY(launch_fill_u32(db->hist, kScatGroups * kMaxParts, 0u, st));
 
     BuildArgs a{};
     a.text = genomes + off0;
@@ -361,6 +365,8 @@ int build_chunk(mc_db* db, const uint8_t* genomes, const std::vector<TargetDesc>
     a.tile_first = d_tf;
     a.n_tiles = tile_first[n];
     a.k = db->k; a.w = db->w; a.S = db->S; a.s = db->s;
+    a.chunk_tiles = chunk_tiles;
+    a.chunk_slot = d_tf + n + 1;
     a.table = db->table;
     a.bcount = db->bcount;
     a.nb = db->nb;
@@ -960,6 +966,7 @@ int mc_db_sketch(mc_db* db, const char* seqs_dev, const uint64_t* lengths, uint3
     a.tile_first = d_tf;
     a.n_tiles = tile_first[n];
     a.k = db->k; a.w = db->w; a.S = db->S; a.s = db->s;
+    a.chunk_tiles = scatter_chunk_tiles(db->s);
     a.out_counts = out_counts;
     a.out_feats = out_features;
     hipError_t e = hipMemcpyAsync(d_td, td.data(), n * sizeof(TargetDesc), hipMemcpyHostToDevice, st);

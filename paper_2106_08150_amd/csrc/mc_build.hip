@@ -22,7 +22,7 @@ struct SketchLds {
     Word words[kTileWordsMax];
     uint32_t scratch[kWavesPerBuild][kWave];
     uint32_t feats[kWavesPerBuild][2 * kMaxSketch];   // sketches of a window pair
-    uint32_t hist[kMaxParts];
+    uint32_t hist[kScatGroups * kMaxParts];
 };
 
 // Partition of a feature: its home bucket >> part_shift, so partition p holds
@@ -37,7 +37,8 @@ __device__ __forceinline__ uint32_t part_of(uint32_t f, uint64_t nb, uint32_t sh
 //   kPairs = false: out_counts[w] and out_feats[w*s ..] per window (export).
 //   kPairs = true:  pairs[w*s + i] = feature << 32 | location for i < n and
 //                   empty for n <= i < s, plus a histogram of the pairs' table
-//                   partitions.
+//                   partitions per scatter group (the group of a tile's pairs
+//                   is that of the level-1 scatter chunk holding the tile).
 template <int KPL, bool kPairs>
 __global__ __launch_bounds__(kBuildThreads) void k_sketch(BuildArgs a) {
     __shared__ SketchLds L;
@@ -45,7 +46,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_sketch(BuildArgs a) {
     const int wave = tid >> 6, lane = tid & 63;
     const uint32_t P = a.n_parts;
     if (kPairs) {
-        for (uint32_t p = tid; p < P; p += kBuildThreads) L.hist[p] = 0;
+        for (uint32_t p = tid; p < kScatGroups * kMaxParts; p += kBuildThreads) L.hist[p] = 0;
     }
     for (uint64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
         // target of this tile: last t with tile_first[t] <= tile
@@ -55,8 +56,15 @@ __global__ __launch_bounds__(kBuildThreads) void k_sketch(BuildArgs a) {
             if (a.tile_first[mid] <= tile) lo = mid; else hi = mid;
         }
         const TargetDesc td = a.targets[lo];
+        const uint32_t hbase = (uint32_t)((tile / a.chunk_tiles) % kScatGroups) * kMaxParts;
         const uint32_t j0 = (uint32_t)(tile - a.tile_first[lo]) * kTileWindows;
         const uint32_t nwin = min((uint32_t)kTileWindows, td.nw - j0);
+        if (kPairs && tid == 0) {   // slot bounds of the level-1 scatter chunks
+            if (tile % a.chunk_tiles == 0) a.chunk_slot[tile / a.chunk_tiles] = (td.win_base + j0) * a.s;
+            if (tile + 1 == a.n_tiles)
+                a.chunk_slot[(a.n_tiles + a.chunk_tiles - 1) / a.chunk_tiles] =
+                    (td.win_base + j0 + nwin) * a.s;
+        }
         const uintptr_t tstart = (uintptr_t)(a.text + td.off);
         const uintptr_t tend = tstart + td.len;
         const uintptr_t blo = tstart + (uint64_t)j0 * a.S;
@@ -93,7 +101,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_sketch(BuildArgs a) {
                     if (i < nh) {
                         const uint32_t f = sk[h * kMaxSketch + i];
                         pe = ((uint64_t)f << 32) | ((td.id << kWindowBits) | j);
-                        atomicAdd(&L.hist[part_of(f, a.nb, a.part_shift)], 1u);
+                        atomicAdd(&L.hist[hbase + part_of(f, a.nb, a.part_shift)], 1u);
                     }
                     a.pairs[gw * a.s + i] = pe;
                 } else {
@@ -106,8 +114,8 @@ __global__ __launch_bounds__(kBuildThreads) void k_sketch(BuildArgs a) {
     }
     if (kPairs) {
         __syncthreads();
-        for (uint32_t p = tid; p < P; p += kBuildThreads)
-            if (L.hist[p]) atomicAdd(&a.hist[p], L.hist[p]);
+        for (uint32_t i = tid; i < kScatGroups * kMaxParts; i += kBuildThreads)
+            if (L.hist[i]) atomicAdd(&a.hist[i], L.hist[i]);
     }
 }
 
@@ -134,22 +142,29 @@ __device__ __forceinline__ unsigned long long block_scan256(unsigned long long v
 }
 
 constexpr uint32_t kHistChunk = 65536;   // pairs per histogram chunk (slice mode)
-constexpr int kScatPer = 16;
-constexpr int kScatChunk = kBuildThreads * kScatPer;   // pairs per scatter chunk
+constexpr uint32_t kNoKey = 0xFFFFFFFFu;  // register-held entry without a key
 
 // Exclusive scan of the partition histogram (one workgroup of 256 threads):
-// part_start[p] and the scatter cursors; part_start[P] = number of pairs. In
-// slice mode also the prefix of histogram and scatter chunks per partition
-// (chunks never straddle two partitions).
+// part_start[p], and the cursor of each scatter group within partition p
+// (groups in order). In slice mode also the prefix of histogram and scatter
+// chunks per partition (chunks never straddle two partitions) and the most
+// scatter chunks of any partition.
 __global__ __launch_bounds__(kMaxParts) void k_scan_parts(BuildArgs a) {
     __shared__ unsigned long long wsum[kMaxParts / kWave];
+    __shared__ unsigned long long cmax;
     const uint32_t t = threadIdx.x, P = a.n_parts;
-    const unsigned long long v = t < P ? a.hist[t] : 0ull;
+    unsigned long long v = 0;
+    if (t < P)
+        for (uint32_t g = 0; g < kScatGroups; ++g) v += a.hist[g * kMaxParts + t];
     unsigned long long total;
     const unsigned long long excl = block_scan256(v, wsum, total);
     if (t < P) {
         a.part_start[t] = excl;
-        a.cursor[t] = excl;
+        unsigned long long run = excl;
+        for (uint32_t g = 0; g < kScatGroups; ++g) {
+            a.cursor[g * kMaxParts + t] = run;
+            run += a.hist[g * kMaxParts + t];
+        }
     }
     if (t == 0) a.part_start[P] = total;
     if (!a.slice_mode) return;
@@ -158,6 +173,10 @@ __global__ __launch_bounds__(kMaxParts) void k_scan_parts(BuildArgs a) {
     unsigned long long th, ts;
     const unsigned long long eh = block_scan256(ch, wsum, th);
     const unsigned long long es = block_scan256(cs, wsum, ts);
+    if (t == 0) cmax = 0;
+    __syncthreads();
+    if (cs) atomicMax(&cmax, cs);
+    __syncthreads();
     if (t < P) {
         a.chunk_first[t] = eh;
         a.chunk_first[kMaxParts + 1 + t] = es;
@@ -165,76 +184,106 @@ __global__ __launch_bounds__(kMaxParts) void k_scan_parts(BuildArgs a) {
     if (t == 0) {
         a.chunk_first[P] = th;
         a.chunk_first[kMaxParts + 1 + P] = ts;
+        a.chunk_first[kChunkMaxAt] = cmax;
     }
 }
 
+// Exclusive prefix sums of one u32 per thread over a kScatThreads workgroup.
+__device__ __forceinline__ uint32_t block_scan1024(uint32_t v, uint32_t* wsum, uint32_t& total) {
+    const uint32_t t = threadIdx.x, lane = t & 63, w = t >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t y = shfl_idx(x, lane >= (uint32_t)d ? (int)lane - d : (int)lane);
+        if (lane >= (uint32_t)d) x += y;
+    }
+    __syncthreads();
+    if (lane == kWave - 1) wsum[w] = x;
+    __syncthreads();
+    uint32_t base = 0;
+    total = 0;
+    for (uint32_t i = 0; i < (uint32_t)(kScatThreads / kWave); ++i) {
+        const uint32_t y = wsum[i];
+        if (i < w) base += y;
+        total += y;
+    }
+    return base + x - v;
+}
+
 struct ScatLds {
-    unsigned long long buf[kScatChunk];
-    uint8_t bin[kScatChunk];
+    unsigned long long buf[kScatChunk];   // the chunk's pairs, sorted by bin
     uint32_t hist[256], lstart[256];
     unsigned long long gbase[256];
-    unsigned long long wsum[kBuildThreads / kWave];
+    uint32_t wsum[kScatThreads / kWave];
 };
 
 // Scatter in[c0, c1) (at most kScatChunk entries; kEmpty entries are
-// skipped) into 256 or fewer bins: the workgroup sorts its entries by bin in
-// LDS, reserves one run per bin with an atomic on that bin's cursor, and
-// writes the runs out contiguously (counting sort).
+// skipped) into 256 or fewer bins: each thread holds kScatPer entries in
+// registers and ranks them within their bin with an LDS counter; the
+// workgroup reserves one run per bin with an atomic on that bin's cursor,
+// sorts the entries by bin in LDS and writes the runs out contiguously
+// (counting sort). bin_of is evaluated again for the write instead of being
+// stored.
 template <typename BinOf>
 __device__ __forceinline__ void scatter_chunk(const unsigned long long* in, uint64_t c0,
                                               uint64_t c1, BinOf bin_of,
                                               unsigned long long* cursor,
                                               unsigned long long* out, ScatLds& S) {
-    const uint32_t t = threadIdx.x;
-    S.hist[t] = 0;
+    const uint32_t n = (uint32_t)(c1 - c0);
+    if (n == 0) return;
+    uint32_t t = threadIdx.x;
+    asm volatile("" : "+v"(t));   // per-entry indices recomputed each chunk
+    if (t < 256) S.hist[t] = 0;
     __syncthreads();
     unsigned long long e[kScatPer];
-    uint32_t pos[kScatPer], pb[kScatPer];
+    uint32_t key[kScatPer];       // bin << 16 | rank within the bin, or kNoKey
+#pragma unroll
+    for (int j = 0; j < kScatPer; ++j) {   // past the end: a repeat of the last entry, no key
+        const uint32_t i = (uint32_t)j * kScatThreads + t;
+        e[j] = in[c0 + min(i, n - 1)];
+        key[j] = i < n && e[j] != kEmpty ? 0u : kNoKey;
+    }
 #pragma unroll
     for (int j = 0; j < kScatPer; ++j) {
-        const uint64_t i = c0 + (uint64_t)j * kBuildThreads + t;
-        e[j] = i < c1 ? in[i] : kEmpty;
-        pb[j] = 0;
-        pos[j] = 0;
-        if (e[j] != kEmpty) {
-            pb[j] = bin_of(e[j]);
-            pos[j] = atomicAdd(&S.hist[pb[j]], 1u);
+        if (key[j] == 0u) {
+            const uint32_t b = bin_of(e[j]);
+            key[j] = (b << 16) | atomicAdd(&S.hist[b], 1u);
         }
     }
     __syncthreads();
-    const uint32_t v = S.hist[t];   // thread t owns bin t
-    unsigned long long total;
-    const uint32_t excl = (uint32_t)block_scan256(v, S.wsum, total);
-    S.lstart[t] = excl;
-    S.gbase[t] = v ? atomicAdd(&cursor[t], (unsigned long long)v) : 0ull;
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < kScatPer; ++j) {
-        if (e[j] != kEmpty) {
-            const uint32_t d = S.lstart[pb[j]] + pos[j];
-            S.buf[d] = e[j];
-            S.bin[d] = (uint8_t)pb[j];
-        }
+    const uint32_t v = t < 256 ? S.hist[t] : 0u;
+    uint32_t total;
+    const uint32_t excl = block_scan1024(v, S.wsum, total);
+    if (t < 256) {
+        S.lstart[t] = excl;
+        S.gbase[t] = v ? atomicAdd(&cursor[t], (unsigned long long)v) : 0ull;
     }
     __syncthreads();
-    for (uint32_t i = t; i < (uint32_t)total; i += kBuildThreads) {
-        const uint32_t b = S.bin[i];
-        out[S.gbase[b] + (i - S.lstart[b])] = S.buf[i];
+#pragma unroll
+    for (int j = 0; j < kScatPer; ++j)
+        if (key[j] != kNoKey) S.buf[S.lstart[key[j] >> 16] + (key[j] & 0xFFFFu)] = e[j];
+    __syncthreads();
+    for (uint32_t i = t; i < total; i += kScatThreads) {
+        const unsigned long long x = S.buf[i];
+        const uint32_t b = bin_of(x);
+        out[S.gbase[b] + (i - S.lstart[b])] = x;
     }
     __syncthreads();
 }
 
-// Level 1: the per-window pairs into partition order (parted).
-__global__ __launch_bounds__(kBuildThreads) void k_scatter(BuildArgs a, uint64_t n_slots) {
+// Level 1: the per-window pairs into partition order (parted). Chunk m is
+// the slots of sketch tiles [m * chunk_tiles, (m + 1) * chunk_tiles) and
+// takes its runs from cursor set m % kScatGroups.
+__global__ __launch_bounds__(kScatThreads) void k_scatter(BuildArgs a) {
     __shared__ ScatLds S;
     const uint64_t nb = a.nb;
     const uint32_t sh = a.part_shift;
-    for (uint64_t c0 = (uint64_t)blockIdx.x * kScatChunk; c0 < n_slots;
-         c0 += (uint64_t)gridDim.x * kScatChunk) {
-        const uint64_t c1 = c0 + kScatChunk < n_slots ? c0 + kScatChunk : n_slots;
+    const uint64_t n_chunks = (a.n_tiles + a.chunk_tiles - 1) / a.chunk_tiles;
+    for (uint64_t m = blockIdx.x; m < n_chunks; m += gridDim.x) {
+        const uint64_t c0 = a.chunk_slot[m], c1 = a.chunk_slot[m + 1];
         scatter_chunk(a.pairs, c0, c1,
                       [=](unsigned long long e) { return part_of((uint32_t)(e >> 32), nb, sh); },
-                      a.cursor, a.parted, S);
+                      a.cursor + (m % kScatGroups) * kMaxParts, a.parted, S);
     }
 }
 
@@ -296,16 +345,20 @@ __global__ __launch_bounds__(kBuildThreads) void k_scan2(BuildArgs a) {
 }
 
 // Slice mode, level 2: parted (partition order) into slice order (pairs).
-__global__ __launch_bounds__(kBuildThreads) void k_scatter2(BuildArgs a) {
+// Work item q is chunk q / P of partition q % P, so the chunks in flight
+// belong to different partitions and reserve their runs on different cursors.
+__global__ __launch_bounds__(kScatThreads) void k_scatter2(BuildArgs a) {
     __shared__ ScatLds S;
     const uint32_t P = a.n_parts;
     const unsigned long long* first = a.chunk_first + kMaxParts + 1;
-    const uint64_t n_chunks = first[P];
+    const uint64_t n_items = a.chunk_first[kChunkMaxAt] * P;
     const uint64_t nb = a.nb;
     const uint32_t sh = a.slice_shift, mask = (1u << a.fine_bits) - 1u;
-    for (uint64_t ci = blockIdx.x; ci < n_chunks; ci += gridDim.x) {
-        const uint32_t p = chunk_part(first, P, ci);
-        const uint64_t c0 = a.part_start[p] + (ci - first[p]) * kScatChunk;
+    for (uint64_t q = blockIdx.x; q < n_items; q += gridDim.x) {
+        const uint32_t p = (uint32_t)(q % P);
+        const uint64_t r = q / P;
+        if (r >= first[p + 1] - first[p]) continue;
+        const uint64_t c0 = a.part_start[p] + r * kScatChunk;
         const uint64_t end = a.part_start[p + 1];
         const uint64_t c1 = c0 + kScatChunk < end ? c0 + kScatChunk : end;
         scatter_chunk(a.parted, c0, c1,
@@ -412,7 +465,6 @@ constexpr int kLineThreads = 1024;
 constexpr int kLineWaves = kLineThreads / kWave;
 constexpr int kLinePer = 24;                        // pairs per thread held in registers
 constexpr uint32_t kLineCap = (uint32_t)kLineThreads * kLinePer;
-constexpr uint32_t kNoKey = 0xFFFFFFFFu;
 static_assert(kLineCap < 0x10000, "sorted positions are kept in 16 bits");
 
 __device__ __forceinline__ void defer_pair(BuildArgs& a, unsigned long long e) {
@@ -857,8 +909,9 @@ hipError_t launch_partition(const BuildArgs& a, uint64_t n_slots, hipStream_t st
     hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kMaxParts), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || n_slots == 0) return e;
-    hipLaunchKernelGGL(k_scatter, dim3(grid_for(n_slots, kScatChunk, 8192)), dim3(kBuildThreads),
-                       0, st, a, n_slots);
+    const uint64_t n_chunks = (a.n_tiles + a.chunk_tiles - 1) / a.chunk_tiles;
+    hipLaunchKernelGGL(k_scatter, dim3(grid_for(n_chunks, 1, 8192)), dim3(kScatThreads), 0, st,
+                       a);
     e = hipGetLastError();
     if (e != hipSuccess || !a.slice_mode) return e;
     const uint64_t pairs_bound = n_slots;   // chunks: at most one partial per partition
@@ -870,7 +923,7 @@ hipError_t launch_partition(const BuildArgs& a, uint64_t n_slots, hipStream_t st
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_scatter2, dim3(grid_for(pairs_bound, kScatChunk, 8192)),
-                       dim3(kBuildThreads), 0, st, a);
+                       dim3(kScatThreads), 0, st, a);
     return hipGetLastError();
 }
 

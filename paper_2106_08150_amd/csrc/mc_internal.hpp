@@ -55,9 +55,13 @@ struct BuildArgs {
     unsigned long long* parted;         // pairs in partition order
     uint32_t part_shift;                // partition of a pair: home bucket >> part_shift
     uint32_t n_parts;                   // partitions (<= kMaxParts)
-    uint32_t* hist;                     // n_parts counters
+    uint32_t chunk_tiles;               // sketch tiles per level-1 scatter chunk
+    uint64_t* chunk_slot;               // first slot of each level-1 scatter chunk, then
+                                        // the end of the slots (n_chunks + 1)
+    uint32_t* hist;                     // pairs per (scatter group g, partition p) at
+                                        // g * kMaxParts + p
     unsigned long long* part_start;     // n_parts + 1 offsets
-    unsigned long long* cursor;         // n_parts scatter cursors
+    unsigned long long* cursor;         // scatter cursor of (g, p) at g * kMaxParts + p
     // slice mode: partitions split into 2^fine_bits slices of 2^slice_shift
     // buckets each; a workgroup inserts one slice's pairs with LDS counters
     uint32_t slice_mode;
@@ -67,18 +71,33 @@ struct BuildArgs {
     unsigned long long* slice_start;    // (n_parts << fine_bits) + 1 offsets
     unsigned long long* cursor2;        // n_parts << fine_bits scatter cursors
     unsigned long long* chunk_first;    // [0, n_parts]: prefix of histogram chunks per
-                                        // partition; [kMaxParts + 1, ...]: scatter chunks
+                                        // partition; [kMaxParts + 1, ...]: scatter chunks;
+                                        // [kChunkMaxAt]: most scatter chunks of a partition
     uint32_t fresh;                     // slice mode: table and counters uncleared; the
                                         // insert writes every bucket of every slice
 };
 
 constexpr uint32_t kMaxParts = 256;         // partitions (8 bits)
+// Level-1 scatter chunks are spread over kScatGroups cursor sets (chunk m
+// uses set m % kScatGroups), so the chunks in flight do not all serialise on
+// the same 256 atomics.
+constexpr uint32_t kScatGroups = 8;
+constexpr uint32_t kChunkFirstLen = 2 * (kMaxParts + 1) + 1;
+constexpr uint32_t kChunkMaxAt = 2 * (kMaxParts + 1);
 constexpr uint32_t kMaxSliceShift = 13;     // slice of at most 8192 buckets (32 KiB counters)
 constexpr uint32_t kMinSliceShift = 10;
 constexpr uint32_t kMaxSlices = 65536;      // kMaxParts << 8
 
 constexpr int kTileWindows = 32;  // windows per build workgroup tile
 constexpr int kBuildThreads = 256;
+constexpr int kScatThreads = 1024;                     // scatter workgroup (one per CU)
+constexpr int kScatPer = 16;                           // pairs per thread held in registers
+constexpr int kScatChunk = kScatThreads * kScatPer;    // most pairs of a scatter chunk
+// Sketch tiles per level-1 scatter chunk (a tile holds at most 32 * s slots).
+inline uint32_t scatter_chunk_tiles(uint32_t s) {
+    const uint32_t c = (uint32_t)kScatChunk / ((uint32_t)kTileWindows * s);
+    return c ? c : 1u;
+}
 
 // Query-side counters (device, u32).
 enum QueryCounter {
