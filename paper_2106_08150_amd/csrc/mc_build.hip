@@ -44,7 +44,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_sketch(BuildArgs a) {
     __shared__ SketchLds L;
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
-    const uint32_t P = a.n_parts;
+    const Threshold th(a.S, a.s);
     if (kPairs) {
         for (uint32_t p = tid; p < kScatGroups * kMaxParts; p += kBuildThreads) L.hist[p] = 0;
     }
@@ -86,7 +86,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_sketch(BuildArgs a) {
             }
             uint32_t* sk = L.feats[wave];
             uint32_t n[2];
-            sketch_pair<KPL>(L.words, x0[0], nk[0], L.words, x0[1], nk[1], a.k, a.s, sk,
+            sketch_pair<KPL>(L.words, x0[0], nk[0], L.words, x0[1], nk[1], a.k, a.s, th, sk,
                              sk + kMaxSketch, L.scratch[wave], n[0], n[1]);
             wave_lds_sync();
             // entry e of the pair: window e / s, sketch slot e % s

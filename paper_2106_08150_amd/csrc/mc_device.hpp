@@ -336,6 +336,18 @@ __device__ __forceinline__ uint32_t hash_threshold(float expect, uint32_t nk) {
     return t >= 4294967040.0f ? 0xFFFFFFFFu : (uint32_t)t;
 }
 
+// Candidate threshold of sketch_pair (hash_threshold of 1.5 s): computed once
+// for the full window of S k-mers, divided out only for shorter windows.
+struct Threshold {
+    uint32_t S, tS;
+    __device__ __forceinline__ Threshold(uint32_t S_, uint32_t s)
+        : S(S_), tS(hash_threshold(1.5f * (float)s, S_)) {}
+    __device__ __forceinline__ uint32_t of(uint32_t nk, uint32_t s) const {
+        if (nk == S) return tS;
+        return hash_threshold(1.5f * (float)s, nk);
+    }
+};
+
 // h1 of the canonical k-mers of one window whose nk k-mer starts begin x0
 // bases after the first staged word: key[r] belongs to k-mer r*64 + lane and is
 // 0xFFFFFFFF for an invalid k-mer or past nk. Returns whether some valid k-mer
@@ -464,14 +476,15 @@ __device__ __forceinline__ void wave_sort_halves(uint32_t& v) {
 // sketched on its own. Returns the number of entries written.
 template <int KPL>
 __device__ __forceinline__ uint32_t half_candidates(const uint32_t (&key)[KPL], uint32_t nk,
-                                                    uint32_t s, uint32_t* half, int& mode) {
+                                                    uint32_t s, const Threshold& th,
+                                                    uint32_t* half, int& mode) {
     const int lane = lane_id();
     if (nk <= 32u) {
         if (lane < 32) half[lane] = key[0];
         mode = 0;
         return 32u;
     }
-    const uint32_t T = hash_threshold(1.5f * (float)s, nk);
+    const uint32_t T = th.of(nk, s);
     uint64_t bal[KPL];
     uint32_t c = 0;
 #pragma unroll
@@ -502,7 +515,8 @@ __device__ __forceinline__ uint32_t half_candidates(const uint32_t (&key)[KPL], 
 template <int KPL>
 __device__ __forceinline__ void sketch_pair(const Word* WA, uint32_t xA, uint32_t nkA,
                                             const Word* WB, uint32_t xB, uint32_t nkB,
-                                            uint32_t k, uint32_t s, uint32_t* skA, uint32_t* skB,
+                                            uint32_t k, uint32_t s, const Threshold& th,
+                                            uint32_t* skA, uint32_t* skB,
                                             uint32_t* scratch, uint32_t& nA, uint32_t& nB) {
     const int lane = lane_id();
     int modeA, modeB;
@@ -511,9 +525,9 @@ __device__ __forceinline__ void sketch_pair(const Word* WA, uint32_t xA, uint32_
     {
         uint32_t key[KPL];
         topA = window_keys<KPL>(WA, xA, nkA, k, key);
-        cA = half_candidates<KPL>(key, nkA, s, scratch, modeA);
+        cA = half_candidates<KPL>(key, nkA, s, th, scratch, modeA);
         topB = window_keys<KPL>(WB, xB, nkB, k, key);
-        cB = half_candidates<KPL>(key, nkB, s, scratch + 32, modeB);
+        cB = half_candidates<KPL>(key, nkB, s, th, scratch + 32, modeB);
     }
     wave_lds_sync();
     const uint32_t hl = (uint32_t)lane & 31u;

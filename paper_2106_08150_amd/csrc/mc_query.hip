@@ -270,7 +270,7 @@ struct WaveStats {
 
 template <uint32_t LCAP, int KPL>
 __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>& L, bool big,
-                                WaveStats& ws) {
+                                const Threshold& th, WaveStats& ws) {
     const int lane = lane_id();
     uint64_t o0, o1, o2;
     if (a.paired) {
@@ -303,7 +303,8 @@ __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>
         wave_lds_sync();
         uint32_t nA, nB;
         sketch_pair<KPL>(L.sk.stage, wr[0].x0, wr[0].nk, L.sk.stage + kStageWords, wr[1].x0, wr[1].nk,
-                         a.k, a.s, L.sk.feats + nf, L.sk.feats + nf + a.s, L.sk.scratch, nA, nB);
+                         a.k, a.s, th, L.sk.feats + nf, L.sk.feats + nf + a.s, L.sk.scratch, nA,
+                         nB);
         wave_lds_sync();
         if (nA < a.s && nB) {      // close the gap after A's features
             const uint32_t f = (uint32_t)lane < nB ? L.sk.feats[nf + a.s + lane] : 0u;
@@ -443,9 +444,10 @@ void k_classify(QueryArgs a, int big) {
     wave_lds_sync();
     const uint32_t n_iter = big ? uniform(a.counters[kQOverflow]) : a.n_records;
     WaveStats ws;
+    const Threshold th(a.S, a.s);
     for (uint32_t it = blockIdx.x * WPB + wave; it < n_iter; it += gridDim.x * WPB) {
         const uint32_t rec = big ? uniform(a.queue[it]) : it;
-        classify_record<LCAP, KPL>(a, rec, L[wave], big != 0, ws);
+        classify_record<LCAP, KPL>(a, rec, L[wave], big != 0, th, ws);
     }
     // work of records that go on to the large-list pass counts in both passes
     if (lane_id() == 0 && a.qstats) {
