@@ -282,8 +282,12 @@ int mc_server_submit(mc_server* srv, const char* reads, const uint64_t* offsets,
                      uint32_t n_records, const mc_query_opts* opts, uint32_t* out_labels,
                      mc_tophit* out_top, uint32_t flags, uint64_t* ticket);
 
-/* Queue a genome addition (as mc_db_add_targets, host buffers copied before
- * return) optionally followed by a taxonomy replacement (parents may be NULL). */
+/* Queue a genome addition (as mc_db_add_targets) optionally followed by a
+ * taxonomy replacement (parents may be NULL). genomes/lengths/taxon_ids/parents
+ * are HOST buffers owned by the caller and are not copied: they must stay
+ * valid until mc_server_wait returns for the ticket (or the server is
+ * destroyed). The addition runs after every earlier batch has finished and
+ * before any later one starts. */
 int mc_server_add_targets(mc_server* srv, const char* genomes, const uint64_t* lengths,
                           const uint32_t* taxon_ids, uint32_t n, const uint32_t* parents,
                           uint32_t n_nodes, uint64_t* ticket);

@@ -448,7 +448,7 @@ class Server:
         _check(lib().mc_server_add_targets(self.h, _np_ptr(g), _np_ptr(L), _np_ptr(x), L.size,
                                            _np_ptr(p) if p is not None else None,
                                            0 if p is None else p.size, C.byref(t)))
-        self._jobs[t.value] = None
+        self._jobs[t.value] = ("add", g, L, x, p)   # the server reads them in place
         return t.value
 
     def wait(self, ticket: int):
@@ -456,7 +456,7 @@ class Server:
         rc = lib().mc_server_wait(self.h, ticket, C.byref(ms))
         job = self._jobs.pop(ticket, None)
         _check(rc)
-        if job is None:
+        if job is None or isinstance(job[0], str):   # an addition
             return None, None, ms.value
         _, _, labels, top, n = job
         return labels[:n], (top[:n] if top is not None else None), ms.value

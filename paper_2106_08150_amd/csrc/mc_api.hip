@@ -101,6 +101,10 @@ struct mc_db {
     mc_db_stats st{};
     // per-stream query workspaces
     std::map<hipStream_t, Workspace> ws;
+    // queues a stream's workspace outgrew: work still queued may use them, and
+    // freeing them now would wait for the whole device (every stream), so they
+    // are freed with the handle
+    std::vector<uint32_t*> retired;
     // build scratch (grow-only): per-window pairs, partitioned pairs, partition data
     unsigned long long* pairs = nullptr;
     unsigned long long* parted = nullptr;
@@ -494,12 +498,11 @@ Workspace* workspace(mc_db* db, hipStream_t st, uint64_t n_records, int* rc) {
         }
     }
     if (n_records > w.queue_cap) {
-        (void)hipStreamSynchronize(st);   // the old queue may still be in use on st
-        if (w.queue) (void)hipFree(w.queue);
-        w.queue = nullptr;
-        w.queue_cap = 0;
-        uint64_t c = std::max<uint64_t>(n_records, 1024);
-        if ((*rc = dev_alloc(&w.queue, c))) return nullptr;
+        uint32_t* q = nullptr;
+        const uint64_t c = std::max<uint64_t>(std::max<uint64_t>(n_records, 1024), 2 * w.queue_cap);
+        if ((*rc = dev_alloc(&q, c))) return nullptr;
+        if (w.queue) db->retired.push_back(w.queue);
+        w.queue = q;
         w.queue_cap = c;
     }
     return &w;
@@ -692,6 +695,7 @@ int mc_db_destroy(mc_db* db) {
         (void)hipFree(kv.second.counters);
         (void)hipFree(kv.second.qstats);
     }
+    for (uint32_t* q : db->retired) (void)hipFree(q);
     for (auto& t : db->timers) (void)drain(t, nullptr, nullptr);
     (void)hipFree(db->pairs);
     (void)hipFree(db->parted);

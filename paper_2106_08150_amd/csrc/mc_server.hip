@@ -34,11 +34,14 @@ struct Job {
     uint64_t bytes = 0;          // read bytes
     bool pinned = false;         // reads are in pinned host memory
     uint64_t dev_need = 0;       // device bytes while in flight
-    // genome addition (copied)
-    std::vector<char> genomes;
-    std::vector<uint64_t> lengths;
-    std::vector<uint32_t> taxa;
-    std::vector<uint32_t> parents;
+    uint64_t order = 0;          // admission order (the order of the batches' copies in)
+    // genome addition (caller's host buffers, valid until its ticket is waited on)
+    const char* genomes = nullptr;
+    const uint64_t* lengths = nullptr;
+    const uint32_t* taxa = nullptr;
+    uint32_t n_targets = 0;
+    const uint32_t* parents = nullptr;
+    uint32_t n_nodes = 0;
     Clock::time_point t_submit;
 };
 
@@ -51,6 +54,7 @@ struct Done {
 // pinned staging. The dispatcher hands it one batch at a time.
 struct Slot {
     hipStream_t stream = nullptr;
+    hipEvent_t copied = nullptr; // its batch's reads are on the device
     char* d_buf = nullptr;
     uint64_t d_cap = 0;
     char* h_buf = nullptr;       // pinned
@@ -77,6 +81,15 @@ struct mc_server {
     std::map<uint64_t, Done> done;
     std::mutex mu;               // queue, slots' ownership, results, stats
     std::mutex launch_mu;        // calls into the database
+    // Reads are copied in one batch at a time, in admission order, on one copy
+    // stream: a batch's transfer gets the whole host link, as in plain
+    // back-to-back launches, while classification and the copies out of
+    // earlier batches overlap it on the slots' streams.
+    hipStream_t copy_stream = nullptr;
+    std::mutex copy_mu;
+    std::condition_variable copy_cv;
+    uint64_t copy_turn = 0;      // order of the next batch to copy in
+    uint64_t next_order = 0;
     std::condition_variable cv_queue, cv_done, cv_slot;
     bool stopping = false;
     uint64_t next_ticket = 1;
@@ -122,13 +135,44 @@ struct mc_server {
             s.h_cap = 0;
             if (hipHostMalloc((void**)&s.h_buf, cap, hipHostMallocDefault) != hipSuccess)
                 return MC_ERR_OOM;
+            // touch every page now: a page's first write otherwise faults in the
+            // batch that reaches it (about 1.5 us a 4-KiB page, milliseconds a batch)
+            std::memset(s.h_buf, 0, cap);
             s.h_cap = cap;
         }
         return MC_OK;
     }
 
     // Stage, copy in, classify, copy out and hand back one batch (worker thread).
+    // A batch's turn on the copy stream: taken once, on every path (a batch
+    // that fails before its copy still passes the turn on).
+    struct CopyTurn {
+        mc_server& srv;
+        uint64_t order;
+        bool passed = false;
+        void wait() {
+            std::unique_lock<std::mutex> lk(srv.copy_mu);
+            srv.copy_cv.wait(lk, [&] { return srv.copy_turn == order; });
+        }
+        void pass() {
+            if (passed) return;
+            passed = true;
+            {
+                std::lock_guard<std::mutex> lk(srv.copy_mu);
+                srv.copy_turn += 1;
+            }
+            srv.copy_cv.notify_all();
+        }
+        ~CopyTurn() {
+            if (!passed) {
+                wait();
+                pass();
+            }
+        }
+    };
+
     int process(Slot& s, Job& j) {
+        CopyTurn turn{*this, j.order};
         const uint64_t seg = (j.opts.paired ? 2ull : 1ull) * j.n;   // offsets - 1
         const uint64_t base = j.offsets[0];
         const uint64_t rb = j.offsets[seg] - base;
@@ -141,16 +185,20 @@ struct mc_server {
         if (rc != MC_OK) return rc;
         uint64_t* ho = reinterpret_cast<uint64_t*>(s.h_buf + off_offsets);
         for (uint64_t i = 0; i <= seg; ++i) ho[i] = j.offsets[i] - base;
+        if (!j.pinned) std::memcpy(s.h_buf, j.reads + base, rb);
         hipError_t e;
+        turn.wait();
         if (j.pinned) {   // direct DMA from the caller's pinned buffer
-            e = hipMemcpyAsync(s.d_buf, j.reads + base, rb, hipMemcpyHostToDevice, s.stream);
+            e = hipMemcpyAsync(s.d_buf, j.reads + base, rb, hipMemcpyHostToDevice, copy_stream);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(s.d_buf + off_offsets, s.h_buf + off_offsets,
-                                   off_labels - off_offsets, hipMemcpyHostToDevice, s.stream);
+                                   off_labels - off_offsets, hipMemcpyHostToDevice, copy_stream);
         } else {
-            std::memcpy(s.h_buf, j.reads + base, rb);
-            e = hipMemcpyAsync(s.d_buf, s.h_buf, off_labels, hipMemcpyHostToDevice, s.stream);
+            e = hipMemcpyAsync(s.d_buf, s.h_buf, off_labels, hipMemcpyHostToDevice, copy_stream);
         }
+        if (e == hipSuccess) e = hipEventRecord(s.copied, copy_stream);
+        turn.pass();
+        if (e == hipSuccess) e = hipStreamWaitEvent(s.stream, s.copied, 0);
         if (e != hipSuccess) return MC_ERR_HIP;
         {
             std::lock_guard<std::mutex> lk(launch_mu);
@@ -193,10 +241,9 @@ struct mc_server {
         int rc;
         {
             std::lock_guard<std::mutex> lk(launch_mu);
-            rc = mc_db_add_targets(db, j.genomes.data(), j.lengths.data(), j.taxa.data(),
-                                   (uint32_t)j.lengths.size());
-            if (rc == MC_OK && !j.parents.empty())
-                rc = mc_db_set_taxonomy(db, j.parents.data(), (uint32_t)j.parents.size());
+            rc = mc_db_add_targets(db, j.genomes, j.lengths, j.taxa, j.n_targets);
+            if (rc == MC_OK && j.parents && j.n_nodes)
+                rc = mc_db_set_taxonomy(db, j.parents, j.n_nodes);
         }
         std::lock_guard<std::mutex> lk(mu);
         finish_locked(j, rc);
@@ -227,6 +274,7 @@ struct mc_server {
                 return free_slot &&
                        (inflight_bytes + j.dev_need <= budget || busy_slots == 0);
             });
+            j.order = next_order++;
             free_slot->busy = true;
             free_slot->has_job = true;
             inflight_bytes += j.dev_need;
@@ -262,9 +310,10 @@ mc_server* mc_server_create(mc_db* db, const mc_server_opts* opts) {
     s->budget = opts && opts->memory_budget ? opts->memory_budget : free_b / 4;
     s->slots = std::vector<Slot>(s->n_slots);
     if (opts && opts->staging_bytes) s->staging = opts->staging_bytes;
-    bool ok = true;
+    bool ok = hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking) == hipSuccess;
     for (auto& sl : s->slots) {
         ok = ok && hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess;
+        ok = ok && hipEventCreateWithFlags(&sl.copied, hipEventDisableTiming) == hipSuccess;
         ok = ok && mc_server::grow(sl, s->staging) == MC_OK;
     }
     (void)hipSetDevice(prev);
@@ -326,10 +375,12 @@ int mc_server_add_targets(mc_server* srv, const char* genomes, const uint64_t* l
     uint64_t total = 0;
     for (uint32_t i = 0; i < n; ++i) total += lengths[i];
     if (total && !genomes) return mc::set_error(MC_ERR_INVALID_ARG, "genomes is NULL");
-    j.genomes.assign(genomes, genomes + total);
-    j.lengths.assign(lengths, lengths + n);
-    j.taxa.assign(taxon_ids, taxon_ids + n);
-    if (parents && n_nodes) j.parents.assign(parents, parents + n_nodes);
+    j.genomes = genomes;
+    j.lengths = lengths;
+    j.taxa = taxon_ids;
+    j.n_targets = n;
+    j.parents = n_nodes ? parents : nullptr;
+    j.n_nodes = parents ? n_nodes : 0;
     j.t_submit = Clock::now();
     std::lock_guard<std::mutex> lk(srv->mu);
     j.ticket = srv->next_ticket++;
@@ -401,6 +452,11 @@ int mc_server_destroy(mc_server* srv) {
         (void)hipFree(s.d_buf);
         (void)hipHostFree(s.h_buf);
         if (s.stream) (void)hipStreamDestroy(s.stream);
+        if (s.copied) (void)hipEventDestroy(s.copied);
+    }
+    if (srv->copy_stream) {
+        (void)hipStreamSynchronize(srv->copy_stream);
+        (void)hipStreamDestroy(srv->copy_stream);
     }
     (void)hipSetDevice(prev);
     delete srv;
