@@ -42,7 +42,13 @@ int fail(int code, const char* fmt, ...) {
     } while (0)
 
 constexpr double kDefaultLoad = 0.5;
-constexpr uint64_t kMaxSlotsPerChunk = 1ull << 30;      // pair slots per build chunk (8 GiB)
+// Pair slots of one build chunk (16 bytes each: the pairs and their
+// partitioned copy): about 60% of the device memory free at the add, within
+// [kMinChunkSlots, kMaxChunkSlots], so that a reference set that fits builds
+// in one pass over the table's slices. Build scratch larger than an eighth of
+// the device's memory is released when the add returns.
+constexpr uint64_t kMinChunkSlots = 1ull << 26;
+constexpr uint64_t kMaxChunkSlots = 1ull << 32;
 constexpr uint64_t kPartBytes = 256ull << 20;           // target table bytes per partition
 constexpr uint64_t kMinBuckets = 64;
 constexpr uint64_t kCandCapMax = 1ull << 24;
@@ -293,19 +299,31 @@ uint32_t ceil_log2(uint64_t x) {
 }
 
 // Partitioning of the insert pass. Slice mode (the default): slices of
-// 2^slice_shift buckets (at least 1024, at most 65536 slices, counters fit
-// LDS), 2^fine_bits slices per partition, at most 256 partitions. Otherwise
+// 2^slice_shift buckets (at most kMaxSlices = 2^18 slices), 2^fine_bits
+// slices per partition (at most 1024), at most 256 partitions. Otherwise
 // (tables too large for that, or MC_INSERT=global) partitions of about
 // kPartBytes of table each (MC_PART_MB overrides) with global counters.
 void plan_partitions(const mc_db* db, BuildArgs& a) {
     const uint64_t nb = db->nb;
     const uint32_t lg = ceil_log2(nb);
-    const uint32_t sb = std::max<uint32_t>(kMinSliceShift, lg > 16 ? lg - 16 : 0);
+    // slices of 2^11 buckets (about 16K pairs at load 0.5) from 2^27 buckets up,
+    // 2^10 below; larger only past 2^29 buckets (256 x 1024 slices)
+    uint32_t sb = std::max<uint32_t>(kMinSliceShift, std::min<uint32_t>(11, lg > 16 ? lg - 16 : 0));
+    sb = std::max<uint32_t>(sb, lg > 8 + kMaxFineBits ? lg - 8 - kMaxFineBits : 0);
+    // test overrides: a slice size, and the slice bits taken by level 2
+    if (const char* env = getenv("MC_SLICE_SHIFT")) {
+        const long v = atol(env);
+        if (v >= 4 && v <= (long)kMaxSliceShift) sb = (uint32_t)v;
+    }
     const char* mode = getenv("MC_INSERT");
     const bool global = mode && std::string(mode) == "global";
-    if (!global && slice_mode_fits(sb)) {
+    if (!global && slice_mode_fits(sb) && lg <= sb + 8 + kMaxFineBits) {
         const uint32_t ns_bits = lg > sb ? lg - sb : 0;       // slices: 2^ns_bits >= nb >> sb
-        const uint32_t fb = ns_bits > 8 ? ns_bits - 8 : 0;
+        uint32_t fb = ns_bits > 8 ? ns_bits - 8 : 0;
+        if (const char* env = getenv("MC_FINE_BITS")) {
+            const long v = atol(env);
+            if (v >= (long)fb && v <= (long)std::min<uint32_t>(ns_bits, kMaxFineBits)) fb = (uint32_t)v;
+        }
         a.slice_mode = 1;
         a.slice_shift = sb;
         a.fine_bits = fb;
@@ -439,12 +457,22 @@ int add_targets_dev(mc_db* db, const uint8_t* genomes, const uint64_t* lengths,
     if (rc) return rc;
     auto insert_all = [&]() -> int {
         HIP_TRY(launch_fill_u64(db->counters, kNumBuildCounters, 0ull, st));
-        // chunks of whole targets with at most kMaxSlotsPerChunk pair slots
+        // chunks of whole targets with at most max_chunk pair slots
+        uint64_t max_chunk = kMinChunkSlots;
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) {
+            const uint64_t avail = (uint64_t)free_b + db->pairs_cap * 16;   // held scratch is reused
+            max_chunk = std::min(kMaxChunkSlots, std::max(kMinChunkSlots, avail / 16 / 10 * 6));
+        }
+        if (const char* env = getenv("MC_CHUNK_SLOTS")) {   // test override: small chunks
+            const long long v = atoll(env);
+            if (v > 0) max_chunk = (uint64_t)v;
+        }
         for (uint32_t t0 = 0; t0 < n;) {
             uint32_t t1 = t0;
             uint64_t slots = 0;
             while (t1 < n &&
-                   (t1 == t0 || slots + (uint64_t)td[t1].nw * db->s <= kMaxSlotsPerChunk)) {
+                   (t1 == t0 || slots + (uint64_t)td[t1].nw * db->s <= max_chunk)) {
                 slots += (uint64_t)td[t1].nw * db->s;
                 ++t1;
             }
@@ -477,6 +505,14 @@ int add_targets_dev(mc_db* db, const uint8_t* genomes, const uint64_t* lengths,
     db->st.n_pairs_inserted += c[kCntInserted];
     db->st.probe_sum += c[kCntProbe];
     db->st.n_cap_candidates += c[kCntCand];
+    size_t free_b = 0, total_b = 0;
+    if (db->pairs_cap && hipMemGetInfo(&free_b, &total_b) == hipSuccess &&
+        db->pairs_cap * 16 > (uint64_t)total_b / 8) {
+        HIP_TRY(hipFree(db->pairs));
+        HIP_TRY(hipFree(db->parted));
+        db->pairs = db->parted = nullptr;
+        db->pairs_cap = 0;
+    }
     return MC_OK;
 }
 

@@ -210,15 +210,18 @@ __device__ __forceinline__ uint32_t block_scan1024(uint32_t v, uint32_t* wsum, u
     return base + x - v;
 }
 
+constexpr uint32_t kMaxBins = 1u << kMaxFineBits;   // bins of one scatter (>= kMaxParts)
+static_assert(kMaxBins >= kMaxParts && kMaxBins <= (uint32_t)kScatThreads, "one thread a bin");
+
 struct ScatLds {
     unsigned long long buf[kScatChunk];   // the chunk's pairs, sorted by bin
-    uint32_t hist[256], lstart[256];
-    unsigned long long gbase[256];
+    uint32_t hist[kMaxBins], lstart[kMaxBins];
+    unsigned long long gbase[kMaxBins];
     uint32_t wsum[kScatThreads / kWave];
 };
 
 // Scatter in[c0, c1) (at most kScatChunk entries; kEmpty entries are
-// skipped) into 256 or fewer bins: each thread holds kScatPer entries in
+// skipped) into nbins <= kMaxBins bins: each thread holds kScatPer entries in
 // registers and ranks them within their bin with an LDS counter; the
 // workgroup reserves one run per bin with an atomic on that bin's cursor,
 // sorts the entries by bin in LDS and writes the runs out contiguously
@@ -226,14 +229,14 @@ struct ScatLds {
 // stored.
 template <typename BinOf>
 __device__ __forceinline__ void scatter_chunk(const unsigned long long* in, uint64_t c0,
-                                              uint64_t c1, BinOf bin_of,
+                                              uint64_t c1, BinOf bin_of, uint32_t nbins,
                                               unsigned long long* cursor,
                                               unsigned long long* out, ScatLds& S) {
     const uint32_t n = (uint32_t)(c1 - c0);
     if (n == 0) return;
     uint32_t t = threadIdx.x;
     asm volatile("" : "+v"(t));   // per-entry indices recomputed each chunk
-    if (t < 256) S.hist[t] = 0;
+    if (t < nbins) S.hist[t] = 0;
     __syncthreads();
     unsigned long long e[kScatPer];
     uint32_t key[kScatPer];       // bin << 16 | rank within the bin, or kNoKey
@@ -251,10 +254,10 @@ __device__ __forceinline__ void scatter_chunk(const unsigned long long* in, uint
         }
     }
     __syncthreads();
-    const uint32_t v = t < 256 ? S.hist[t] : 0u;
+    const uint32_t v = t < nbins ? S.hist[t] : 0u;
     uint32_t total;
     const uint32_t excl = block_scan1024(v, S.wsum, total);
-    if (t < 256) {
+    if (t < nbins) {
         S.lstart[t] = excl;
         S.gbase[t] = v ? atomicAdd(&cursor[t], (unsigned long long)v) : 0ull;
     }
@@ -283,7 +286,7 @@ __global__ __launch_bounds__(kScatThreads) void k_scatter(BuildArgs a) {
         const uint64_t c0 = a.chunk_slot[m], c1 = a.chunk_slot[m + 1];
         scatter_chunk(a.pairs, c0, c1,
                       [=](unsigned long long e) { return part_of((uint32_t)(e >> 32), nb, sh); },
-                      a.cursor + (m % kScatGroups) * kMaxParts, a.parted, S);
+                      a.n_parts, a.cursor + (m % kScatGroups) * kMaxParts, a.parted, S);
     }
 }
 
@@ -305,7 +308,7 @@ __device__ __forceinline__ uint32_t fine_of(unsigned long long e, uint64_t nb, u
 
 // Slice mode, level 2 histogram: pairs per slice within each partition.
 __global__ __launch_bounds__(kBuildThreads) void k_hist2(BuildArgs a) {
-    __shared__ uint32_t h[256];
+    __shared__ uint32_t h[kMaxBins];
     const uint32_t t = threadIdx.x, P = a.n_parts;
     const uint32_t mask = (1u << a.fine_bits) - 1u;
     const uint64_t n_chunks = a.chunk_first[P];
@@ -314,12 +317,13 @@ __global__ __launch_bounds__(kBuildThreads) void k_hist2(BuildArgs a) {
         const uint64_t c0 = a.part_start[p] + (ci - a.chunk_first[p]) * kHistChunk;
         const uint64_t end = a.part_start[p + 1];
         const uint64_t c1 = c0 + kHistChunk < end ? c0 + kHistChunk : end;
-        h[t] = 0;
+        for (uint32_t b = t; b <= mask; b += kBuildThreads) h[b] = 0;
         __syncthreads();
         for (uint64_t i = c0 + t; i < c1; i += kBuildThreads)
             atomicAdd(&h[fine_of(a.parted[i], a.nb, a.slice_shift, mask)], 1u);
         __syncthreads();
-        if (t <= mask && h[t]) atomicAdd(&a.hist2[(p << a.fine_bits) + t], h[t]);
+        for (uint32_t b = t; b <= mask; b += kBuildThreads)
+            if (h[b]) atomicAdd(&a.hist2[(p << a.fine_bits) + b], h[b]);
         __syncthreads();
     }
 }
@@ -363,7 +367,7 @@ __global__ __launch_bounds__(kScatThreads) void k_scatter2(BuildArgs a) {
         const uint64_t c1 = c0 + kScatChunk < end ? c0 + kScatChunk : end;
         scatter_chunk(a.parted, c0, c1,
                       [=](unsigned long long e) { return fine_of(e, nb, sh, mask); },
-                      a.cursor2 + ((uint64_t)p << a.fine_bits), a.pairs, S);
+                      mask + 1u, a.cursor2 + ((uint64_t)p << a.fine_bits), a.pairs, S);
     }
 }
 
@@ -456,9 +460,10 @@ __global__ __launch_bounds__(kBuildThreads) void k_insert(BuildArgs a,
 // r, the pairs carried past bucket r are carry(r) = max(0, carry(r-1) + d(r)),
 // a max-plus scan across the slice, and buckets <= r hold the first
 // N(r) - carry(r) pairs in home order (N = inclusive count). The placed pairs
-// are staged in LDS in home order and every bucket that gains pairs is
-// written as one whole 128-byte line (old slots, new pairs, empty slots), so
-// the table sees full-line writes only. Pairs carried past the slice end are
+// are staged in LDS in home order. In a new table every bucket is written as
+// one whole 128-byte line (its new pairs, then empty slots), so the table
+// sees full-line writes only; in a table that holds entries only the slots
+// that gain pairs are written. Pairs carried past the slice end are
 // deferred to the global pass (k_insert). A slice with more pairs than the
 // registers hold takes the direct path: LDS fill counters, one store a pair.
 constexpr int kLineThreads = 1024;
@@ -669,21 +674,24 @@ __global__ __launch_bounds__(kLineThreads) void k_insert_slices(BuildArgs a, uin
             for (uint32_t r = tid / kSlots; r < nbk; r += kLineThreads / kSlots) {
                 const uint32_t st = r ? Tp[r - 1] : 0u, placed = Tp[r] - st;
                 if (placed == 0 || st - W >= step) continue;
+                // a new table's line is written whole (new pairs, then empty
+                // slots); in a table that holds entries only the new pairs'
+                // slots are written (old slots stay, empty ones are empty)
                 const uint32_t c = c8[r];
-                unsigned long long* slot = a.table + (b0 + r) * kSlots + sl;
+                if (sl < c) continue;
                 unsigned long long v = kEmpty;
-                if (sl < c) {
-                    v = *slot;
-                } else if (sl - c < placed) {
+                if (sl - c < placed) {
                     v = buf[st - W + sl - c];
                     const uint32_t f = (uint32_t)(v >> 32);
                     const uint32_t dist = r - (uint32_t)(home_bucket(f, a.nb) - b0);
                     ins += 1;
                     probe += dist;
                     if (dist >= a.cap_dist) push_candidate(a, f);
+                } else if (!a.fresh) {
+                    continue;
                 }
-                *slot = v;
-                if (sl == 0) a.bcount[b0 + r] = c + placed;
+                a.table[(b0 + r) * kSlots + sl] = v;
+                if (sl == c) a.bcount[b0 + r] = c + placed;
             }
         }
     }

@@ -78,6 +78,7 @@ struct BuildArgs {
 };
 
 constexpr uint32_t kMaxParts = 256;         // partitions (8 bits)
+constexpr uint32_t kMaxFineBits = 10;       // slices per partition: at most 1024
 // Level-1 scatter chunks are spread over kScatGroups cursor sets (chunk m
 // uses set m % kScatGroups), so the chunks in flight do not all serialise on
 // the same 256 atomics.
@@ -86,7 +87,7 @@ constexpr uint32_t kChunkFirstLen = 2 * (kMaxParts + 1) + 1;
 constexpr uint32_t kChunkMaxAt = 2 * (kMaxParts + 1);
 constexpr uint32_t kMaxSliceShift = 13;     // slice of at most 8192 buckets (32 KiB counters)
 constexpr uint32_t kMinSliceShift = 10;
-constexpr uint32_t kMaxSlices = 65536;      // kMaxParts << 8
+constexpr uint32_t kMaxSlices = kMaxParts << kMaxFineBits;
 
 constexpr int kTileWindows = 32;  // windows per build workgroup tile
 constexpr int kBuildThreads = 256;

@@ -251,6 +251,82 @@ def scale_genomes(seed: int = 201, total_bp: float = 4.0e9, progress=None) -> Ge
     return clustered_genomes(100, 10, total_bp, seed, level1=20, progress=progress)
 
 
+def _large_cluster(args) -> None:
+    """Worker of :func:`large_genomes`: cluster c written into the shared text."""
+    name, size, seed, c, spans, divs = args
+    from multiprocessing import shared_memory
+    shm = shared_memory.SharedMemory(name=name)
+    try:
+        text = np.ndarray((size,), dtype=np.uint8, buffer=shm.buf)
+        rng = rng_for(seed * 1_000_003 + c)
+        root = random_text(rng, max(L for _, L in spans))
+        for (o, L), d in zip(spans, divs):
+            dst = text[o:o + L]
+            dst[:] = root[:L]
+            substitute_inplace(rng, dst, d)
+        del text, dst
+    finally:
+        shm.close()
+
+
+_KEEP_SHM = []   # shared blocks backing large_genomes() texts (live for the process)
+
+
+def large_genomes(seed: int = 501, total_bp: float = 3.0e10, n_clusters: int = 750,
+                  per_cluster: int = 10, div_lo: float = 0.01, div_hi: float = 0.20,
+                  level1: int = 150, workers: int = 16, progress=None) -> Genomes:
+    """The large reference set: 7,500 genomes = 750 clusters x 10 (about 30 Gbp),
+    divergence U[1%, 20%], lengths and taxonomy as :func:`clustered_genomes`.
+    Cluster c is drawn from its own seed, so the text does not depend on the
+    number of worker processes. Workers are forked: call this before the
+    process touches a GPU."""
+    import multiprocessing as mp
+    from multiprocessing import shared_memory
+    rng = rng_for(seed)
+    n = n_clusters * per_cluster
+    raw = np.exp(rng.normal(np.log(4e6), 0.4, size=n))
+    raw = np.clip(raw, 1e6, 1e7)
+    lengths = np.maximum(np.round(raw * (total_bp / raw.sum())), 1).astype(np.int64)
+    divs = rng.uniform(div_lo, div_hi, size=n)
+    l1_base = 1
+    cl_base = l1_base + level1
+    sub_base = cl_base + n_clusters
+    leaf_base = sub_base + 3 * n_clusters
+    parents = np.zeros(leaf_base + n, dtype=np.uint32)
+    taxa = np.zeros(n, dtype=np.uint32)
+    order, leaf_parent = [], {}
+    for c in range(n_clusters):
+        parents[cl_base + c] = l1_base + (c * level1) // n_clusters
+        ids = np.arange(c * per_cluster, (c + 1) * per_cluster)
+        for j, grp in enumerate(np.array_split(np.arange(per_cluster), 3)):
+            parents[sub_base + 3 * c + j] = cl_base + c
+            for m in grp:
+                gid = int(ids[m])
+                order.append(gid)
+                parents[leaf_base + gid] = sub_base + 3 * c + j
+                taxa[gid] = leaf_base + gid
+    order = np.array(order)
+    out_len = lengths[order]
+    off = np.zeros(n + 1, dtype=np.uint64)
+    np.cumsum(out_len, out=off[1:])
+    size = int(off[-1])
+    shm = shared_memory.SharedMemory(create=True, size=max(size, 1))
+    _KEEP_SHM.append(shm)
+    pos_of = {int(g): i for i, g in enumerate(order)}
+    jobs = []
+    for c in range(n_clusters):
+        ids = range(c * per_cluster, (c + 1) * per_cluster)
+        spans = [(int(off[pos_of[g]]), int(lengths[g])) for g in ids]
+        jobs.append((shm.name, size, seed, c, spans, [float(divs[g]) for g in ids]))
+    with mp.get_context("fork").Pool(workers) as pool:
+        for i, _ in enumerate(pool.imap_unordered(_large_cluster, jobs, chunksize=4)):
+            if progress is not None and i % 50 == 49:
+                progress(f"clusters {i + 1}/{n_clusters}")
+    shm.unlink()   # the mapping stays valid in this process
+    text = np.ndarray((size,), dtype=np.uint8, buffer=shm.buf)
+    return Genomes(text, out_len.astype(np.uint64), taxa[order], parents)
+
+
 def scale_reads(genomes: Genomes, n: int = 10_000_000, seed: int = 202, progress=None) -> Reads:
     """150 bp reads, 1% substitutions, 5% foreign."""
     return sample_reads(genomes, n, 150, seed, error=0.01, foreign=0.05, progress=progress)

@@ -308,6 +308,8 @@ INSERT_MODES = {
     "staged": {"MC_SLICE_STAGE": "512"},
     "direct": {"MC_SLICE_DIRECT": "0"},
     "global": {"MC_INSERT": "global", "MC_PART_MB": "1"},
+    "fine1024": {"MC_SLICE_SHIFT": "5", "MC_FINE_BITS": "10"},
+    "chunks": {"MC_CHUNK_SLOTS": "20000"},
 }
 
 
@@ -316,9 +318,12 @@ def test_insert_modes_agree(torch, monkeypatch, mode):
     """Every insert path stores the oracle's pairs, over two add calls (the
     second fills buckets the first left partly full): the slice-local insert
     (default), the same with a 512-pair staging buffer (many rounds a slice),
-    its direct path (LDS fill counters, one store a pair), and the
+    its direct path (LDS fill counters, one store a pair), the
     global-counter insert used for tables too large for LDS slices (1 MiB
-    partitions)."""
+    partitions), slices of 32 buckets with 1024 slices per partition (the
+    largest level-2 scatter, as the largest tables use), and an add built in
+    chunks of about 20,000 pair slots (every chunk after the first inserts
+    into a table that already holds entries)."""
     for k, v in INSERT_MODES[mode].items():
         monkeypatch.setenv(k, v)
     g = synth.clustered_genomes(4, 5, 2e6, seed=47, median_bp=1e5, clip=(3e3, 3e5))
