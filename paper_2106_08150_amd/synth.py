@@ -251,25 +251,19 @@ def scale_genomes(seed: int = 201, total_bp: float = 4.0e9, progress=None) -> Ge
     return clustered_genomes(100, 10, total_bp, seed, level1=20, progress=progress)
 
 
+_LARGE_TEXT = None   # shared text of large_genomes() while its workers run
+
+
 def _large_cluster(args) -> None:
     """Worker of :func:`large_genomes`: cluster c written into the shared text."""
-    name, size, seed, c, spans, divs = args
-    from multiprocessing import shared_memory
-    shm = shared_memory.SharedMemory(name=name)
-    try:
-        text = np.ndarray((size,), dtype=np.uint8, buffer=shm.buf)
-        rng = rng_for(seed * 1_000_003 + c)
-        root = random_text(rng, max(L for _, L in spans))
-        for (o, L), d in zip(spans, divs):
-            dst = text[o:o + L]
-            dst[:] = root[:L]
-            substitute_inplace(rng, dst, d)
-        del text, dst
-    finally:
-        shm.close()
-
-
-_KEEP_SHM = []   # shared blocks backing large_genomes() texts (live for the process)
+    seed, c, spans, divs = args
+    text = _LARGE_TEXT
+    rng = rng_for(seed * 1_000_003 + c)
+    root = random_text(rng, max(L for _, L in spans))
+    for (o, L), d in zip(spans, divs):
+        dst = text[o:o + L]
+        dst[:] = root[:L]
+        substitute_inplace(rng, dst, d)
 
 
 def large_genomes(seed: int = 501, total_bp: float = 3.0e10, n_clusters: int = 750,
@@ -280,8 +274,9 @@ def large_genomes(seed: int = 501, total_bp: float = 3.0e10, n_clusters: int = 7
     Cluster c is drawn from its own seed, so the text does not depend on the
     number of worker processes. Workers are forked: call this before the
     process touches a GPU."""
+    import mmap
     import multiprocessing as mp
-    from multiprocessing import shared_memory
+    global _LARGE_TEXT
     rng = rng_for(seed)
     n = n_clusters * per_cluster
     raw = np.exp(rng.normal(np.log(4e6), 0.4, size=n))
@@ -310,20 +305,23 @@ def large_genomes(seed: int = 501, total_bp: float = 3.0e10, n_clusters: int = 7
     off = np.zeros(n + 1, dtype=np.uint64)
     np.cumsum(out_len, out=off[1:])
     size = int(off[-1])
-    shm = shared_memory.SharedMemory(create=True, size=max(size, 1))
-    _KEEP_SHM.append(shm)
+    # anonymous shared mapping: the forked workers write into it in place
+    buf = mmap.mmap(-1, max(size, 1), flags=mmap.MAP_SHARED | mmap.MAP_ANONYMOUS)
+    text = np.frombuffer(buf, dtype=np.uint8, count=size)
     pos_of = {int(g): i for i, g in enumerate(order)}
     jobs = []
     for c in range(n_clusters):
         ids = range(c * per_cluster, (c + 1) * per_cluster)
         spans = [(int(off[pos_of[g]]), int(lengths[g])) for g in ids]
-        jobs.append((shm.name, size, seed, c, spans, [float(divs[g]) for g in ids]))
-    with mp.get_context("fork").Pool(workers) as pool:
-        for i, _ in enumerate(pool.imap_unordered(_large_cluster, jobs, chunksize=4)):
-            if progress is not None and i % 50 == 49:
-                progress(f"clusters {i + 1}/{n_clusters}")
-    shm.unlink()   # the mapping stays valid in this process
-    text = np.ndarray((size,), dtype=np.uint8, buffer=shm.buf)
+        jobs.append((seed, c, spans, [float(divs[g]) for g in ids]))
+    _LARGE_TEXT = text
+    try:
+        with mp.get_context("fork").Pool(workers) as pool:
+            for i, _ in enumerate(pool.imap_unordered(_large_cluster, jobs, chunksize=4)):
+                if progress is not None and i % 50 == 49:
+                    progress(f"clusters {i + 1}/{n_clusters}")
+    finally:
+        _LARGE_TEXT = None
     return Genomes(text, out_len.astype(np.uint64), taxa[order], parents)
 
 
