@@ -220,58 +220,80 @@ struct ScatLds {
     uint32_t wsum[kScatThreads / kWave];
 };
 
-// Scatter in[c0, c1) (at most kScatChunk entries; kEmpty entries are
-// skipped) into nbins <= kMaxBins bins: each thread holds kScatPer entries in
-// registers and ranks them within their bin with an LDS counter; the
-// workgroup reserves one run per bin with an atomic on that bin's cursor,
-// sorts the entries by bin in LDS and writes the runs out contiguously
-// (counting sort). bin_of is evaluated again for the write instead of being
-// stored.
-template <typename BinOf>
-__device__ __forceinline__ void scatter_chunk(const unsigned long long* in, uint64_t c0,
-                                              uint64_t c1, BinOf bin_of, uint32_t nbins,
-                                              unsigned long long* cursor,
-                                              unsigned long long* out, ScatLds& S) {
-    const uint32_t n = (uint32_t)(c1 - c0);
-    if (n == 0) return;
-    uint32_t t = threadIdx.x;
-    asm volatile("" : "+v"(t));   // per-entry indices recomputed each chunk
-    if (t < nbins) S.hist[t] = 0;
-    __syncthreads();
+// One chunk of a scatter: entries in[c0, c1) (1 <= c1 - c0 <= kScatChunk) and
+// the cursors of its bins.
+struct ScatChunk {
+    uint64_t c0, c1;
+    unsigned long long* cursor;
+};
+
+// A chunk's entries into registers, kScatPer a thread (past the end: a repeat
+// of the last entry).
+__device__ __forceinline__ void scat_load(const unsigned long long* in, const ScatChunk& c,
+                                          uint32_t t, unsigned long long (&e)[kScatPer]) {
+    const uint32_t n = (uint32_t)(c.c1 - c.c0);
+#pragma unroll
+    for (int j = 0; j < kScatPer; ++j) e[j] = in[c.c0 + min((uint32_t)j * kScatThreads + t, n - 1)];
+}
+
+// Scatter the chunks that next() yields (kEmpty entries are skipped) into
+// nbins <= kMaxBins bins: each thread holds kScatPer entries in registers and
+// ranks them within their bin with an LDS counter; the workgroup reserves one
+// run per bin with an atomic on that bin's cursor, sorts the entries by bin in
+// LDS and writes the runs out contiguously (counting sort). The cursor atomics
+// are in flight while the chunk is sorted into LDS, and the next chunk's loads
+// while this one is written out. bin_of is evaluated again for the write
+// instead of being stored.
+template <typename NextFn, typename BinOf>
+__device__ __forceinline__ void scatter_chunks(const unsigned long long* in, NextFn next,
+                                               BinOf bin_of, uint32_t nbins,
+                                               unsigned long long* out, ScatLds& S) {
+    const uint32_t t = threadIdx.x;
+    ScatChunk cur;
+    bool have = next(cur);
     unsigned long long e[kScatPer];
-    uint32_t key[kScatPer];       // bin << 16 | rank within the bin, or kNoKey
+    if (have) scat_load(in, cur, t, e);
+    while (have) {
+        ScatChunk nxt;
+        const bool have_next = next(nxt);
+        const uint32_t n = (uint32_t)(cur.c1 - cur.c0);
+        if (t < nbins) S.hist[t] = 0;
+        __syncthreads();                   // also: the previous chunk's write-out is done
+        uint32_t key[kScatPer];            // bin << 16 | rank within the bin, or kNoKey
 #pragma unroll
-    for (int j = 0; j < kScatPer; ++j) {   // past the end: a repeat of the last entry, no key
-        const uint32_t i = (uint32_t)j * kScatThreads + t;
-        e[j] = in[c0 + min(i, n - 1)];
-        key[j] = i < n && e[j] != kEmpty ? 0u : kNoKey;
-    }
+        for (int j = 0; j < kScatPer; ++j)
+            key[j] = (uint32_t)j * kScatThreads + t < n && e[j] != kEmpty ? 0u : kNoKey;
 #pragma unroll
-    for (int j = 0; j < kScatPer; ++j) {
-        if (key[j] == 0u) {
-            const uint32_t b = bin_of(e[j]);
-            key[j] = (b << 16) | atomicAdd(&S.hist[b], 1u);
+        for (int j = 0; j < kScatPer; ++j) {
+            if (key[j] == 0u) {
+                const uint32_t b = bin_of(e[j]);
+                key[j] = (b << 16) | atomicAdd(&S.hist[b], 1u);
+            }
         }
-    }
-    __syncthreads();
-    const uint32_t v = t < nbins ? S.hist[t] : 0u;
-    uint32_t total;
-    const uint32_t excl = block_scan1024(v, S.wsum, total);
-    if (t < nbins) {
-        S.lstart[t] = excl;
-        S.gbase[t] = v ? atomicAdd(&cursor[t], (unsigned long long)v) : 0ull;
-    }
-    __syncthreads();
+        __syncthreads();
+        const uint32_t v = t < nbins ? S.hist[t] : 0u;
+        uint32_t total;
+        const uint32_t excl = block_scan1024(v, S.wsum, total);
+        unsigned long long g = 0ull;
+        if (t < nbins) {
+            S.lstart[t] = excl;
+            if (v) g = atomicAdd(&cur.cursor[t], (unsigned long long)v);
+        }
+        __syncthreads();
 #pragma unroll
-    for (int j = 0; j < kScatPer; ++j)
-        if (key[j] != kNoKey) S.buf[S.lstart[key[j] >> 16] + (key[j] & 0xFFFFu)] = e[j];
-    __syncthreads();
-    for (uint32_t i = t; i < total; i += kScatThreads) {
-        const unsigned long long x = S.buf[i];
-        const uint32_t b = bin_of(x);
-        out[S.gbase[b] + (i - S.lstart[b])] = x;
+        for (int j = 0; j < kScatPer; ++j)
+            if (key[j] != kNoKey) S.buf[S.lstart[key[j] >> 16] + (key[j] & 0xFFFFu)] = e[j];
+        if (t < nbins) S.gbase[t] = g;
+        __syncthreads();
+        if (have_next) scat_load(in, nxt, t, e);
+        for (uint32_t i = t; i < total; i += kScatThreads) {
+            const unsigned long long x = S.buf[i];
+            const uint32_t b = bin_of(x);
+            out[S.gbase[b] + (i - S.lstart[b])] = x;
+        }
+        cur = nxt;
+        have = have_next;
     }
-    __syncthreads();
 }
 
 // Level 1: the per-window pairs into partition order (parted). Chunk m is
@@ -282,12 +304,21 @@ __global__ __launch_bounds__(kScatThreads) void k_scatter(BuildArgs a) {
     const uint64_t nb = a.nb;
     const uint32_t sh = a.part_shift;
     const uint64_t n_chunks = (a.n_tiles + a.chunk_tiles - 1) / a.chunk_tiles;
-    for (uint64_t m = blockIdx.x; m < n_chunks; m += gridDim.x) {
-        const uint64_t c0 = a.chunk_slot[m], c1 = a.chunk_slot[m + 1];
-        scatter_chunk(a.pairs, c0, c1,
-                      [=](unsigned long long e) { return part_of((uint32_t)(e >> 32), nb, sh); },
-                      a.n_parts, a.cursor + (m % kScatGroups) * kMaxParts, a.parted, S);
-    }
+    uint64_t m = blockIdx.x;
+    auto next = [&](ScatChunk& c) -> bool {
+        for (; m < n_chunks; m += gridDim.x) {
+            const uint64_t c0 = a.chunk_slot[m], c1 = a.chunk_slot[m + 1];
+            if (c1 > c0) {
+                c = ScatChunk{c0, c1, a.cursor + (m % kScatGroups) * kMaxParts};
+                m += gridDim.x;
+                return true;
+            }
+        }
+        return false;
+    };
+    scatter_chunks(a.pairs, next,
+                   [=](unsigned long long e) { return part_of((uint32_t)(e >> 32), nb, sh); },
+                   a.n_parts, a.parted, S);
 }
 
 // Partition of chunk ci of the prefix first[0..P] (first[P] = number of chunks).
@@ -358,17 +389,26 @@ __global__ __launch_bounds__(kScatThreads) void k_scatter2(BuildArgs a) {
     const uint64_t n_items = a.chunk_first[kChunkMaxAt] * P;
     const uint64_t nb = a.nb;
     const uint32_t sh = a.slice_shift, mask = (1u << a.fine_bits) - 1u;
-    for (uint64_t q = blockIdx.x; q < n_items; q += gridDim.x) {
-        const uint32_t p = (uint32_t)(q % P);
-        const uint64_t r = q / P;
-        if (r >= first[p + 1] - first[p]) continue;
-        const uint64_t c0 = a.part_start[p] + r * kScatChunk;
-        const uint64_t end = a.part_start[p + 1];
-        const uint64_t c1 = c0 + kScatChunk < end ? c0 + kScatChunk : end;
-        scatter_chunk(a.parted, c0, c1,
-                      [=](unsigned long long e) { return fine_of(e, nb, sh, mask); },
-                      mask + 1u, a.cursor2 + ((uint64_t)p << a.fine_bits), a.pairs, S);
-    }
+    uint64_t q = blockIdx.x;
+    auto next = [&](ScatChunk& c) -> bool {
+        for (; q < n_items; q += gridDim.x) {
+            const uint32_t p = (uint32_t)(q % P);
+            const uint64_t r = q / P;
+            if (r >= first[p + 1] - first[p]) continue;
+            const uint64_t c0 = a.part_start[p] + r * kScatChunk;
+            const uint64_t end = a.part_start[p + 1];
+            const uint64_t c1 = c0 + kScatChunk < end ? c0 + kScatChunk : end;
+            if (c1 > c0) {
+                c = ScatChunk{c0, c1, a.cursor2 + ((uint64_t)p << a.fine_bits)};
+                q += gridDim.x;
+                return true;
+            }
+        }
+        return false;
+    };
+    scatter_chunks(a.parted, next,
+                   [=](unsigned long long e) { return fine_of(e, nb, sh, mask); }, mask + 1u,
+                   a.pairs, S);
 }
 
 // Insert one entry (B5). Every bucket has a fill counter; an insert claims
