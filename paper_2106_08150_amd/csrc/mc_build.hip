@@ -350,8 +350,19 @@ __global__ __launch_bounds__(kBuildThreads) void k_hist2(BuildArgs a) {
         const uint64_t c1 = c0 + kHistChunk < end ? c0 + kHistChunk : end;
         for (uint32_t b = t; b <= mask; b += kBuildThreads) h[b] = 0;
         __syncthreads();
-        for (uint64_t i = c0 + t; i < c1; i += kBuildThreads)
-            atomicAdd(&h[fine_of(a.parted[i], a.nb, a.slice_shift, mask)], 1u);
+        constexpr int U = 8;   // independent loads in flight a thread
+        for (uint64_t i0 = c0 + t; i0 < c1; i0 += U * kBuildThreads) {
+            unsigned long long x[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint64_t i = i0 + (uint64_t)u * kBuildThreads;
+                x[u] = a.parted[i < c1 ? i : c1 - 1];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (i0 + (uint64_t)u * kBuildThreads < c1)
+                    atomicAdd(&h[fine_of(x[u], a.nb, a.slice_shift, mask)], 1u);
+        }
         __syncthreads();
         for (uint32_t b = t; b <= mask; b += kBuildThreads)
             if (h[b]) atomicAdd(&a.hist2[(p << a.fine_bits) + b], h[b]);
