@@ -707,11 +707,13 @@ __global__ __launch_bounds__(kLineThreads) void k_insert_slices(BuildArgs a, uin
             }
         }
         const uint32_t sl = tid & (kSlots - 1);
+        unsigned long long* const tab = a.table + b0 * kSlots;   // the slice's lines
+        uint32_t* const cnt_out = a.bcount + b0;
         if (a.fresh) {   // buckets that gain no pair: empty lines, zero counters
             for (uint32_t r = tid / kSlots; r < nbk; r += kLineThreads / kSlots) {
                 if (Tp[r] != (r ? Tp[r - 1] : 0u)) continue;
-                a.table[(b0 + r) * kSlots + sl] = kEmpty;
-                if (sl == 0) a.bcount[b0 + r] = 0u;
+                tab[r * kSlots + sl] = kEmpty;
+                if (sl == 0) cnt_out[r] = 0u;
             }
         }
         // rounds: positions [W, W + buf_cap) staged; buckets starting in [W, W + step)
@@ -733,16 +735,22 @@ __global__ __launch_bounds__(kLineThreads) void k_insert_slices(BuildArgs a, uin
                 unsigned long long v = kEmpty;
                 if (sl - c < placed) {
                     v = buf[st - W + sl - c];
-                    const uint32_t f = (uint32_t)(v >> 32);
-                    const uint32_t dist = r - (uint32_t)(home_bucket(f, a.nb) - b0);
                     ins += 1;
-                    probe += dist;
-                    if (dist >= a.cap_dist) push_candidate(a, f);
+                    // nothing carried into r (the first pair placed there is the
+                    // first homed there): its pairs are all homed at r, distance 0
+                    if (st != (uint32_t)Te[r]) {
+                        const uint32_t f = (uint32_t)(v >> 32);
+                        const uint32_t dist = r - (uint32_t)(home_bucket(f, a.nb) - b0);
+                        probe += dist;
+                        if (dist >= a.cap_dist) push_candidate(a, f);
+                    } else if (a.cap_dist == 0) {   // caps of 1..15: every insert is a candidate
+                        push_candidate(a, (uint32_t)(v >> 32));
+                    }
                 } else if (!a.fresh) {
                     continue;
                 }
-                a.table[(b0 + r) * kSlots + sl] = v;
-                if (sl == c) a.bcount[b0 + r] = c + placed;
+                tab[r * kSlots + sl] = v;
+                if (sl == c) cnt_out[r] = c + placed;
             }
         }
     }
