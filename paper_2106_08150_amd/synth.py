@@ -276,7 +276,12 @@ def large_genomes(seed: int = 501, total_bp: float = 3.0e10, n_clusters: int = 7
     process touches a GPU."""
     import mmap
     import multiprocessing as mp
+    import sys
     global _LARGE_TEXT
+    torch = sys.modules.get("torch")
+    if torch is not None and torch.cuda.is_initialized():
+        raise RuntimeError("large_genomes forks worker processes: call it before the process "
+                           "touches a GPU")
     rng = rng_for(seed)
     n = n_clusters * per_cluster
     raw = np.exp(rng.normal(np.log(4e6), 0.4, size=n))
