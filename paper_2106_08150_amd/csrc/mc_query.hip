@@ -59,26 +59,30 @@ struct QueryLds {
 // encoding: vmcnt bits 3..0 and 15..14, expcnt 6..4, lgkmcnt 11..8).
 constexpr int kWaitVmem0 = 0x0F70;
 
-// Lanes 15, 31, 47 and 63: the last slot of the bucket each 16-lane group reads.
-constexpr uint64_t kLastSlots = 0x8000800080008000ull;
+// Lanes 7, 15, ..., 63: the lanes holding the last slot of the bucket each
+// 8-lane group reads.
+constexpr uint64_t kLastSlots = 0x8080808080808080ull;
 
 // Append the locations of features F[0..nf) to list (LDS). A work item is a
-// (feature, bucket) pair; the wave takes up to 4 * NB items at a time, item
-// 4q + g read by 16-lane group g as one 128-byte bucket line (lane = slot), so
-// that NB lines per group are in flight. Slots of a bucket fill in order, so
-// a bucket is full exactly when its last slot is occupied: a full bucket
-// queues the feature's next bucket as a new item, and a feature's chain ends
-// at its first bucket that is not full (inserts never pass such a bucket).
-// Items wait in a ring in LDS, at most one per feature; every ring entry
-// always holds some item of the launch (the ring is cleared to bucket 0 when a
-// wave starts), so groups past a batch's last item may read any entry and
-// their lines are simply ignored. Returns false once the list outgrew LCAP.
+// (feature, bucket) pair; the wave takes up to 8 * NB items at a time, item
+// 8q + g read by 8-lane group g as one 128-byte bucket line (16 bytes, two
+// slots, a lane), so that NB lines per group are in flight. Slots of a bucket
+// fill in order, so a bucket is full exactly when its last slot is occupied:
+// a full bucket queues the feature's next bucket as a new item, and a
+// feature's chain ends at its first bucket that is not full (inserts never
+// pass such a bucket). Items wait in a ring in LDS, at most one per feature;
+// every ring entry always holds some item of the launch (the ring is cleared
+// to bucket 0 when a wave starts), so groups past a batch's last item may read
+// any entry and their lines are simply ignored. Returns false once the list
+// outgrew LCAP (locations past LCAP + 64 are then not stored: the record goes
+// to the large-list pass).
 template <uint32_t LCAP>
 __device__ bool lookup(const QueryArgs& a, const uint32_t* F, uint32_t nf, uint2* ring,
                        uint32_t* list, uint32_t& nlist, uint32_t& probes) {
-    constexpr int NB = 8;
+    constexpr int NB = 4;
+    constexpr uint32_t G = 8;            // groups of 8 lanes, one bucket line each
     const uint32_t lane = (uint32_t)lane_id();
-    const uint32_t g = lane >> 4;
+    const uint32_t g = lane >> 3;
     const uint32_t nb = (uint32_t)a.nb;
     for (uint32_t i = lane; i < nf; i += kWave) {
         const uint2 it = make_uint2(F[i], (uint32_t)home_bucket(F[i], a.nb));
@@ -86,45 +90,56 @@ __device__ bool lookup(const QueryArgs& a, const uint32_t* F, uint32_t nf, uint2
         if (i < kRingMirror) ring[i + kRing] = it;
     }
     wave_lds_sync();
-    const unsigned long long* slot = a.table + (lane & 15u);
+    // slots 2 (lane & 7) and 2 (lane & 7) + 1 of a bucket, as one 16-byte load
+    typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+    const u64x2* slot2 = reinterpret_cast<const u64x2*>(a.table) + (lane & 7u);
     uint32_t head = 0, tail = nf;
     while (head < tail) {
         // every line issued so far has been used; saying so here lets this
         // batch's loads go out back to back (the compiler cannot tell which
         // of the previous batch's loads were issued)
         __builtin_amdgcn_s_waitcnt(kWaitVmem0);
-        const uint32_t c = min(tail - head, 4u * NB);
+        const uint32_t c = min(tail - head, G * NB);
         uint32_t f[NB], b[NB];
-        uint64_t sl[NB];
-        const uint2* batch = ring + ((head & (kRing - 1u)) + g);   // item 4q + g at batch[4q]
+        u64x2 sl[NB];
+        const uint2* batch = ring + ((head & (kRing - 1u)) + g);   // item 8q + g at batch[8q]
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
-            const uint2 it = batch[4 * q];
+            const uint2 it = batch[G * q];
             f[q] = it.x;
             b[q] = it.y;
         }
 #pragma unroll
         for (int q = 0; q < NB; ++q)
-            if (4u * q < c) sl[q] = slot[(uint64_t)b[q] * kSlots];
+            if (G * q < c) sl[q] = slot2[(uint64_t)b[q] * (kSlots / 2)];
         head += c;
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
-            if (4u * q >= c) break;
-            const uint32_t nv = min(c - 4u * q, 4u);   // groups holding an item
+            if (G * q >= c) break;
+            const uint32_t nv = min(c - G * q, G);   // groups holding an item
             probes += nv;
             const bool valid = g < nv;
-            const uint32_t hi = (uint32_t)(sl[q] >> 32), lo = (uint32_t)sl[q];
-            const bool mine = valid && hi == f[q] && lo < kTombLoc;
-            const uint64_t hit = ballot(mine);
-            if (hit) {
-                if (mine) list[rank_below(hit, nlist)] = lo;
-                nlist += popc64(hit);
+            const unsigned long long s0 = sl[q].x, s1 = sl[q].y;
+            const bool mine0 = valid && (uint32_t)(s0 >> 32) == f[q] && (uint32_t)s0 < kTombLoc;
+            const bool mine1 = valid && (uint32_t)(s1 >> 32) == f[q] && (uint32_t)s1 < kTombLoc;
+            const uint64_t hit0 = ballot(mine0), hit1 = ballot(mine1);
+            if (hit0 | hit1) {
+                const uint32_t n0 = popc64(hit0);
+                if (mine0) {
+                    const uint32_t i = rank_below(hit0, nlist);
+                    if (i < LCAP + kWave) list[i] = (uint32_t)s0;
+                }
+                if (mine1) {
+                    const uint32_t i = rank_below(hit1, nlist + n0);
+                    if (i < LCAP + kWave) list[i] = (uint32_t)s1;
+                }
+                nlist += n0 + popc64(hit1);
                 if (nlist > LCAP) return false;
             }
-            const bool occupied = valid && sl[q] != kEmpty;
+            const bool occupied = valid && s1 != kEmpty;
             const uint64_t full = ballot(occupied) & kLastSlots;
             if (full) {
-                if (occupied && (lane & 15u) == 15u) {
+                if (occupied && (lane & 7u) == 7u) {
                     const uint32_t nxt = b[q] + 1u == nb ? 0u : b[q] + 1u;
                     const uint32_t pos = (tail + rank_below(full)) & (kRing - 1u);
                     ring[pos] = make_uint2(f[q], nxt);
