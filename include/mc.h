@@ -123,9 +123,17 @@ int mc_db_reserve(mc_db* db, uint64_t n_pairs, double load_factor);
  * Targets get consecutive ids starting at the current target count, in array
  * order. The caller keeps ownership; the call is synchronous. May be called
  * again after mc_classify (on-demand addition); new targets always get larger
- * ids, so the per-feature cap keeps its meaning. On error nothing is added.
+ * ids, so the per-feature cap keeps its meaning. Argument, capacity and
+ * allocation errors are detected before the table is written: then nothing
+ * is added. MC_ERR_TABLE_FULL or MC_ERR_HIP after inserts began leave the
+ * handle with part of the call's entries: destroy it.
  * MC_ERR_CAPACITY: more than MC_MAX_TARGETS targets in total, or a sequence
- * with more than MC_MAX_WINDOWS windows. */
+ * with more than MC_MAX_WINDOWS windows.
+ * Device memory: besides the table (16 slots of 8 bytes a bucket, grown to
+ * keep the load factor), the build uses 16 bytes per pair slot (sketch_size
+ * slots a window) of its largest chunk; an add is cut into chunks of whole
+ * sequences that fit about 60% of the free device memory, and scratch larger
+ * than an eighth of the device's memory is released before the call returns. */
 int mc_db_add_targets(mc_db* db, const char* genomes, const uint64_t* lengths,
                       const uint32_t* taxon_ids, uint32_t n);
 

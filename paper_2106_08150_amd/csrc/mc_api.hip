@@ -344,12 +344,24 @@ void plan_partitions(const mc_db* db, BuildArgs& a) {
     a.n_parts = (uint32_t)(((nb - 1) >> a.part_shift) + 1);
 }
 
-// Build pipeline over targets [t0, t1) of the call (one chunk).
+// Host copies of the chunks' descriptors, kept until the call's stream work is
+// done (the uploads read them asynchronously).
+struct ChunkHost {
+    std::vector<std::vector<TargetDesc>> td;
+    std::vector<std::vector<uint64_t>> tile_first;
+};
+
+// Build pipeline over targets [t0, t1) of the call (one chunk). d_td holds
+// t1 - t0 descriptors and d_tf the tile and chunk bounds (device buffers of
+// the call, sized for its largest chunk).
 int build_chunk(mc_db* db, const uint8_t* genomes, const std::vector<TargetDesc>& all,
-                uint32_t t0, uint32_t t1, hipStream_t st) {
+                uint32_t t0, uint32_t t1, TargetDesc* d_td, uint64_t* d_tf,
+                ChunkHost& keep, hipStream_t st) {
     const uint32_t n = t1 - t0;
-    std::vector<TargetDesc> td(all.begin() + t0, all.begin() + t1);
-    std::vector<uint64_t> tile_first(n + 1, 0);
+    keep.td.emplace_back(all.begin() + t0, all.begin() + t1);
+    keep.tile_first.emplace_back(n + 1, 0);
+    std::vector<TargetDesc>& td = keep.td.back();
+    std::vector<uint64_t>& tile_first = keep.tile_first.back();
     const uint64_t off0 = td[0].off, win0 = td[0].win_base;
     for (uint32_t i = 0; i < n; ++i) {
         td[i].off -= off0;
@@ -361,20 +373,9 @@ int build_chunk(mc_db* db, const uint8_t* genomes, const std::vector<TargetDesc>
     if (slots == 0) return MC_OK;
     int rc = ensure_scratch(db, slots);
     if (rc) return rc;
-    TargetDesc* d_td = nullptr;
-    uint64_t* d_tf = nullptr;
-    rc = dev_alloc(&d_td, n);
-    if (rc) return rc;
-    // tile_first (n + 1), then the first slot of each level-1 scatter chunk
-    // and the end of the slots (written by the sketch kernel)
+    // d_tf: tile_first (n + 1), then the first slot of each level-1 scatter
+    // chunk and the end of the slots (written by the sketch kernel)
     const uint32_t chunk_tiles = scatter_chunk_tiles(db->s);
-    const uint64_t n_chunks = (tile_first[n] + chunk_tiles - 1) / chunk_tiles;
-    rc = dev_alloc(&d_tf, n + 1 + n_chunks + 1);
-    if (rc) { (void)hipFree(d_td); return rc; }
-    struct Free {
-        void* a; void* b;
-        ~Free() { (void)hipFree(a); (void)hipFree(b); }
-    } guard{d_td, d_tf};
     HIP_TRY(hipMemcpyAsync(d_td, td.data(), n * sizeof(TargetDesc), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(d_tf, tile_first.data(), (n + 1) * 8, hipMemcpyHostToDevice, st));
     HIP_TRY(launch_fill_u32(db->hist, kScatGroups * kMaxParts, 0u, st));
@@ -468,6 +469,8 @@ int add_targets_dev(mc_db* db, const uint8_t* genomes, const uint64_t* lengths,
             const long long v = atoll(env);
             if (v > 0) max_chunk = (uint64_t)v;
         }
+        std::vector<uint32_t> cuts{0};
+        uint64_t most = 0;
         for (uint32_t t0 = 0; t0 < n;) {
             uint32_t t1 = t0;
             uint64_t slots = 0;
@@ -476,10 +479,32 @@ int add_targets_dev(mc_db* db, const uint8_t* genomes, const uint64_t* lengths,
                 slots += (uint64_t)td[t1].nw * db->s;
                 ++t1;
             }
-            if (int r = build_chunk(db, genomes, td, t0, t1, st)) return r;
+            cuts.push_back(t1);
+            most = std::max(most, slots);
             t0 = t1;
         }
-        return MC_OK;
+        // every buffer the chunks use is allocated before the first insert: an
+        // allocation failure then leaves the table as it was
+        if (most == 0) return MC_OK;
+        if (int r = ensure_scratch(db, most)) return r;
+        uint64_t tiles = 0;
+        for (uint32_t i = 0; i < n; ++i) tiles += (td[i].nw + kTileWindows - 1) / kTileWindows;
+        TargetDesc* d_td = nullptr;
+        uint64_t* d_tf = nullptr;
+        if (int r = dev_alloc(&d_td, n)) return r;
+        // n + 1 tile bounds, at most tiles + 1 chunk bounds and the end, for any chunk
+        if (int r = dev_alloc(&d_tf, (uint64_t)n + tiles + 3)) { (void)hipFree(d_td); return r; }
+        ChunkHost keep;
+        keep.td.reserve(cuts.size());
+        keep.tile_first.reserve(cuts.size());
+        int r = MC_OK;
+        for (size_t c = 0; c + 1 < cuts.size() && r == MC_OK; ++c)
+            r = build_chunk(db, genomes, td, cuts[c], cuts[c + 1], d_td, d_tf, keep, st);
+        // hipFree waits for the stream work that reads d_td, d_tf and keep
+        const hipError_t e1 = hipFree(d_td), e2 = hipFree(d_tf);
+        if (r == MC_OK && (e1 != hipSuccess || e2 != hipSuccess))
+            r = fail(MC_ERR_HIP, "hipFree: %s", hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+        return r;
     };
     rc = insert_all();
     // a table still uncleared (no insert ran, or one failed first) is cleared now
