@@ -447,10 +447,14 @@ __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>
     write_result(a, rec, label, L, nsel);
 }
 
-// Seven waves per SIMD (at most 72 VGPRs): the lookups' memory latency is
-// hidden by other waves' work, so occupancy pays for a few spilled registers.
+// Occupancy: the lookups' memory latency is hidden by other waves' work, so
+// occupancy pays for a few spilled scalar registers. A 512-entry list takes
+// about 5.7 KB of LDS a wave, which holds a CU to 28 waves: seven a SIMD (at
+// most 72 VGPRs). A 256-entry list takes about 3.7 KB, so eight waves a SIMD
+// fit (64 VGPRs).
 template <uint32_t LCAP, int WPB, int KPL>
-__global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(7)))
+__global__ __launch_bounds__(WPB * 64)
+__attribute__((amdgpu_waves_per_eu(LCAP <= 256 ? 8 : 7)))
 void k_classify(QueryArgs a, int big) {
     __shared__ QueryLds<LCAP> L[WPB];
     const int wave = (int)uniform(threadIdx.x >> 6);
