@@ -111,8 +111,18 @@ const char* mc_last_error(void);
 mc_db* mc_db_create(uint32_t k, uint32_t window, uint32_t sketch_size,
                     uint32_t max_locations);
 
-/* Free every device and host resource of the handle. NULL is accepted. */
+/* Free every device and host resource of the handle. NULL is accepted.
+ * Device blocks of 256 MiB or more (the table, build scratch) are kept mapped
+ * by the library for reuse by later allocations on the same device (mapping
+ * and unmapping tens of GB costs far more than a build), as long as the kept
+ * blocks of a device stay under half its memory; an allocation that fails
+ * gives them back first. */
 int mc_db_destroy(mc_db* db);
+
+/* Give every device block the library keeps for reuse back to the runtime
+ * (all devices), e.g. before other code needs that memory. Blocks in use by
+ * live handles are not affected. Returns MC_OK, or MC_ERR_HIP. */
+int mc_release_cached_memory(void);
 
 /* Size the table for at least n_pairs stored pairs (optional; tables also
  * grow by themselves). load_factor in (0, 0.9]; 0 selects the default 0.5. */

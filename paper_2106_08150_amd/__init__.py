@@ -41,6 +41,7 @@ EXPORTS = [
     "mc_server_get_stats", "mc_server_destroy",
     "mc_db_set_launch_config", "mc_db_get_launch_config", "mc_db_autotune",
     "mc_classify_graph_create", "mc_classify_graph_launch", "mc_classify_graph_destroy",
+    "mc_release_cached_memory",
 ]
 
 
@@ -104,6 +105,7 @@ def lib():
         L.mc_db_create.restype = vp
         L.mc_db_create.argtypes = [u32, u32, u32, u32]
         L.mc_db_destroy.restype, L.mc_db_destroy.argtypes = i32, [vp]
+        L.mc_release_cached_memory.restype, L.mc_release_cached_memory.argtypes = i32, []
         L.mc_db_reserve.restype, L.mc_db_reserve.argtypes = i32, [vp, u64, C.c_double]
         L.mc_db_add_targets.restype = i32
         L.mc_db_add_targets.argtypes = [vp, vp, vp, vp, u32]
@@ -192,6 +194,10 @@ def mc_db_create(k: int = 16, window: int = 128, sketch_size: int = 16,
 
 def mc_db_destroy(db: int) -> None:
     _check(lib().mc_db_destroy(db))
+
+
+def mc_release_cached_memory() -> None:
+    _check(lib().mc_release_cached_memory())
 
 
 def mc_db_reserve(db: int, n_pairs: int, load_factor: float = 0.0) -> None:

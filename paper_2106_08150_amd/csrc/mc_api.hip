@@ -10,7 +10,9 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/mc.h"
@@ -138,12 +140,107 @@ uint64_t num_windows(uint64_t len, uint32_t k, uint32_t S) {
     return (len - k + 1 + S - 1) / S;
 }
 
+// Large device blocks are kept for reuse after they are released: hipMalloc
+// and hipFree of tens of GB cost hundreds of milliseconds to seconds once the
+// runtime stops deferring them (about 28 ms per GB to free and 4 ms per GB to
+// map), far more than the build that uses them, so a process that rebuilds
+// databases would pay that on every build. A released block of at least
+// kCacheMinBytes stays mapped (idle) while the idle blocks of its device stay
+// under half the device's memory; an allocation takes an idle block of its
+// device whose size is within 25% above the request. An allocation that fails
+// releases every idle block of the device and tries once more.
+// mc_release_cached_memory() gives all idle blocks back.
+constexpr size_t kCacheMinBytes = size_t(256) << 20;
+
+struct BlockCache {
+    std::mutex mu;
+    std::unordered_map<void*, std::pair<int, size_t>> live;   // block -> (device, bytes)
+    std::multimap<std::pair<int, size_t>, void*> idle;        // (device, bytes) -> block
+    std::map<int, size_t> idle_bytes;
+};
+
+BlockCache& block_cache() {
+    static BlockCache* c = new BlockCache;   // never destroyed: blocks outlive static teardown
+    return *c;
+}
+
+// Frees the idle blocks of `device` (every device if device < 0); the caller
+// holds the cache lock.
+void release_idle(BlockCache& c, int device) {
+    for (auto it = c.idle.begin(); it != c.idle.end();) {
+        if (device >= 0 && it->first.first != device) { ++it; continue; }
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        if (cur != it->first.first) (void)hipSetDevice(it->first.first);
+        (void)hipFree(it->second);
+        if (cur != it->first.first) (void)hipSetDevice(cur);
+        c.idle_bytes[it->first.first] -= it->first.second;
+        it = c.idle.erase(it);
+    }
+}
+
+int block_alloc(void** p, size_t bytes) {
+    *p = nullptr;
+    if (bytes < kCacheMinBytes) {
+        HIP_TRY(hipMalloc(p, bytes));
+        return MC_OK;
+    }
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    BlockCache& c = block_cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto it = c.idle.lower_bound({dev, bytes});
+    if (it != c.idle.end() && it->first.first == dev && it->first.second <= bytes + bytes / 4) {
+        *p = it->second;
+        c.live[*p] = it->first;
+        c.idle_bytes[dev] -= it->first.second;
+        c.idle.erase(it);
+        return MC_OK;
+    }
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        release_idle(c, dev);
+        HIP_TRY(hipMalloc(p, bytes));
+    }
+    c.live[*p] = {dev, bytes};
+    return MC_OK;
+}
+
 template <typename T>
 int dev_alloc(T** p, uint64_t n) {
-    *p = nullptr;
     if (n == 0) n = 1;
-    HIP_TRY(hipMalloc((void**)p, n * sizeof(T)));
-    return MC_OK;
+    void* v = nullptr;
+    const int rc = block_alloc(&v, n * sizeof(T));
+    *p = static_cast<T*>(v);
+    return rc;
+}
+
+// Release a block from dev_alloc (any other device pointer is freed). Like
+// hipFree it waits for the device first, so no queued work still uses a
+// block when it is handed out again.
+hipError_t dev_free(void* p) {
+    if (!p) return hipSuccess;
+    BlockCache& c = block_cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto it = c.live.find(p);
+    if (it == c.live.end()) return hipFree(p);
+    const std::pair<int, size_t> key = it->second;
+    c.live.erase(it);
+    size_t free_b = 0, total_b = 0;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (cur != key.first) (void)hipSetDevice(key.first);
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemGetInfo(&free_b, &total_b);
+    if (e == hipSuccess && c.idle_bytes[key.first] + key.second <= total_b / 2) {
+        c.idle.insert({key, p});
+        c.idle_bytes[key.first] += key.second;
+    } else {
+        e = hipFree(p);
+    }
+    if (cur != key.first) (void)hipSetDevice(cur);
+    return e;
 }
 
 // Make room for `extra` more occupied slots at the handle's load factor,
@@ -176,7 +273,7 @@ int ensure_capacity(mc_db* db, uint64_t extra, hipStream_t st, bool defer_fill =
     int rc = dev_alloc(&t, nb * kSlots);
     if (rc) return rc;
     rc = dev_alloc(&cnt, nb);
-    if (rc) { (void)hipFree(t); return rc; }
+    if (rc) { (void)dev_free(t); return rc; }
     const bool grow = db->table != nullptr;
     if (grow && db->touched) {
         HIP_TRY(launch_fill_u64(t, nb * kSlots, ~0ull, st));
@@ -187,8 +284,8 @@ int ensure_capacity(mc_db* db, uint64_t extra, hipStream_t st, bool defer_fill =
         HIP_TRY(hipMemcpyAsync(c, db->counters, sizeof c, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         if (c[kCntFull]) {
-            (void)hipFree(t);
-            (void)hipFree(cnt);
+            (void)dev_free(t);
+            (void)dev_free(cnt);
             return fail(MC_ERR_TABLE_FULL, "rehash found no free slot for %llu entries",
                         (unsigned long long)c[kCntFull]);
         }
@@ -205,8 +302,8 @@ int ensure_capacity(mc_db* db, uint64_t extra, hipStream_t st, bool defer_fill =
         }
     }
     if (grow) {
-        HIP_TRY(hipFree(db->table));
-        HIP_TRY(hipFree(db->bcount));
+        HIP_TRY(dev_free(db->table));
+        HIP_TRY(dev_free(db->bcount));
         db->st.n_rehash += 1;
     }
     db->bcount = cnt;
@@ -223,7 +320,7 @@ int upload_taxa(mc_db* db, hipStream_t st) {
         uint64_t c = std::max<uint64_t>(n, db->d_taxa_cap * 2);
         int rc = dev_alloc(&p, c);
         if (rc) return rc;
-        if (db->d_taxa) HIP_TRY(hipFree(db->d_taxa));
+        if (db->d_taxa) HIP_TRY(dev_free(db->d_taxa));
         db->d_taxa = p;
         db->d_taxa_cap = c;
         db->version += 1;
@@ -281,8 +378,8 @@ int ensure_scratch(mc_db* db, uint64_t slots) {
         if (rc) return rc;
     }
     if (slots <= db->pairs_cap) return MC_OK;
-    (void)hipFree(db->pairs);
-    (void)hipFree(db->parted);
+    (void)dev_free(db->pairs);
+    (void)dev_free(db->parted);
     db->pairs = db->parted = nullptr;
     db->pairs_cap = 0;
     int rc = dev_alloc(&db->pairs, slots);
@@ -447,7 +544,7 @@ int add_targets_dev(mc_db* db, const uint8_t* genomes, const uint64_t* lengths,
     int rc = MC_OK;
     uint64_t cand_need = std::min<uint64_t>(std::max<uint64_t>(upper, 1), kCandCapMax);
     if (cand_need > db->cand_cap) {
-        if (db->cand) HIP_TRY(hipFree(db->cand));
+        if (db->cand) HIP_TRY(dev_free(db->cand));
         db->cand = nullptr;
         db->cand_cap = 0;
         rc = dev_alloc(&db->cand, cand_need);
@@ -493,7 +590,7 @@ int add_targets_dev(mc_db* db, const uint8_t* genomes, const uint64_t* lengths,
         uint64_t* d_tf = nullptr;
         if (int r = dev_alloc(&d_td, n)) return r;
         // n + 1 tile bounds, at most tiles + 1 chunk bounds and the end, for any chunk
-        if (int r = dev_alloc(&d_tf, (uint64_t)n + tiles + 3)) { (void)hipFree(d_td); return r; }
+        if (int r = dev_alloc(&d_tf, (uint64_t)n + tiles + 3)) { (void)dev_free(d_td); return r; }
         ChunkHost keep;
         keep.td.reserve(cuts.size());
         keep.tile_first.reserve(cuts.size());
@@ -501,7 +598,7 @@ int add_targets_dev(mc_db* db, const uint8_t* genomes, const uint64_t* lengths,
         for (size_t c = 0; c + 1 < cuts.size() && r == MC_OK; ++c)
             r = build_chunk(db, genomes, td, cuts[c], cuts[c + 1], d_td, d_tf, keep, st);
         // hipFree waits for the stream work that reads d_td, d_tf and keep
-        const hipError_t e1 = hipFree(d_td), e2 = hipFree(d_tf);
+        const hipError_t e1 = dev_free(d_td), e2 = dev_free(d_tf);
         if (r == MC_OK && (e1 != hipSuccess || e2 != hipSuccess))
             r = fail(MC_ERR_HIP, "hipFree: %s", hipGetErrorString(e1 != hipSuccess ? e1 : e2));
         return r;
@@ -533,8 +630,8 @@ int add_targets_dev(mc_db* db, const uint8_t* genomes, const uint64_t* lengths,
     size_t free_b = 0, total_b = 0;
     if (db->pairs_cap && hipMemGetInfo(&free_b, &total_b) == hipSuccess &&
         db->pairs_cap * 16 > (uint64_t)total_b / 8) {
-        HIP_TRY(hipFree(db->pairs));
-        HIP_TRY(hipFree(db->parted));
+        HIP_TRY(dev_free(db->pairs));
+        HIP_TRY(dev_free(db->parted));
         db->pairs = db->parted = nullptr;
         db->pairs_cap = 0;
     }
@@ -640,9 +737,9 @@ int alloc_workspace(Workspace& w, uint64_t n_records, hipStream_t st) {
 }
 
 void free_workspace(Workspace& w) {
-    (void)hipFree(w.queue);
-    (void)hipFree(w.counters);
-    (void)hipFree(w.qstats);
+    (void)dev_free(w.queue);
+    (void)dev_free(w.counters);
+    (void)dev_free(w.qstats);
     w = Workspace();
 }
 
@@ -747,33 +844,42 @@ mc_db* mc_db_create(uint32_t k, uint32_t window, uint32_t sketch_size, uint32_t 
     return db;
 }
 
+int mc_release_cached_memory(void) {
+    BlockCache& c = block_cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    release_idle(c, -1);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(MC_ERR_HIP, "release of cached blocks: %s", hipGetErrorString(e));
+    return MC_OK;
+}
+
 int mc_db_destroy(mc_db* db) {
     if (!db) return MC_OK;
     DeviceGuard dg(db->device);
     (void)hipDeviceSynchronize();
     for (auto& kv : db->ws) {
-        (void)hipFree(kv.second.queue);
-        (void)hipFree(kv.second.counters);
-        (void)hipFree(kv.second.qstats);
+        (void)dev_free(kv.second.queue);
+        (void)dev_free(kv.second.counters);
+        (void)dev_free(kv.second.qstats);
     }
-    for (uint32_t* q : db->retired) (void)hipFree(q);
+    for (uint32_t* q : db->retired) (void)dev_free(q);
     for (auto& t : db->timers) (void)drain(t, nullptr, nullptr);
-    (void)hipFree(db->pairs);
-    (void)hipFree(db->parted);
-    (void)hipFree(db->hist);
-    (void)hipFree(db->part_start);
-    (void)hipFree(db->cursor);
-    (void)hipFree(db->hist2);
-    (void)hipFree(db->slice_start);
-    (void)hipFree(db->cursor2);
-    (void)hipFree(db->chunk_first);
-    (void)hipFree(db->table);
-    (void)hipFree(db->bcount);
-    (void)hipFree(db->counters);
-    (void)hipFree(db->cand);
-    (void)hipFree(db->d_taxa);
-    (void)hipFree(db->d_parents);
-    (void)hipFree(db->d_depth);
+    (void)dev_free(db->pairs);
+    (void)dev_free(db->parted);
+    (void)dev_free(db->hist);
+    (void)dev_free(db->part_start);
+    (void)dev_free(db->cursor);
+    (void)dev_free(db->hist2);
+    (void)dev_free(db->slice_start);
+    (void)dev_free(db->cursor2);
+    (void)dev_free(db->chunk_first);
+    (void)dev_free(db->table);
+    (void)dev_free(db->bcount);
+    (void)dev_free(db->counters);
+    (void)dev_free(db->cand);
+    (void)dev_free(db->d_taxa);
+    (void)dev_free(db->d_parents);
+    (void)dev_free(db->d_depth);
     delete db;
     return MC_OK;
 }
@@ -805,11 +911,11 @@ int mc_db_add_targets(mc_db* db, const char* genomes, const uint64_t* lengths,
     if (rc) return rc;
     hipError_t e = total ? hipMemcpy(d, genomes, total, hipMemcpyHostToDevice) : hipSuccess;
     if (e != hipSuccess) {
-        (void)hipFree(d);
+        (void)dev_free(d);
         return fail(MC_ERR_HIP, "copy of genomes failed: %s", hipGetErrorString(e));
     }
     rc = add_targets_dev(db, d, lengths, taxon_ids, n, nullptr);
-    (void)hipFree(d);
+    (void)dev_free(d);
     return rc;
 }
 
@@ -855,17 +961,17 @@ int mc_db_set_taxonomy(mc_db* db, const uint32_t* parents, uint32_t n_nodes) {
     int rc = dev_alloc(&dp, n_nodes);
     if (rc) return rc;
     rc = dev_alloc(&dd, n_nodes);
-    if (rc) { (void)hipFree(dp); return rc; }
+    if (rc) { (void)dev_free(dp); return rc; }
     hipError_t e1 = hipMemcpy(dp, parents, n_nodes * 4ull, hipMemcpyHostToDevice);
     hipError_t e2 = hipMemcpy(dd, depth.data(), n_nodes * 4ull, hipMemcpyHostToDevice);
     if (e1 != hipSuccess || e2 != hipSuccess) {
-        (void)hipFree(dp);
-        (void)hipFree(dd);
+        (void)dev_free(dp);
+        (void)dev_free(dd);
         return fail(MC_ERR_HIP, "taxonomy upload failed");
     }
     HIP_TRY(hipDeviceSynchronize());   // no classify may still read the old arrays
-    (void)hipFree(db->d_parents);
-    (void)hipFree(db->d_depth);
+    (void)dev_free(db->d_parents);
+    (void)dev_free(db->d_depth);
     db->d_parents = dp;
     db->d_depth = dd;
     db->version += 1;
@@ -924,7 +1030,7 @@ int mc_db_get_stats(mc_db* db, mc_db_stats* out) {
     hipError_t e = launch_fill_u64(cnt, 1, 0ull, nullptr);
     if (e == hipSuccess) e = launch_count_valid(db->table, db->nb, cnt, nullptr);
     if (e == hipSuccess) e = hipMemcpy(&stored, cnt, 8, hipMemcpyDeviceToHost);
-    (void)hipFree(cnt);
+    (void)dev_free(cnt);
     if (e != hipSuccess) return fail(MC_ERR_HIP, "stats: %s", hipGetErrorString(e));
     *out = db->st;
     for (auto& kv : db->ws) {
@@ -973,7 +1079,7 @@ int mc_db_dump(mc_db* db, uint32_t feature_lo, uint32_t feature_hi, uint32_t* fe
     int rc = dev_alloc(&cnt, 1);
     if (rc) return rc;
     rc = dev_alloc(&buf, std::max<uint64_t>(capacity, 1));
-    if (rc) { (void)hipFree(cnt); return rc; }
+    if (rc) { (void)dev_free(cnt); return rc; }
     unsigned long long n = 0;
     std::vector<unsigned long long> host;
     hipError_t e = launch_fill_u64(cnt, 1, 0ull, nullptr);
@@ -984,8 +1090,8 @@ int mc_db_dump(mc_db* db, uint32_t feature_lo, uint32_t feature_hi, uint32_t* fe
         host.resize(n);
         e = hipMemcpy(host.data(), buf, n * 8, hipMemcpyDeviceToHost);
     }
-    (void)hipFree(cnt);
-    (void)hipFree(buf);
+    (void)dev_free(cnt);
+    (void)dev_free(buf);
     if (e != hipSuccess) return fail(MC_ERR_HIP, "dump: %s", hipGetErrorString(e));
     *n_out = n;
     if (n <= capacity) {
@@ -1022,7 +1128,7 @@ int mc_db_sketch(mc_db* db, const char* seqs_dev, const uint64_t* lengths, uint3
     int rc = dev_alloc(&d_td, n);
     if (rc) return rc;
     rc = dev_alloc(&d_tf, n + 1);
-    if (rc) { (void)hipFree(d_td); return rc; }
+    if (rc) { (void)dev_free(d_td); return rc; }
     BuildArgs a{};
     a.text = reinterpret_cast<const uint8_t*>(seqs_dev);
     a.text_len = off;
@@ -1039,8 +1145,8 @@ int mc_db_sketch(mc_db* db, const char* seqs_dev, const uint64_t* lengths, uint3
         e = hipMemcpyAsync(d_tf, tile_first.data(), (n + 1) * 8, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = launch_sketch(a, false, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    (void)hipFree(d_td);
-    (void)hipFree(d_tf);
+    (void)dev_free(d_td);
+    (void)dev_free(d_tf);
     if (e != hipSuccess) return fail(MC_ERR_HIP, "sketch: %s", hipGetErrorString(e));
     return MC_OK;
 }
