@@ -207,6 +207,17 @@ int block_alloc(void** p, size_t bytes) {
     return MC_OK;
 }
 
+// Bytes of the idle blocks of the current device (memory the next
+// allocations can take although the runtime counts it as used).
+uint64_t idle_cached_bytes() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    BlockCache& c = block_cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto it = c.idle_bytes.find(dev);
+    return it == c.idle_bytes.end() ? 0 : it->second;
+}
+
 template <typename T>
 int dev_alloc(T** p, uint64_t n) {
     if (n == 0) n = 1;
@@ -559,7 +570,8 @@ int add_targets_dev(mc_db* db, const uint8_t* genomes, const uint64_t* lengths,
         uint64_t max_chunk = kMinChunkSlots;
         size_t free_b = 0, total_b = 0;
         if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) {
-            const uint64_t avail = (uint64_t)free_b + db->pairs_cap * 16;   // held scratch is reused
+            // held scratch and idle cached blocks are reused
+            const uint64_t avail = (uint64_t)free_b + db->pairs_cap * 16 + idle_cached_bytes();
             max_chunk = std::min(kMaxChunkSlots, std::max(kMinChunkSlots, avail / 16 / 10 * 6));
         }
         if (const char* env = getenv("MC_CHUNK_SLOTS")) {   // test override: small chunks
