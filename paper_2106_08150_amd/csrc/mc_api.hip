@@ -164,19 +164,22 @@ BlockCache& block_cache() {
     return *c;
 }
 
-// Frees the idle blocks of `device` (every device if device < 0); the caller
-// holds the cache lock.
-void release_idle(BlockCache& c, int device) {
+// Frees the idle blocks of `device` (every device if device < 0) and returns
+// the first error; the caller holds the cache lock.
+hipError_t release_idle(BlockCache& c, int device) {
+    hipError_t err = hipSuccess;
     for (auto it = c.idle.begin(); it != c.idle.end();) {
         if (device >= 0 && it->first.first != device) { ++it; continue; }
         int cur = 0;
         (void)hipGetDevice(&cur);
         if (cur != it->first.first) (void)hipSetDevice(it->first.first);
-        (void)hipFree(it->second);
+        const hipError_t e = hipFree(it->second);
+        if (err == hipSuccess) err = e;
         if (cur != it->first.first) (void)hipSetDevice(cur);
         c.idle_bytes[it->first.first] -= it->first.second;
         it = c.idle.erase(it);
     }
+    return err;
 }
 
 int block_alloc(void** p, size_t bytes) {
@@ -200,7 +203,7 @@ int block_alloc(void** p, size_t bytes) {
     hipError_t e = hipMalloc(p, bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
-        release_idle(c, dev);
+        (void)release_idle(c, dev);
         HIP_TRY(hipMalloc(p, bytes));
     }
     c.live[*p] = {dev, bytes};
@@ -859,8 +862,7 @@ mc_db* mc_db_create(uint32_t k, uint32_t window, uint32_t sketch_size, uint32_t 
 int mc_release_cached_memory(void) {
     BlockCache& c = block_cache();
     std::lock_guard<std::mutex> lk(c.mu);
-    release_idle(c, -1);
-    const hipError_t e = hipGetLastError();
+    const hipError_t e = release_idle(c, -1);
     if (e != hipSuccess) return fail(MC_ERR_HIP, "release of cached blocks: %s", hipGetErrorString(e));
     return MC_OK;
 }

@@ -47,6 +47,7 @@ def test_argument_errors_without_device():
         assert not L.mc_db_create(*args)
         assert b"invalid" in L.mc_last_error()
     assert L.mc_db_destroy(None) == mc.MC_OK
+    assert L.mc_release_cached_memory() == mc.MC_OK   # nothing kept: no device call
     opts = mc.QueryOpts(4, 4, 0, 0, 0)
     assert L.mc_classify_ex(None, None, None, 1, ctypes.byref(opts), None, None, None) == \
         mc.MC_ERR_INVALID_ARG
