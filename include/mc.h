@@ -99,6 +99,11 @@ typedef struct mc_db_stats {
     uint64_t q_features;       /* sketch elements looked up by classify     */
     uint64_t q_locations;      /* locations gathered by classify            */
     uint64_t q_probes;         /* bucket lines read by classify lookups     */
+    uint64_t n_features;       /* distinct features among the stored pairs  */
+    uint64_t n_tombstones;     /* slots of entries removed by the cap or by
+                                  the rollback of a failed add              */
+    double load_factor;        /* occupied slots (stored + tombstones) over
+                                  all slots of the table                    */
 } mc_db_stats;
 
 /* Text of the calling thread's last error ("" if none). Never NULL. */
@@ -112,12 +117,22 @@ mc_db* mc_db_create(uint32_t k, uint32_t window, uint32_t sketch_size,
                     uint32_t max_locations);
 
 /* Free every device and host resource of the handle. NULL is accepted.
- * Device blocks of 256 MiB or more (the table, build scratch) are kept mapped
- * by the library for reuse by later allocations on the same device (mapping
- * and unmapping tens of GB costs far more than a build), as long as the kept
- * blocks of a device stay under half its memory; an allocation that fails
- * gives them back first. */
+ * Device blocks of 256 MiB or more (the table, build scratch) are freed, or
+ * kept mapped for reuse if mc_set_cached_memory_limit allows it. */
 int mc_db_destroy(mc_db* db);
+
+/* Reuse of large device blocks (process-wide, every device). Mapping and
+ * unmapping tens of GB costs far more than a build (hundreds of milliseconds
+ * to seconds), so a process that rebuilds databases may keep released blocks
+ * of 256 MiB or more mapped, idle, for later allocations of the library on the
+ * same device (a block serves a request up to 25% smaller than itself), while
+ * the idle blocks of a device stay within `bytes_per_device`. Default 0:
+ * nothing is kept, every release frees at once. Idle blocks are memory the
+ * runtime counts as used: an allocation of the library that fails gives them
+ * back and retries, other code must call mc_release_cached_memory. Lowering
+ * the limit below what a device keeps releases that device's idle blocks.
+ * Returns MC_OK, or MC_ERR_HIP if a release failed. */
+int mc_set_cached_memory_limit(uint64_t bytes_per_device);
 
 /* Give every device block the library keeps for reuse back to the runtime
  * (all devices), e.g. before other code needs that memory. Blocks in use by
@@ -133,17 +148,21 @@ int mc_db_reserve(mc_db* db, uint64_t n_pairs, double load_factor);
  * Targets get consecutive ids starting at the current target count, in array
  * order. The caller keeps ownership; the call is synchronous. May be called
  * again after mc_classify (on-demand addition); new targets always get larger
- * ids, so the per-feature cap keeps its meaning. Argument, capacity and
- * allocation errors are detected before the table is written: then nothing
- * is added. MC_ERR_TABLE_FULL or MC_ERR_HIP after inserts began leave the
- * handle with part of the call's entries: destroy it.
+ * ids, so the per-feature cap keeps its meaning. The call first waits for the
+ * device: classifications still queued on any stream finish on the old table.
+ * On any error nothing of the call is added: argument, capacity and
+ * allocation errors are detected before the table is written; if inserts had
+ * begun (MC_ERR_TABLE_FULL, MC_ERR_HIP), every entry of the call's targets is
+ * turned into a tombstone (its slot stays occupied) before the call returns.
+ * Only if that rollback fails as well does the error text say so: then the
+ * handle must be destroyed.
  * MC_ERR_CAPACITY: more than MC_MAX_TARGETS targets in total, or a sequence
  * with more than MC_MAX_WINDOWS windows.
  * Device memory: besides the table (16 slots of 8 bytes a bucket, grown to
  * keep the load factor), the build uses 16 bytes per pair slot (sketch_size
  * slots a window) of its largest chunk; an add is cut into chunks of whole
  * sequences that fit about 60% of the free device memory, and scratch larger
- * than an eighth of the device's memory is released before the call returns. */
+ * than 512 MiB is released before the call returns. */
 int mc_db_add_targets(mc_db* db, const char* genomes, const uint64_t* lengths,
                       const uint32_t* taxon_ids, uint32_t n);
 
@@ -231,8 +250,38 @@ mc_graph* mc_classify_graph_create(mc_db* db, const char* reads, const uint64_t*
 int mc_classify_graph_launch(mc_graph* g, void* stream);
 int mc_classify_graph_destroy(mc_graph* g);
 
-/* Counters of the handle (synchronous). */
+/* Counters of the handle (synchronous; counts the table's slots). */
 int mc_db_get_stats(mc_db* db, mc_db_stats* out);
+
+/* Test entry point, not for production use: forces the insert path of later
+ * mc_db_add_targets* calls on this handle, so that tests reach every path of
+ * the build on small inputs. The stored table never depends on it. NULL (or
+ * all fields zero) restores the automatic choice. Fields:
+ *   global_insert  1: insert with global per-bucket counters in partitions of
+ *                  part_mb MiB of table (0 = 256) instead of slice-local;
+ *   slice_shift    slice insert: 2^slice_shift buckets per slice, 4..13;
+ *   fine_bits      slice insert: 2^fine_bits slices per partition (used when
+ *                  not below the automatic value and at most 10);
+ *   stage_entries  slice insert: pairs staged in LDS per round (at least half
+ *                  a slice's buckets and 64);
+ *   direct         slice insert: 1 = every slice takes the direct path;
+ *   chunk_slots    most pair slots of one build chunk;
+ *   fail_after     1 = the next add reports MC_ERR_TABLE_FULL after all its
+ *                  inserts ran, so that tests reach the rollback (the flag
+ *                  clears itself).
+ * MC_ERR_INVALID_ARG for slice_shift outside 4..13 (0 excepted). */
+typedef struct mc_insert_path {
+    uint32_t global_insert;
+    uint32_t part_mb;
+    uint32_t slice_shift;
+    uint32_t fine_bits;
+    uint32_t stage_entries;
+    uint32_t direct;
+    uint64_t chunk_slots;
+    uint32_t fail_after;
+    uint32_t reserved;
+} mc_insert_path;
+int mc_db_set_insert_path(mc_db* db, const mc_insert_path* path);
 
 /* Test/inspection export, not part of the hot path: every stored pair whose
  * feature lies in [feature_lo, feature_hi], sorted by feature then location,
@@ -267,10 +316,14 @@ typedef struct mc_server mc_server;
 
 typedef struct mc_server_opts {
     uint32_t slots;           /* batches in flight at once, 1..16 (0 = 4)            */
-    uint64_t memory_budget;   /* device bytes for in-flight batch buffers
-                                 (0 = a quarter of the free device memory)           */
-    uint64_t staging_bytes;   /* initial device + pinned buffer per slot, grown by
-                                 doubling when a batch needs more (0 = 64 MiB)       */
+    uint64_t memory_budget;   /* device bytes of all slots' batch buffers together
+                                 (0 = a quarter of the device memory free at
+                                 creation); a batch is admitted when a free slot
+                                 holds it, or can grow to hold it within the budget
+                                 (the buffers of other free slots are released
+                                 to make room)                                       */
+    uint64_t staging_bytes;   /* initial device + pinned buffer per slot, grown in
+                                 32 MiB steps when a batch needs more (0 = 64 MiB)   */
 } mc_server_opts;
 
 typedef struct mc_server_stats {
@@ -311,7 +364,8 @@ int mc_server_add_targets(mc_server* srv, const char* genomes, const uint64_t* l
                           uint32_t n_nodes, uint64_t* ticket);
 
 /* Block until the job is done; returns its status (MC_OK or an error code) and
- * its latency in milliseconds (may be NULL). Each ticket can be waited once. */
+ * its latency in milliseconds (may be NULL). Each ticket can be waited once: a
+ * second wait on it returns MC_ERR_INVALID_ARG at once. */
 int mc_server_wait(mc_server* srv, uint64_t ticket, double* latency_ms);
 
 int mc_server_get_stats(mc_server* srv, mc_server_stats* out);

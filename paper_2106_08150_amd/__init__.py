@@ -41,7 +41,7 @@ EXPORTS = [
     "mc_server_get_stats", "mc_server_destroy",
     "mc_db_set_launch_config", "mc_db_get_launch_config", "mc_db_autotune",
     "mc_classify_graph_create", "mc_classify_graph_launch", "mc_classify_graph_destroy",
-    "mc_release_cached_memory",
+    "mc_release_cached_memory", "mc_set_cached_memory_limit", "mc_db_set_insert_path",
 ]
 
 
@@ -60,10 +60,19 @@ class DbStats(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in (
         "n_targets", "n_windows", "n_pairs_inserted", "n_pairs_stored", "n_buckets",
         "table_bytes", "n_cap_candidates", "probe_sum", "n_rehash", "q_features",
-        "q_locations", "q_probes")]
+        "q_locations", "q_probes", "n_features", "n_tombstones")] + [("load_factor", C.c_double)]
 
     def as_dict(self) -> dict:
-        return {n: int(getattr(self, n)) for n, _ in self._fields_}
+        return {n: (float(getattr(self, n)) if t is C.c_double else int(getattr(self, n)))
+                for n, t in self._fields_}
+
+
+class InsertPath(C.Structure):
+    _fields_ = [("global_insert", C.c_uint32), ("part_mb", C.c_uint32),
+                ("slice_shift", C.c_uint32), ("fine_bits", C.c_uint32),
+                ("stage_entries", C.c_uint32), ("direct", C.c_uint32),
+                ("chunk_slots", C.c_uint64), ("fail_after", C.c_uint32),
+                ("reserved", C.c_uint32)]
 
 
 class LaunchConfig(C.Structure):
@@ -106,6 +115,10 @@ def lib():
         L.mc_db_create.argtypes = [u32, u32, u32, u32]
         L.mc_db_destroy.restype, L.mc_db_destroy.argtypes = i32, [vp]
         L.mc_release_cached_memory.restype, L.mc_release_cached_memory.argtypes = i32, []
+        L.mc_set_cached_memory_limit.restype = i32
+        L.mc_set_cached_memory_limit.argtypes = [u64]
+        L.mc_db_set_insert_path.restype = i32
+        L.mc_db_set_insert_path.argtypes = [vp, C.POINTER(InsertPath)]
         L.mc_db_reserve.restype, L.mc_db_reserve.argtypes = i32, [vp, u64, C.c_double]
         L.mc_db_add_targets.restype = i32
         L.mc_db_add_targets.argtypes = [vp, vp, vp, vp, u32]
@@ -198,6 +211,19 @@ def mc_db_destroy(db: int) -> None:
 
 def mc_release_cached_memory() -> None:
     _check(lib().mc_release_cached_memory())
+
+
+def mc_set_cached_memory_limit(bytes_per_device: int) -> None:
+    _check(lib().mc_set_cached_memory_limit(int(bytes_per_device)))
+
+
+def mc_db_set_insert_path(db: int, **fields) -> None:
+    """Test entry point: force the insert path (no fields = automatic)."""
+    if not fields:
+        _check(lib().mc_db_set_insert_path(db, None))
+        return
+    p = InsertPath(**fields)
+    _check(lib().mc_db_set_insert_path(db, C.byref(p)))
 
 
 def mc_db_reserve(db: int, n_pairs: int, load_factor: float = 0.0) -> None:

@@ -47,20 +47,24 @@ constexpr double kDefaultLoad = 0.5;
 // Pair slots of one build chunk (16 bytes each: the pairs and their
 // partitioned copy): about 60% of the device memory free at the add, within
 // [kMinChunkSlots, kMaxChunkSlots], so that a reference set that fits builds
-// in one pass over the table's slices. Build scratch larger than an eighth of
-// the device's memory is released when the add returns.
+// in one pass over the table's slices. Build scratch larger than
+// kKeepScratchBytes is released when the add returns.
 constexpr uint64_t kMinChunkSlots = 1ull << 26;
+constexpr uint64_t kKeepScratchBytes = 512ull << 20;   // build scratch kept after an add
 constexpr uint64_t kMaxChunkSlots = 1ull << 32;
 constexpr uint64_t kPartBytes = 256ull << 20;           // target table bytes per partition
 constexpr uint64_t kMinBuckets = 64;
 constexpr uint64_t kCandCapMax = 1ull << 24;
 
 struct Workspace {
-    uint32_t* queue = nullptr;
-    uint64_t queue_cap = 0;
+    uint32_t* queue = nullptr;               // 2 * queue_cap record ids
+    uint64_t queue_cap = 0;                  // records
     uint32_t* counters = nullptr;            // kNumQueryCounters
     unsigned long long* qstats = nullptr;    // kNumQueryStats
+    unsigned char* huge = nullptr;           // kHugeBytes (HBM-list pass)
 };
+
+
 
 // Event pairs bracketing profiled launches.
 struct Timed {
@@ -124,6 +128,8 @@ struct mc_db {
     unsigned long long* slice_start = nullptr;  // kMaxSlices + 1
     unsigned long long* cursor2 = nullptr;      // kMaxSlices
     unsigned long long* chunk_first = nullptr;  // kChunkFirstLen
+    // insert path forced by mc_db_set_insert_path (tests); zero = automatic
+    mc_insert_path ipath{};
     // fast-path launch shape (set by mc_db_set_launch_config / mc_db_autotune)
     ClassifyConfig cfg;
     // bumped whenever device arrays a captured graph refers to may have moved
@@ -140,15 +146,16 @@ uint64_t num_windows(uint64_t len, uint32_t k, uint32_t S) {
     return (len - k + 1 + S - 1) / S;
 }
 
-// Large device blocks are kept for reuse after they are released: hipMalloc
+// Large device blocks can be kept for reuse after they are released: hipMalloc
 // and hipFree of tens of GB cost hundreds of milliseconds to seconds once the
 // runtime stops deferring them (about 28 ms per GB to free and 4 ms per GB to
 // map), far more than the build that uses them, so a process that rebuilds
-// databases would pay that on every build. A released block of at least
-// kCacheMinBytes stays mapped (idle) while the idle blocks of its device stay
-// under half the device's memory; an allocation takes an idle block of its
-// device whose size is within 25% above the request. An allocation that fails
-// releases every idle block of the device and tries once more.
+// databases would pay that on every build. Keeping is opt-in
+// (mc_set_cached_memory_limit): a released block of at least kCacheMinBytes
+// stays mapped (idle) while the idle blocks of its device stay within the
+// limit; otherwise it is freed at once. An allocation takes an idle block of
+// its device whose size is within 25% above the request. An allocation that
+// fails releases every idle block of the device and tries once more.
 // mc_release_cached_memory() gives all idle blocks back.
 constexpr size_t kCacheMinBytes = size_t(256) << 20;
 
@@ -157,6 +164,7 @@ struct BlockCache {
     std::unordered_map<void*, std::pair<int, size_t>> live;   // block -> (device, bytes)
     std::multimap<std::pair<int, size_t>, void*> idle;        // (device, bytes) -> block
     std::map<int, size_t> idle_bytes;
+    uint64_t limit = 0;                                       // idle bytes kept per device
 };
 
 BlockCache& block_cache() {
@@ -230,9 +238,10 @@ int dev_alloc(T** p, uint64_t n) {
     return rc;
 }
 
-// Release a block from dev_alloc (any other device pointer is freed). Like
-// hipFree it waits for the device first, so no queued work still uses a
-// block when it is handed out again.
+// Release a block from dev_alloc (any other device pointer is freed). A block
+// kept for reuse is parked only after the device has finished the work queued
+// so far, so no queued work still uses it when it is handed out again
+// (hipFree waits the same way).
 hipError_t dev_free(void* p) {
     if (!p) return hipSuccess;
     BlockCache& c = block_cache();
@@ -241,15 +250,16 @@ hipError_t dev_free(void* p) {
     if (it == c.live.end()) return hipFree(p);
     const std::pair<int, size_t> key = it->second;
     c.live.erase(it);
-    size_t free_b = 0, total_b = 0;
     int cur = 0;
     (void)hipGetDevice(&cur);
     if (cur != key.first) (void)hipSetDevice(key.first);
-    hipError_t e = hipDeviceSynchronize();
-    if (e == hipSuccess) e = hipMemGetInfo(&free_b, &total_b);
-    if (e == hipSuccess && c.idle_bytes[key.first] + key.second <= total_b / 2) {
-        c.idle.insert({key, p});
-        c.idle_bytes[key.first] += key.second;
+    hipError_t e = hipSuccess;
+    if (c.idle_bytes[key.first] + key.second <= c.limit) {
+        e = hipDeviceSynchronize();
+        if (e == hipSuccess) {
+            c.idle.insert({key, p});
+            c.idle_bytes[key.first] += key.second;
+        }
     } else {
         e = hipFree(p);
     }
@@ -412,8 +422,9 @@ uint32_t ceil_log2(uint64_t x) {
 // Partitioning of the insert pass. Slice mode (the default): slices of
 // 2^slice_shift buckets (at most kMaxSlices = 2^18 slices), 2^fine_bits
 // slices per partition (at most 1024), at most 256 partitions. Otherwise
-// (tables too large for that, or MC_INSERT=global) partitions of about
-// kPartBytes of table each (MC_PART_MB overrides) with global counters.
+// (tables too large for that, or the global insert forced by
+// mc_db_set_insert_path) partitions of about kPartBytes of table each with
+// global counters.
 void plan_partitions(const mc_db* db, BuildArgs& a) {
     const uint64_t nb = db->nb;
     const uint32_t lg = ceil_log2(nb);
@@ -421,30 +432,22 @@ void plan_partitions(const mc_db* db, BuildArgs& a) {
     // 2^10 below; larger only past 2^29 buckets (256 x 1024 slices)
     uint32_t sb = std::max<uint32_t>(kMinSliceShift, std::min<uint32_t>(11, lg > 16 ? lg - 16 : 0));
     sb = std::max<uint32_t>(sb, lg > 8 + kMaxFineBits ? lg - 8 - kMaxFineBits : 0);
-    // test overrides: a slice size, and the slice bits taken by level 2
-    if (const char* env = getenv("MC_SLICE_SHIFT")) {
-        const long v = atol(env);
-        if (v >= 4 && v <= (long)kMaxSliceShift) sb = (uint32_t)v;
-    }
-    const char* mode = getenv("MC_INSERT");
-    const bool global = mode && std::string(mode) == "global";
-    if (!global && slice_mode_fits(sb) && lg <= sb + 8 + kMaxFineBits) {
+    // forced by mc_db_set_insert_path (tests): a slice size, the slice bits
+    // taken by level 2, the global-counter insert and its partition size
+    const mc_insert_path& ip = db->ipath;
+    if (ip.slice_shift >= 4 && ip.slice_shift <= kMaxSliceShift) sb = ip.slice_shift;
+    if (!ip.global_insert && slice_mode_fits(sb) && lg <= sb + 8 + kMaxFineBits) {
         const uint32_t ns_bits = lg > sb ? lg - sb : 0;       // slices: 2^ns_bits >= nb >> sb
         uint32_t fb = ns_bits > 8 ? ns_bits - 8 : 0;
-        if (const char* env = getenv("MC_FINE_BITS")) {
-            const long v = atol(env);
-            if (v >= (long)fb && v <= (long)std::min<uint32_t>(ns_bits, kMaxFineBits)) fb = (uint32_t)v;
-        }
+        if (ip.fine_bits >= fb && ip.fine_bits <= std::min<uint32_t>(ns_bits, kMaxFineBits))
+            fb = ip.fine_bits;
         a.slice_mode = 1;
         a.slice_shift = sb;
         a.fine_bits = fb;
         a.part_shift = sb + fb;
     } else {
         uint64_t part = kPartBytes;
-        if (const char* env = getenv("MC_PART_MB")) {
-            long mb = atol(env);
-            if (mb > 0) part = (uint64_t)mb << 20;
-        }
+        if (ip.part_mb > 0) part = (uint64_t)ip.part_mb << 20;
         const uint64_t per = std::max<uint64_t>(1, part / (kSlots * 8));   // buckets
         uint32_t sh = ceil_log2(per);
         while (((nb - 1) >> sh) + 1 > kMaxParts) ++sh;
@@ -523,6 +526,8 @@ int build_chunk(mc_db* db, const uint8_t* genomes, const std::vector<TargetDesc>
     a.slice_start = db->slice_start;
     a.cursor2 = db->cursor2;
     a.chunk_first = db->chunk_first;
+    a.stage_entries = db->ipath.stage_entries;
+    a.force_direct = db->ipath.direct;
     if (a.slice_mode) {
         HIP_TRY(launch_fill_u32(db->hist2, (uint64_t)a.n_parts << a.fine_bits, 0u, st));
         HIP_TRY(launch_fill_u64(db->counters + kCntDefer, 1, 0ull, st));
@@ -555,6 +560,10 @@ int add_targets_dev(mc_db* db, const uint8_t* genomes, const uint64_t* lengths,
         wins += nw;
     }
     const uint64_t upper = wins * db->s;
+    // classifications queued earlier on any stream may still read the table
+    // (and a graph replay its arrays): they finish before the table changes
+    HIP_TRY(hipDeviceSynchronize());
+    const uint32_t first_target = (uint32_t)db->taxa.size();
     int rc = MC_OK;
     uint64_t cand_need = std::min<uint64_t>(std::max<uint64_t>(upper, 1), kCandCapMax);
     if (cand_need > db->cand_cap) {
@@ -577,10 +586,7 @@ int add_targets_dev(mc_db* db, const uint8_t* genomes, const uint64_t* lengths,
             const uint64_t avail = (uint64_t)free_b + db->pairs_cap * 16 + idle_cached_bytes();
             max_chunk = std::min(kMaxChunkSlots, std::max(kMinChunkSlots, avail / 16 / 10 * 6));
         }
-        if (const char* env = getenv("MC_CHUNK_SLOTS")) {   // test override: small chunks
-            const long long v = atoll(env);
-            if (v > 0) max_chunk = (uint64_t)v;
-        }
+        if (db->ipath.chunk_slots) max_chunk = db->ipath.chunk_slots;   // forced (tests)
         std::vector<uint32_t> cuts{0};
         uint64_t most = 0;
         for (uint32_t t0 = 0; t0 < n;) {
@@ -621,13 +627,35 @@ int add_targets_dev(mc_db* db, const uint8_t* genomes, const uint64_t* lengths,
     rc = insert_all();
     // a table still uncleared (no insert ran, or one failed first) is cleared now
     const int rc_clear = materialize(db, st);
-    if (rc) return rc;
-    if (rc_clear) return rc_clear;
-    unsigned long long c[kNumBuildCounters];
-    HIP_TRY(hipMemcpyAsync(c, db->counters, sizeof c, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    if (c[kCntFull]) return fail(MC_ERR_TABLE_FULL, "%llu inserts found no free slot",
-                                 (unsigned long long)c[kCntFull]);
+    if (rc == MC_OK) rc = rc_clear;
+    unsigned long long c[kNumBuildCounters] = {};
+    if (hipMemcpyAsync(c, db->counters, sizeof c, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        if (rc == MC_OK) rc = fail(MC_ERR_HIP, "build counters could not be read");
+    }
+    if (rc == MC_OK && c[kCntFull])
+        rc = fail(MC_ERR_TABLE_FULL, "%llu inserts found no free slot",
+                  (unsigned long long)c[kCntFull]);
+    if (rc == MC_OK && db->ipath.fail_after) {   // forced by a test (mc_db_set_insert_path)
+        db->ipath.fail_after = 0;
+        rc = fail(MC_ERR_TABLE_FULL, "failure forced after %llu inserts",
+                  (unsigned long long)c[kCntInserted]);
+    }
+    if (rc != MC_OK) {
+        // nothing of the call stays: every entry of its targets (ids from
+        // first_target on) becomes a tombstone; the cap has not run yet, so
+        // the earlier targets' entries are as they were
+        const std::string msg = g_err;
+        if (db->touched) {
+            db->slots_used += c[kCntInserted];   // tombstones still occupy their slots
+            if (launch_rollback(db->table, db->nb, first_target, st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess)
+                g_err = msg + "; the rollback of the call's entries failed too: destroy the handle";
+            else
+                g_err = msg;
+        }
+        return rc;
+    }
     if (c[kCntCand] <= db->cand_cap) {
         HIP_TRY(launch_cap_finalize(db->table, db->nb, db->cap, db->cand, c[kCntCand], st));
     } else {
@@ -642,9 +670,9 @@ int add_targets_dev(mc_db* db, const uint8_t* genomes, const uint64_t* lengths,
     db->st.n_pairs_inserted += c[kCntInserted];
     db->st.probe_sum += c[kCntProbe];
     db->st.n_cap_candidates += c[kCntCand];
-    size_t free_b = 0, total_b = 0;
-    if (db->pairs_cap && hipMemGetInfo(&free_b, &total_b) == hipSuccess &&
-        db->pairs_cap * 16 > (uint64_t)total_b / 8) {
+    // build scratch beyond a small amount (enough for additions of a few
+    // hundred Mbp) is released: a resident database does not carry dead pairs
+    if (db->pairs_cap * 16 > kKeepScratchBytes) {
         HIP_TRY(dev_free(db->pairs));
         HIP_TRY(dev_free(db->parted));
         db->pairs = db->parted = nullptr;
@@ -658,22 +686,31 @@ int check_db(mc_db* db) {
     return MC_OK;
 }
 
+// Device buffers of a workspace that do not depend on the batch size: the
+// counters and the HBM-list scratch, whose per-target bests start at zero
+// (the pass leaves them at zero).
+int init_workspace(Workspace& w, hipStream_t st) {
+    if (int rc = dev_alloc(&w.counters, kNumQueryCounters)) return rc;
+    if (int rc = dev_alloc(&w.qstats, kNumQueryStats)) return rc;
+    if (int rc = dev_alloc(&w.huge, kHugeBytes)) return rc;
+    HIP_TRY(launch_fill_u32(w.counters, kNumQueryCounters, 0u, st));
+    HIP_TRY(launch_fill_u64(w.qstats, kNumQueryStats, 0ull, st));
+    for (uint32_t r = 0; r < kHugeGroups; ++r)
+        HIP_TRY(launch_fill_u64(reinterpret_cast<unsigned long long*>(w.huge + r * kHugeRegionBytes),
+                                kHugeTargets, 0ull, st));
+    return MC_OK;
+}
+
 Workspace* workspace(mc_db* db, hipStream_t st, uint64_t n_records, int* rc) {
     Workspace& w = db->ws[st];
     *rc = MC_OK;
-    if (!w.counters) {
-        if ((*rc = dev_alloc(&w.counters, kNumQueryCounters))) return nullptr;
-        if ((*rc = dev_alloc(&w.qstats, kNumQueryStats))) return nullptr;
-        if (launch_fill_u32(w.counters, kNumQueryCounters, 0u, st) != hipSuccess ||
-            launch_fill_u64(w.qstats, kNumQueryStats, 0ull, st) != hipSuccess) {
-            *rc = fail(MC_ERR_HIP, "workspace init failed");
-            return nullptr;
-        }
+    if (!w.huge) {
+        if ((*rc = init_workspace(w, st))) return nullptr;
     }
     if (n_records > w.queue_cap) {
         uint32_t* q = nullptr;
         const uint64_t c = std::max<uint64_t>(std::max<uint64_t>(n_records, 1024), 2 * w.queue_cap);
-        if ((*rc = dev_alloc(&q, c))) return nullptr;
+        if ((*rc = dev_alloc(&q, 2 * c))) return nullptr;
         if (w.queue) db->retired.push_back(w.queue);
         w.queue = q;
         w.queue_cap = c;
@@ -709,7 +746,8 @@ int check_classify(mc_db* db, const char* reads, const uint64_t* offsets, uint32
 int classify_launch(mc_db* db, const char* reads, const uint64_t* offsets, uint32_t n_records,
                     const mc_query_opts& opts, uint32_t* out_labels, mc_tophit* out_top,
                     Workspace& w, const ClassifyConfig& cfg, hipStream_t st, bool profile) {
-    HIP_TRY(launch_fill_u32(w.counters + kQOverflow, 1, 0u, st));
+    static_assert(kQOverflow == 0 && kQHuge == 1, "the per-launch queue counters lead");
+    HIP_TRY(launch_fill_u32(w.counters, 2, 0u, st));
     QueryArgs a{};
     a.table = db->table;
     a.nb = db->nb;
@@ -730,6 +768,7 @@ int classify_launch(mc_db* db, const char* reads, const uint64_t* offsets, uint3
     a.queue = w.queue;
     a.counters = w.counters;
     a.qstats = w.qstats;
+    a.huge = w.huge;
     if (profile) {
         HIP_TRY(timed_launch(db, db->timers[MC_K_CLASSIFY], st,
                              [&] { return launch_classify_fast(a, cfg, st); }));
@@ -737,24 +776,21 @@ int classify_launch(mc_db* db, const char* reads, const uint64_t* offsets, uint3
         HIP_TRY(launch_classify_fast(a, cfg, st));
     }
     HIP_TRY(launch_classify_large(a, st));
+    HIP_TRY(launch_classify_huge(a, st));
     return MC_OK;
 }
 
 int alloc_workspace(Workspace& w, uint64_t n_records, hipStream_t st) {
-    int rc = dev_alloc(&w.counters, kNumQueryCounters);
-    if (!rc) rc = dev_alloc(&w.qstats, kNumQueryStats);
-    if (!rc) rc = dev_alloc(&w.queue, std::max<uint64_t>(n_records, 1));
-    if (rc) return rc;
+    if (int rc = init_workspace(w, st)) return rc;
     w.queue_cap = std::max<uint64_t>(n_records, 1);
-    HIP_TRY(launch_fill_u32(w.counters, kNumQueryCounters, 0u, st));
-    HIP_TRY(launch_fill_u64(w.qstats, kNumQueryStats, 0ull, st));
-    return MC_OK;
+    return dev_alloc(&w.queue, 2 * w.queue_cap);
 }
 
 void free_workspace(Workspace& w) {
     (void)dev_free(w.queue);
     (void)dev_free(w.counters);
     (void)dev_free(w.qstats);
+    (void)dev_free(w.huge);
     w = Workspace();
 }
 
@@ -859,6 +895,33 @@ mc_db* mc_db_create(uint32_t k, uint32_t window, uint32_t sketch_size, uint32_t 
     return db;
 }
 
+int mc_set_cached_memory_limit(uint64_t bytes_per_device) {
+    BlockCache& c = block_cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    c.limit = bytes_per_device;
+    hipError_t err = hipSuccess;
+    for (auto& kv : c.idle_bytes) {
+        if (kv.second <= bytes_per_device) continue;
+        const hipError_t e = release_idle(c, kv.first);
+        if (err == hipSuccess) err = e;
+    }
+    if (err != hipSuccess) return fail(MC_ERR_HIP, "release of cached blocks: %s", hipGetErrorString(err));
+    return MC_OK;
+}
+
+int mc_db_set_insert_path(mc_db* db, const mc_insert_path* path) {
+    if (int rc = check_db(db)) return rc;
+    if (!path) {
+        db->ipath = mc_insert_path{};
+        return MC_OK;
+    }
+    if (path->slice_shift != 0 && (path->slice_shift < 4 || path->slice_shift > kMaxSliceShift))
+        return fail(MC_ERR_INVALID_ARG, "slice_shift %u not in 4..%u", path->slice_shift,
+                    kMaxSliceShift);
+    db->ipath = *path;
+    return MC_OK;
+}
+
 int mc_release_cached_memory(void) {
     BlockCache& c = block_cache();
     std::lock_guard<std::mutex> lk(c.mu);
@@ -871,11 +934,7 @@ int mc_db_destroy(mc_db* db) {
     if (!db) return MC_OK;
     DeviceGuard dg(db->device);
     (void)hipDeviceSynchronize();
-    for (auto& kv : db->ws) {
-        (void)dev_free(kv.second.queue);
-        (void)dev_free(kv.second.counters);
-        (void)dev_free(kv.second.qstats);
-    }
+    for (auto& kv : db->ws) free_workspace(kv.second);
     for (uint32_t* q : db->retired) (void)dev_free(q);
     for (auto& t : db->timers) (void)drain(t, nullptr, nullptr);
     (void)dev_free(db->pairs);
@@ -1038,12 +1097,13 @@ int mc_db_get_stats(mc_db* db, mc_db_stats* out) {
     if (!out) return fail(MC_ERR_INVALID_ARG, "out is NULL");
     DeviceGuard dg(db->device);
     unsigned long long* cnt = nullptr;
-    int rc = dev_alloc(&cnt, 1);
+    int rc = dev_alloc(&cnt, 3);
     if (rc) return rc;
-    unsigned long long stored = 0;
-    hipError_t e = launch_fill_u64(cnt, 1, 0ull, nullptr);
-    if (e == hipSuccess) e = launch_count_valid(db->table, db->nb, cnt, nullptr);
-    if (e == hipSuccess) e = hipMemcpy(&stored, cnt, 8, hipMemcpyDeviceToHost);
+    unsigned long long census[3] = {0, 0, 0};   // live, tombstones, distinct features
+    hipError_t e = materialize(db, nullptr) == MC_OK ? hipSuccess : hipErrorUnknown;
+    if (e == hipSuccess) e = launch_fill_u64(cnt, 3, 0ull, nullptr);
+    if (e == hipSuccess) e = launch_census(db->table, db->nb, cnt, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(census, cnt, sizeof census, hipMemcpyDeviceToHost);
     (void)dev_free(cnt);
     if (e != hipSuccess) return fail(MC_ERR_HIP, "stats: %s", hipGetErrorString(e));
     *out = db->st;
@@ -1058,9 +1118,12 @@ int mc_db_get_stats(mc_db* db, mc_db_stats* out) {
     }
     out->n_targets = db->taxa.size();
     out->n_windows = db->n_windows;
-    out->n_pairs_stored = stored;
+    out->n_pairs_stored = census[0];
+    out->n_tombstones = census[1];
+    out->n_features = census[2];
     out->n_buckets = db->nb;
     out->table_bytes = db->nb * (kSlots * 8 + 4);
+    out->load_factor = db->nb ? (double)(census[0] + census[1]) / (double)(db->nb * kSlots) : 0.0;
     return MC_OK;
 }
 

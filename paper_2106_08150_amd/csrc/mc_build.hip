@@ -2,7 +2,6 @@
 // h1 + bottom-s sketch per window + insertion into the bucketed multi-value
 // table, the deterministic per-feature cap, table growth and test exports.
 #include <algorithm>
-#include <cstdlib>
 
 #include "mc_device.hpp"
 #include "mc_internal.hpp"
@@ -909,18 +908,59 @@ __global__ __launch_bounds__(256) void k_dump(const unsigned long long* table, u
     }
 }
 
-__global__ __launch_bounds__(256) void k_count_valid(const unsigned long long* table, uint64_t nb,
-                                                     unsigned long long* count) {
+// Census of the table: live entries, tombstones, and distinct features of the
+// live entries. A live entry counts as its feature's first when no live entry
+// of that feature lies before it on the feature's chain (buckets from the
+// home bucket on, and the lower slots of its own bucket); chains are short
+// (about one bucket) so the backwards walk is cheap.
+__global__ __launch_bounds__(256) void k_census(const unsigned long long* table, uint64_t nb,
+                                                unsigned long long* count) {
     const uint64_t n = nb * kSlots;
-    uint32_t c = 0;
+    uint32_t live = 0, tomb = 0, first = 0;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * blockDim.x) {
-        uint64_t e = table[i];
-        c += live_entry(e) ? 1u : 0u;
+        const uint64_t e = table[i];
+        if (e == kEmpty) continue;
+        if (!live_entry(e)) { tomb += 1; continue; }
+        live += 1;
+        const uint32_t f = (uint32_t)(e >> 32);
+        const uint64_t bb = i / kSlots;
+        uint64_t b = home_bucket(f, nb);
+        bool seen = false;
+        for (;; b = next_bucket(b, nb)) {
+            const uint32_t end = b == bb ? (uint32_t)(i % kSlots) : (uint32_t)kSlots;
+            for (uint32_t j = 0; j < end && !seen; ++j) {
+                const uint64_t x = table[b * kSlots + j];
+                seen = live_entry(x) && (uint32_t)(x >> 32) == f;
+            }
+            if (seen || b == bb) break;
+        }
+        first += seen ? 0u : 1u;
     }
 #pragma unroll
-    for (int m = 1; m < kWave; m <<= 1) c += shfl_xor(c, m);
-    if (lane_id() == 0 && c) atomicAdd(count, (unsigned long long)c);
+    for (int m = 1; m < kWave; m <<= 1) {
+        live += shfl_xor(live, m);
+        tomb += shfl_xor(tomb, m);
+        first += shfl_xor(first, m);
+    }
+    if (lane_id() == 0) {
+        if (live) atomicAdd(&count[0], (unsigned long long)live);
+        if (tomb) atomicAdd(&count[1], (unsigned long long)tomb);
+        if (first) atomicAdd(&count[2], (unsigned long long)first);
+    }
+}
+
+// Undo of a failed add: live entries of targets >= first_target become
+// tombstones (their slots stay occupied, so every chain stays intact).
+__global__ __launch_bounds__(256) void k_rollback(unsigned long long* table, uint64_t nb,
+                                                  uint32_t first_target) {
+    const uint64_t n = nb * kSlots;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t e = table[i];
+        if (live_entry(e) && ((uint32_t)e >> kWindowBits) >= first_target)
+            table[i] = (e & 0xFFFFFFFF00000000ull) | kTombLoc;
+    }
 }
 
 inline unsigned grid_for(uint64_t items, unsigned per_block, unsigned max_blocks) {
@@ -1021,15 +1061,14 @@ hipError_t launch_insert(const BuildArgs& a, uint64_t max_items, hipStream_t st)
     const uint32_t n_slices = a.n_parts << a.fine_bits;
     uint32_t buf_cap = slice_buf_cap(a.slice_shift), line_cap = kLineCap;
     if (buf_cap == 0) return hipErrorInvalidConfiguration;
-    // test overrides: a smaller staging buffer (more rounds a slice), or the
-    // direct path for slices of more than MC_SLICE_DIRECT pairs
-    if (const char* env = getenv("MC_SLICE_STAGE")) {
+    // forced (tests): a smaller staging buffer (more rounds a slice), or the
+    // direct path for every slice
+    if (a.stage_entries) {
         const uint64_t lo = std::max<uint64_t>(4 * kSlots, (uint64_t)1 << (a.slice_shift - 1));
-        const uint64_t v = std::max<uint64_t>(lo, (uint64_t)atoll(env));
+        const uint64_t v = std::max<uint64_t>(lo, (uint64_t)a.stage_entries);
         buf_cap = (uint32_t)std::min<uint64_t>(buf_cap, (v + 7) & ~7ull);
     }
-    if (const char* env = getenv("MC_SLICE_DIRECT"))
-        line_cap = (uint32_t)std::min<long long>(line_cap, std::max(0ll, atoll(env)));
+    if (a.force_direct) line_cap = 0;
     const size_t lds = (size_t)buf_cap * 8 + ((size_t)5 << a.slice_shift);
     hipLaunchKernelGGL(k_insert_slices, dim3(n_slices), dim3(kLineThreads), lds, st, a, buf_cap,
                        line_cap);
@@ -1088,11 +1127,19 @@ hipError_t launch_dump(const unsigned long long* table, uint64_t nb, uint32_t lo
     return hipGetLastError();
 }
 
-hipError_t launch_count_valid(const unsigned long long* table, uint64_t nb,
-                              unsigned long long* count, hipStream_t st) {
+hipError_t launch_census(const unsigned long long* table, uint64_t nb,
+                         unsigned long long* count, hipStream_t st) {
     if (nb == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_count_valid, dim3(grid_for(nb * kSlots, 256, 16384)), dim3(256), 0, st,
+    hipLaunchKernelGGL(k_census, dim3(grid_for(nb * kSlots, 256, 16384)), dim3(256), 0, st,
                        table, nb, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_rollback(unsigned long long* table, uint64_t nb, uint32_t first_target,
+                           hipStream_t st) {
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rollback, dim3(grid_for(nb * kSlots, 256, 16384)), dim3(256), 0, st,
+                       table, nb, first_target);
     return hipGetLastError();
 }
 

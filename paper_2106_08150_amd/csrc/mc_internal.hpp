@@ -75,6 +75,10 @@ struct BuildArgs {
                                         // [kChunkMaxAt]: most scatter chunks of a partition
     uint32_t fresh;                     // slice mode: table and counters uncleared; the
                                         // insert writes every bucket of every slice
+    // forced by mc_db_set_insert_path (tests): LDS staging entries of the slice
+    // insert (0 = as many as fit) and the direct path for every slice
+    uint32_t stage_entries;
+    uint32_t force_direct;
 };
 
 constexpr uint32_t kMaxParts = 256;         // partitions (8 bits)
@@ -103,9 +107,24 @@ inline uint32_t scatter_chunk_tiles(uint32_t s) {
 // Query-side counters (device, u32).
 enum QueryCounter {
     kQOverflow = 0,      // records queued for the large-list pass
-    kQTooLong = 1,       // records whose list exceeded the large-list capacity
+    kQHuge = 1,          // records queued for the HBM-list pass
+    kQTooLong = 2,       // records beyond every pass's capacity (left unclassified)
     kNumQueryCounters = 4
 };
+
+// HBM-list pass: one workgroup a record, its lists in device memory. Each of
+// kHugeGroups workgroups owns one region of the workspace's huge scratch.
+constexpr int kHugeThreads = 256;
+constexpr uint32_t kHugeGroups = 4;
+constexpr uint32_t kHugeFeats = 1u << 14;      // sketch elements of one record
+constexpr uint32_t kHugeLocs = 1u << 20;       // candidate locations of one record
+constexpr uint32_t kHugeSlots = 2 * kHugeLocs; // counting hash table (keys + counts)
+constexpr uint32_t kHugeTargets = 16384;       // per-target best range (> MC_MAX_TARGETS)
+// Bytes of one region: features, locations, hash keys, hash counts (u32 each),
+// per-target best (u64) and the list of targets hit (u32).
+constexpr uint64_t kHugeRegionBytes =
+    4ull * (kHugeFeats + kHugeLocs + 2ull * kHugeSlots) + 8ull * kHugeTargets + 4ull * kHugeTargets;
+constexpr uint64_t kHugeBytes = kHugeRegionBytes * kHugeGroups;
 
 struct QueryArgs {
     const unsigned long long* table;
@@ -121,9 +140,10 @@ struct QueryArgs {
     const uint32_t* depth;
     uint32_t* out_labels;
     uint32_t* out_top;            // n_records * top_m * 3 u32, or null
-    uint32_t* queue;              // overflow record ids (capacity n_records)
+    uint32_t* queue;              // record ids: [0, n) large-list pass, [n, 2n) HBM-list pass
     uint32_t* counters;
     unsigned long long* qstats;   // kNumQueryStats running totals
+    unsigned char* huge;          // kHugeBytes of HBM-list scratch (per-target bests zero)
 };
 
 enum QueryStat { kQsFeatures = 0, kQsLocations = 1, kQsProbes = 2, kNumQueryStats = 4 };
@@ -153,8 +173,13 @@ hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st);
 hipError_t launch_dump(const unsigned long long* table, uint64_t nb, uint32_t lo, uint32_t hi,
                        unsigned long long* out, uint64_t cap, unsigned long long* count,
                        hipStream_t st);
-hipError_t launch_count_valid(const unsigned long long* table, uint64_t nb,
-                              unsigned long long* count, hipStream_t st);
+// Table census into count[0..3): live entries, tombstones, distinct features
+// of the live entries.
+hipError_t launch_census(const unsigned long long* table, uint64_t nb,
+                         unsigned long long* count, hipStream_t st);
+// Every live entry whose target is first_target or later becomes a tombstone.
+hipError_t launch_rollback(unsigned long long* table, uint64_t nb, uint32_t first_target,
+                           hipStream_t st);
 // Launch shape of the fast classification path: candidate locations held in
 // LDS per record (256, 512 or 1024), waves per workgroup (2, 4 or 8) and the
 // largest grid (records beyond it are taken grid-stride).
@@ -169,6 +194,7 @@ bool classify_config_valid(const ClassifyConfig& c);
 // over the records the fast path queued.
 hipError_t launch_classify_fast(const QueryArgs& a, const ClassifyConfig& c, hipStream_t st);
 hipError_t launch_classify_large(const QueryArgs& a, hipStream_t st);
+hipError_t launch_classify_huge(const QueryArgs& a, hipStream_t st);
 
 // Device of a database handle (for threads that must select it).
 int db_device(const struct ::mc_db* db);

@@ -337,14 +337,12 @@ __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>
         }
     }
     if (!fits) {
-        if (!big) {
-            if (lane == 0) {
-                uint32_t qi = atomicAdd(&MC_COLD(counters)[kQOverflow], 1u);
-                MC_COLD(queue)[qi] = rec;
-            }
-        } else {
-            if (lane == 0) atomicAdd(&MC_COLD(counters)[kQTooLong], 1u);
-            write_result(a, rec, kNone, L, 0);
+        // the fast path queues the record for the large-list pass, that pass
+        // for the HBM-list pass (ids from n_records on)
+        if (lane == 0) {
+            uint32_t* const counters = MC_COLD(counters);
+            const uint32_t qi = atomicAdd(&counters[big ? kQHuge : kQOverflow], 1u);
+            MC_COLD(queue)[(big ? MC_COLD(n_records) : 0u) + qi] = rec;
         }
         return;
     }
@@ -476,6 +474,282 @@ void k_classify(QueryArgs a, int big) {
     }
 }
 
+// ------------------------------------------------------ HBM-list pass -----
+// Records whose candidate list outgrew the large-list pass: one workgroup a
+// record, the lists in its region of the workspace's huge scratch. The steps
+// are those of the other passes (Sec. 4.2, Sec. 5.3-5.6) without a sort: the
+// window count of each distinct location is accumulated in a hash table in
+// HBM (Q4-Q6), the score of the range of `sws` windows starting at each
+// distinct location sums the counts of its windows looked up in that table,
+// and each target keeps its best range with a 64-bit atomic maximum of
+// score << 32 | ~location (highest score, then smallest start window, as the
+// sorted passes' keys). Top-m and the label follow as in the other passes.
+struct HugeRegion {
+    uint32_t* feats;                 // kHugeFeats
+    uint32_t* locs;                  // kHugeLocs
+    uint32_t* keys;                  // kHugeSlots, kNone = empty
+    uint32_t* cnt;                   // kHugeSlots
+    unsigned long long* best;        // kHugeTargets, zero between records
+    uint32_t* tlist;                 // kHugeTargets
+};
+
+__device__ __forceinline__ HugeRegion huge_region(unsigned char* base, uint32_t r) {
+    unsigned char* p = base + (uint64_t)r * kHugeRegionBytes;
+    HugeRegion h;
+    h.best = reinterpret_cast<unsigned long long*>(p);
+    p += 8ull * kHugeTargets;
+    h.feats = reinterpret_cast<uint32_t*>(p);
+    h.locs = h.feats + kHugeFeats;
+    h.keys = h.locs + kHugeLocs;
+    h.cnt = h.keys + kHugeSlots;
+    h.tlist = h.cnt + kHugeSlots;
+    return h;
+}
+
+// Values written by atomics of this workgroup are read at device scope (not
+// from a possibly stale vector L1 line).
+__device__ __forceinline__ uint32_t ld_dev(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long ld_dev64(const unsigned long long* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t loc_slot(uint32_t loc, uint32_t mask) {
+    return (loc * 0x9E3779B1u >> 7) & mask;
+}
+
+// Window count of `loc` (0 if absent).
+__device__ __forceinline__ uint32_t huge_count(const HugeRegion& h, uint32_t mask, uint32_t loc) {
+    for (uint32_t i = loc_slot(loc, mask);; i = (i + 1) & mask) {
+        const uint32_t k = ld_dev(&h.keys[i]);
+        if (k == loc) return ld_dev(&h.cnt[i]);
+        if (k == kNone) return 0u;
+    }
+}
+
+constexpr int kHugeWaves = kHugeThreads / kWave;
+
+struct HugeLds {
+    Word stage[kHugeWaves][2 * kStageWords];
+    uint32_t scratch[kHugeWaves][kWave];
+    uint32_t sk[kHugeWaves][2 * 64];
+    unsigned long long red[kHugeWaves];
+    uint32_t nfeat, nloc, ntarget, overflow;
+    uint32_t sel_t[kMaxTopM], sel_s[kMaxTopM], sel_b[kMaxTopM];
+};
+
+// Workgroup maximum of one u64 per thread.
+__device__ __forceinline__ unsigned long long block_max_u64(unsigned long long v,
+                                                            unsigned long long* red) {
+    v = wave_max_u64(v);
+    const uint32_t w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane_id() == 0) red[w] = v;
+    __syncthreads();
+    unsigned long long m = red[0];
+    for (int i = 1; i < kHugeWaves; ++i) m = red[i] > m ? red[i] : m;
+    return m;
+}
+
+template <int KPL>
+__device__ void classify_huge_record(const QueryArgs& a, uint32_t rec, const HugeRegion& h,
+                                     HugeLds& L, const Threshold& th) {
+    const uint32_t tid = threadIdx.x, lane = (uint32_t)lane_id(), wave = tid >> 6;
+    uint64_t o0, o1, o2;
+    if (a.paired) {
+        o0 = a.offsets[2ull * rec]; o1 = a.offsets[2ull * rec + 1]; o2 = a.offsets[2ull * rec + 2];
+    } else {
+        o0 = a.offsets[rec]; o1 = a.offsets[rec + 1ull]; o2 = o1;
+    }
+    const uint64_t len[2] = {o1 - o0, o2 - o1};
+    uint64_t F = len[0] + len[1];
+    if (len[0] > 0 && len[1] > 0 && a.insert_size > F) F = a.insert_size;
+    const uint32_t sws = F < a.k ? 1u : (uint32_t)((F - a.k + a.S - 1) / a.S + 1);
+    uint64_t nws[2];
+    for (int sg = 0; sg < 2; ++sg)
+        nws[sg] = len[sg] < a.k ? 0 : (len[sg] - a.k + 1 + a.S - 1) / a.S;
+    const uint64_t nwt = nws[0] + nws[1];
+    if (tid == 0) {
+        L.nfeat = 0;
+        L.nloc = 0;
+        L.ntarget = 0;
+        L.overflow = 0;
+    }
+    __syncthreads();
+
+    // sketches of all windows: each wave takes pairs of windows
+    for (uint64_t p = 2ull * wave; p < nwt; p += 2ull * kHugeWaves) {
+        WinRef wr[2];
+        for (int x = 0; x < 2; ++x) wr[x] = window_ref(a, p + x, nwt, nws[0], o0, o1, len);
+        wave_lds_sync();
+        stage_pair(L.stage[wave], wr[0], wr[1], (int)lane);
+        wave_lds_sync();
+        uint32_t nA, nB;
+        sketch_pair<KPL>(L.stage[wave], wr[0].x0, wr[0].nk, L.stage[wave] + kStageWords, wr[1].x0,
+                         wr[1].nk, a.k, a.s, th, L.sk[wave], L.sk[wave] + 64, L.scratch[wave], nA,
+                         nB);
+        wave_lds_sync();
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(&L.nfeat, nA + nB);
+        base = uniform(shfl_idx(base, 0));
+        if (base + nA + nB > kHugeFeats) {
+            if (lane == 0) L.overflow = 1;
+        } else {
+            if (lane < nA) h.feats[base + lane] = L.sk[wave][lane];
+            if (lane < nB) h.feats[base + nA + lane] = L.sk[wave][64 + lane];
+        }
+        wave_lds_sync();
+    }
+    __syncthreads();
+    const uint32_t nf = min(L.nfeat, kHugeFeats);
+
+    // lookups: 8-lane groups walk one feature's chain each, appending its
+    // locations with an LDS counter
+    typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+    const u64x2* slot2 = reinterpret_cast<const u64x2*>(a.table) + (lane & 7u);
+    const uint32_t nb = (uint32_t)a.nb;
+    uint32_t probes = 0;
+    for (uint32_t fi = tid >> 3; fi < nf && !L.overflow; fi += kHugeThreads / 8) {
+        const uint32_t f = h.feats[fi];
+        uint32_t b = (uint32_t)home_bucket(f, a.nb);
+        for (;;) {
+            const u64x2 sl = slot2[(uint64_t)b * (kSlots / 2)];
+            probes += (lane & 7u) == 0 ? 1u : 0u;
+            const unsigned long long e[2] = {sl.x, sl.y};
+            for (int x = 0; x < 2; ++x) {
+                if ((uint32_t)(e[x] >> 32) == f && (uint32_t)e[x] < kTombLoc) {
+                    const uint32_t pos = atomicAdd(&L.nloc, 1u);
+                    if (pos < kHugeLocs) h.locs[pos] = (uint32_t)e[x];
+                    else L.overflow = 1;
+                }
+            }
+            // the group's last lane holds the bucket's last slot: full bucket
+            // -> the chain goes on
+            const uint32_t last = (lane & ~7u) | 7u;
+            const bool full = shfl_idx(sl.y != kEmpty ? 1u : 0u, (int)last) != 0u;
+            if (!full) break;
+            b = b + 1u == nb ? 0u : b + 1u;
+        }
+    }
+    __syncthreads();
+    const uint32_t n = L.nloc;
+    if (L.overflow) {
+        if (tid == 0) {
+            atomicAdd(&a.counters[kQTooLong], 1u);
+            a.out_labels[rec] = kNone;
+        }
+        if (a.out_top && tid < a.top_m) {
+            uint32_t* o = a.out_top + ((uint64_t)rec * a.top_m + tid) * 3;
+            o[0] = kNone; o[1] = 0u; o[2] = 0u;
+        }
+        __syncthreads();
+        return;
+    }
+
+    // window counts: hash table of 2^m >= 2n slots, cleared first
+    uint32_t P = 64;
+    while (P < 2 * n) P <<= 1;
+    const uint32_t mask = P - 1;
+    for (uint32_t i = tid; i < P; i += kHugeThreads) {
+        h.keys[i] = kNone;
+        h.cnt[i] = 0u;
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < n; i += kHugeThreads) {
+        const uint32_t loc = h.locs[i];
+        for (uint32_t j = loc_slot(loc, mask);; j = (j + 1) & mask) {
+            const uint32_t old = atomicCAS(&h.keys[j], kNone, loc);
+            if (old == kNone || old == loc) {
+                atomicAdd(&h.cnt[j], 1u);
+                break;
+            }
+        }
+    }
+    __syncthreads();
+    // score of the range starting at each distinct location; best per target
+    for (uint32_t i = tid; i < P; i += kHugeThreads) {
+        const uint32_t loc = ld_dev(&h.keys[i]);
+        if (loc == kNone) continue;
+        const uint32_t t = loc >> kWindowBits, w = loc & kWindowMask;
+        uint32_t score = ld_dev(&h.cnt[i]);
+        for (uint32_t d = 1; d < sws && w + d <= kWindowMask; ++d)
+            score += huge_count(h, mask, (t << kWindowBits) | (w + d));
+        const unsigned long long key = ((unsigned long long)score << 32) | (uint32_t)~loc;
+        const unsigned long long old = atomicMax(&h.best[t], key);
+        if (old == 0ull) h.tlist[atomicAdd(&L.ntarget, 1u)] = t;
+    }
+    __syncthreads();
+
+    // top m targets by (score desc, target asc), one workgroup maximum a round
+    const uint32_t nt = L.ntarget, top_m = a.top_m;
+    uint32_t nsel = 0;
+    for (uint32_t m = 0; m < top_m; ++m) {
+        unsigned long long key = 0;
+        for (uint32_t i = tid; i < nt; i += kHugeThreads) {
+            const uint32_t t = h.tlist[i];
+            bool excluded = false;
+            for (uint32_t x = 0; x < m; ++x) excluded |= L.sel_t[x] == t;
+            const unsigned long long ku = ((ld_dev64(&h.best[t]) >> 32) << 32) | (0xFFFFFFFFu - t);
+            if (!excluded && ku > key) key = ku;
+        }
+        key = block_max_u64(key, L.red);
+        if (key == 0ull) break;
+        if (tid == 0) {
+            const uint32_t t = 0xFFFFFFFFu - (uint32_t)key;
+            const unsigned long long b = ld_dev64(&h.best[t]);
+            L.sel_t[m] = t;
+            L.sel_s[m] = (uint32_t)(key >> 32);
+            L.sel_b[m] = (~(uint32_t)b) & kWindowMask;
+        }
+        __syncthreads();
+        nsel = m + 1;
+    }
+    // the bests go back to zero for the next record
+    for (uint32_t i = tid; i < nt; i += kHugeThreads) h.best[h.tlist[i]] = 0ull;
+
+    if (tid == 0) {
+        uint32_t label = kNone;
+        if (nsel > 0 && L.sel_s[0] >= a.min_hits) {
+            const uint32_t c1 = L.sel_s[0], c2 = nsel > 1 ? L.sel_s[1] : 0u;
+            label = a.target_taxon[L.sel_t[0]];
+            if (c1 - c2 <= a.hit_diff)
+                for (uint32_t x = 1; x < nsel; ++x)
+                    if ((uint64_t)L.sel_s[x] + a.hit_diff >= c1)
+                        label = lca(label, a.target_taxon[L.sel_t[x]], a.parents, a.depth);
+        }
+        a.out_labels[rec] = label;
+    }
+    if (a.out_top && tid < top_m) {
+        const bool hit = tid < nsel;
+        uint32_t* o = a.out_top + ((uint64_t)rec * top_m + tid) * 3;
+        o[0] = hit ? L.sel_t[tid] : kNone;
+        o[1] = hit ? L.sel_s[tid] : 0u;
+        o[2] = hit ? L.sel_b[tid] : 0u;
+    }
+    if (a.qstats) {
+        for (int m = 1; m < kWave; m <<= 1) probes += shfl_xor(probes, m);
+        if (lane == 0 && probes) atomicAdd(&a.qstats[kQsProbes], (unsigned long long)probes);
+        if (tid == 0) {
+            atomicAdd(&a.qstats[kQsFeatures], (unsigned long long)nf);
+            atomicAdd(&a.qstats[kQsLocations], (unsigned long long)n);
+        }
+    }
+    __syncthreads();
+}
+
+// Workgroup r uses region r of the huge scratch and takes records r,
+// r + kHugeGroups, ... of the HBM-list queue (its ids start at n_records).
+template <int KPL>
+__global__ __launch_bounds__(kHugeThreads) void k_classify_huge(QueryArgs a) {
+    __shared__ HugeLds L;
+    const uint32_t n_iter = uniform(a.counters[kQHuge]);
+    const HugeRegion h = huge_region(a.huge, blockIdx.x);
+    const Threshold th(a.S, a.s);
+    for (uint32_t it = blockIdx.x; it < n_iter; it += gridDim.x)
+        classify_huge_record<KPL>(a, uniform(a.queue[a.n_records + it]), h, L, th);
+}
+
 template <uint32_t LCAP, int WPB, int KPL>
 hipError_t launch_fast_t(const QueryArgs& a, uint32_t max_blocks, hipStream_t st) {
     uint64_t blocks = ((uint64_t)a.n_records + WPB - 1) / WPB;
@@ -520,6 +794,15 @@ hipError_t launch_classify_fast(const QueryArgs& a, const ClassifyConfig& c, hip
     if (a.S <= 64) return launch_fast_k<1>(a, c, st);
     if (a.S <= 128) return launch_fast_k<2>(a, c, st);
     return launch_fast_k<4>(a, c, st);
+}
+
+hipError_t launch_classify_huge(const QueryArgs& a, hipStream_t st) {
+    if (a.n_records == 0) return hipSuccess;
+    const dim3 grid(kHugeGroups), blk(kHugeThreads);
+    if (a.S <= 64) hipLaunchKernelGGL(k_classify_huge<1>, grid, blk, 0, st, a);
+    else if (a.S <= 128) hipLaunchKernelGGL(k_classify_huge<2>, grid, blk, 0, st, a);
+    else hipLaunchKernelGGL(k_classify_huge<4>, grid, blk, 0, st, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_classify_large(const QueryArgs& a, hipStream_t st) {

@@ -10,6 +10,7 @@
 #include <deque>
 #include <map>
 #include <mutex>
+#include <set>
 #include <string>
 #include <thread>
 #include <vector>
@@ -57,6 +58,8 @@ struct Slot {
     hipEvent_t copied = nullptr; // its batch's reads are on the device
     char* d_buf = nullptr;
     uint64_t d_cap = 0;
+    uint64_t d_plan = 0;         // device bytes granted by admission (guarded by the
+                                 // server mutex); the worker grows d_buf to it
     char* h_buf = nullptr;       // pinned
     uint64_t h_cap = 0;
     bool busy = false;           // owned by a batch (guarded by the server mutex)
@@ -67,6 +70,11 @@ struct Slot {
 };
 
 uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
+
+// Slot buffers grow in steps of this size (not by doubling, so that the
+// capacity admission counts stays close to what batches need).
+constexpr uint64_t kGrain = 32ull << 20;
+uint64_t round_grain(uint64_t x) { return (x + kGrain - 1) / kGrain * kGrain; }
 
 }  // namespace
 
@@ -79,6 +87,7 @@ struct mc_server {
     std::vector<Slot> slots;
     std::deque<Job> queue;
     std::map<uint64_t, Done> done;
+    std::set<uint64_t> collected;   // tickets already waited on
     std::mutex mu;               // queue, slots' ownership, results, stats
     std::mutex launch_mu;        // calls into the database
     // Reads are copied in one batch at a time, in admission order, on one copy
@@ -93,7 +102,6 @@ struct mc_server {
     std::condition_variable cv_queue, cv_done, cv_slot;
     bool stopping = false;
     uint64_t next_ticket = 1;
-    uint64_t inflight_bytes = 0;
     uint32_t busy_slots = 0;
     std::thread thr;
     // stats
@@ -119,17 +127,18 @@ struct mc_server {
         cv_done.notify_all();
     }
 
-    static int grow(Slot& s, uint64_t need) {
-        if (need > s.d_cap) {
-            uint64_t cap = std::max(need, s.d_cap * 2);
+    // Device buffer of a slot to `dev_cap` bytes, pinned staging to at least
+    // `need` bytes. Called by the slot's worker (or at creation).
+    static int grow(Slot& s, uint64_t need, uint64_t dev_cap) {
+        if (dev_cap > s.d_cap) {
             (void)hipFree(s.d_buf);
             s.d_buf = nullptr;
             s.d_cap = 0;
-            if (hipMalloc((void**)&s.d_buf, cap) != hipSuccess) return MC_ERR_OOM;
-            s.d_cap = cap;
+            if (hipMalloc((void**)&s.d_buf, dev_cap) != hipSuccess) return MC_ERR_OOM;
+            s.d_cap = dev_cap;
         }
         if (need > s.h_cap) {
-            uint64_t cap = std::max(need, s.h_cap * 2);
+            uint64_t cap = std::max(round_grain(need), s.h_cap + s.h_cap / 2);
             (void)hipHostFree(s.h_buf);
             s.h_buf = nullptr;
             s.h_cap = 0;
@@ -181,7 +190,12 @@ struct mc_server {
         const uint64_t off_top = off_labels + align256((uint64_t)j.n * 4);
         const uint64_t top_bytes = (uint64_t)j.n * j.opts.top_m * sizeof(mc_tophit);
         const uint64_t total = off_top + (j.out_top ? align256(top_bytes) : 0);
-        int rc = grow(s, total);
+        uint64_t plan;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            plan = s.d_plan;
+        }
+        int rc = grow(s, total, std::max(plan, total));
         if (rc != MC_OK) return rc;
         uint64_t* ho = reinterpret_cast<uint64_t*>(s.h_buf + off_offsets);
         for (uint64_t i = 0; i <= seg; ++i) ho[i] = j.offsets[i] - base;
@@ -228,7 +242,6 @@ struct mc_server {
             int rc = process(s, s.job);
             std::lock_guard<std::mutex> lk(mu);
             finish_locked(s.job, rc);
-            inflight_bytes -= s.job.dev_need;
             s.job = Job();
             s.has_job = false;
             s.busy = false;
@@ -249,8 +262,51 @@ struct mc_server {
         finish_locked(j, rc);
     }
 
-    // Dispatcher: FIFO order; a batch waits for a free slot and room in the
-    // memory budget; an addition waits until every earlier batch is done.
+    // Device bytes granted to all slots (caller holds mu).
+    uint64_t planned_locked() const {
+        uint64_t t = 0;
+        for (const Slot& s : slots) t += s.d_plan;
+        return t;
+    }
+
+    // A free slot for a batch needing `need` device bytes within the budget,
+    // or null (caller holds mu). The free slot with the smallest buffer that
+    // holds the batch is taken; else the free slot with the largest buffer
+    // grows, if the buffers of all slots together then stay within the
+    // budget; to make room, the buffers of other free slots are released.
+    // A batch never needs more than the budget (submit rejects it), so with
+    // every slot free it always fits.
+    Slot* pick_slot_locked(uint64_t need) {
+        Slot *fit = nullptr, *grower = nullptr;
+        for (Slot& s : slots) {
+            if (s.busy) continue;
+            if (s.d_plan >= need) {
+                if (!fit || s.d_plan < fit->d_plan) fit = &s;
+            } else if (!grower || s.d_plan > grower->d_plan) {
+                grower = &s;
+            }
+        }
+        if (fit) return fit;
+        if (!grower) return nullptr;
+        const uint64_t want = std::max(need, std::min(round_grain(need), budget));
+        if (planned_locked() - grower->d_plan + want > budget) {
+            for (Slot& s : slots) {
+                if (s.busy || &s == grower || !s.d_plan) continue;
+                // a free slot's buffer is not in use: its last batch has synced
+                (void)hipFree(s.d_buf);
+                s.d_buf = nullptr;
+                s.d_cap = 0;
+                s.d_plan = 0;
+            }
+            if (planned_locked() - grower->d_plan + want > budget) return nullptr;
+        }
+        grower->d_plan = want;
+        return grower;
+    }
+
+    // Dispatcher: FIFO order; a batch waits for a free slot whose buffer,
+    // with those of the other slots, fits the memory budget; an addition waits
+    // until every earlier batch is done.
     void loop() {
         (void)hipSetDevice(device);
         std::unique_lock<std::mutex> lk(mu);
@@ -268,16 +324,12 @@ struct mc_server {
             }
             Slot* free_slot = nullptr;
             cv_slot.wait(lk, [&] {
-                free_slot = nullptr;
-                for (auto& s : slots)
-                    if (!s.busy) { free_slot = &s; break; }
-                return free_slot &&
-                       (inflight_bytes + j.dev_need <= budget || busy_slots == 0);
+                free_slot = pick_slot_locked(j.dev_need);
+                return free_slot != nullptr;
             });
             j.order = next_order++;
             free_slot->busy = true;
             free_slot->has_job = true;
-            inflight_bytes += j.dev_need;
             busy_slots += 1;
             free_slot->job = std::move(j);
             free_slot->cv.notify_one();
@@ -311,10 +363,12 @@ mc_server* mc_server_create(mc_db* db, const mc_server_opts* opts) {
     s->slots = std::vector<Slot>(s->n_slots);
     if (opts && opts->staging_bytes) s->staging = opts->staging_bytes;
     bool ok = hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking) == hipSuccess;
+    const uint64_t initial = std::min(round_grain(s->staging), s->budget / s->n_slots);
     for (auto& sl : s->slots) {
         ok = ok && hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess;
         ok = ok && hipEventCreateWithFlags(&sl.copied, hipEventDisableTiming) == hipSuccess;
-        ok = ok && mc_server::grow(sl, s->staging) == MC_OK;
+        ok = ok && mc_server::grow(sl, s->staging, initial) == MC_OK;
+        sl.d_plan = sl.d_cap;
     }
     (void)hipSetDevice(prev);
     if (!ok) {
@@ -348,8 +402,7 @@ int mc_server_submit(mc_server* srv, const char* reads, const uint64_t* offsets,
             return mc::set_error(MC_ERR_INVALID_ARG, "offsets decrease");
     j.bytes = offsets[seg] - offsets[0];
     j.dev_need = align256(j.bytes) + align256((seg + 1) * 8) + align256((uint64_t)n_records * 4) +
-                 (out_top ? align256((uint64_t)n_records * opts->top_m * sizeof(mc_tophit)) : 0) +
-                 (uint64_t)n_records * 4;   // overflow queue of the workspace
+                 (out_top ? align256((uint64_t)n_records * opts->top_m * sizeof(mc_tophit)) : 0);
     if (j.dev_need > srv->budget)
         return mc::set_error(MC_ERR_INVALID_ARG, "batch larger than the memory budget");
     j.t_submit = Clock::now();
@@ -395,6 +448,9 @@ int mc_server_wait(mc_server* srv, uint64_t ticket, double* latency_ms) {
     std::unique_lock<std::mutex> lk(srv->mu);
     if (ticket == 0 || ticket >= srv->next_ticket)
         return mc::set_error(MC_ERR_INVALID_ARG, "unknown ticket");
+    if (srv->collected.count(ticket))
+        return mc::set_error(MC_ERR_INVALID_ARG, "ticket already waited on");
+    srv->collected.insert(ticket);   // a concurrent second wait on it fails too
     srv->cv_done.wait(lk, [&] { return srv->done.count(ticket) != 0; });
     Done d = srv->done[ticket];
     srv->done.erase(ticket);

@@ -335,6 +335,50 @@ def scale_reads(genomes: Genomes, n: int = 10_000_000, seed: int = 202, progress
     return sample_reads(genomes, n, 150, seed, error=0.01, foreign=0.05, progress=progress)
 
 
+_READS_JOB = None   # (genomes, shared output text) while the workers of stream_reads run
+
+
+def _reads_block(args) -> None:
+    """Worker of :func:`stream_reads`: block b of the reads into the shared text."""
+    seed, b, first, m, length, error, foreign = args
+    genomes, text = _READS_JOB
+    blk = sample_reads(genomes, m, length, seed * 1_000_003 + b, error=error, foreign=foreign,
+                       chunk=m)
+    text[first * length:(first + m) * length] = blk.text
+
+
+def stream_reads(genomes: Genomes, n: int, seed: int, length: int = 150, error: float = 0.01,
+                 foreign: float = 0.05, block: int = 1_000_000, workers: int = 16,
+                 progress=None) -> Reads:
+    """``n`` fixed-length reads (module rules) for a large read stream, drawn in
+    blocks of ``block`` reads by forked workers into one shared mapping. Block
+    b is drawn from its own seed, so the reads do not depend on the number of
+    workers. Call it before the process touches a GPU."""
+    import mmap
+    import multiprocessing as mp
+    import sys
+    global _READS_JOB
+    torch = sys.modules.get("torch")
+    if torch is not None and torch.cuda.is_initialized():
+        raise RuntimeError("stream_reads forks worker processes: call it before the process "
+                           "touches a GPU")
+    size = n * length
+    buf = mmap.mmap(-1, max(size, 1), flags=mmap.MAP_SHARED | mmap.MAP_ANONYMOUS)
+    text = np.frombuffer(buf, dtype=np.uint8, count=size)
+    jobs = [(seed, b, f, min(block, n - f), length, error, foreign)
+            for b, f in enumerate(range(0, n, block))]
+    _READS_JOB = (genomes, text)
+    try:
+        with mp.get_context("fork").Pool(workers) as pool:
+            for i, _ in enumerate(pool.imap_unordered(_reads_block, jobs)):
+                if progress is not None and i % 10 == 9:
+                    progress(f"reads {min(n, (i + 1) * block)}/{n}")
+    finally:
+        _READS_JOB = None
+    offsets = np.arange(n + 1, dtype=np.uint64) * np.uint64(length)
+    return Reads(text, offsets, False)
+
+
 def mixed_records(genomes: Genomes, n: int, seed: int = 301, error: float = 0.01,
                   foreign: float = 0.05, chunk: int = 100_000, progress=None) -> Reads:
     """Uneven batch in the paired layout.

@@ -1,16 +1,35 @@
 """Captured query graphs and the launch-shape autotuner.
 
-Every launch shape must give identical labels and top hits; a captured graph
-must reproduce the eager result on every replay (with eager work and input
-changes between replays) and be captured again after the database changes.
+Every launch shape, the shape the autotuner keeps and every graph replay must
+give the oracle's labels and top hits (with eager work and input changes
+between replays), and a graph must be captured again after the database
+changes.
 """
 import numpy as np
 import pytest
 
+import oracle as orc
 import paper_2106_08150_amd as mc
 from paper_2106_08150_amd import synth
 
 pytestmark = pytest.mark.gpu
+
+
+def oracle_results(g, recs, n_targets=None):
+    """Oracle labels and top hits of the paired-layout records (as int32, the
+    dtype of the device tensors) against the first n_targets genomes."""
+    odb = orc.OracleDB()
+    n = g.lengths.size if n_targets is None else n_targets
+    odb.add_targets(g.text[:int(g.offsets[n])], g.lengths[:n], g.taxa[:n], threads=8)
+    odb.set_taxonomy(g.parents)
+    lab, top = odb.classify(recs.text, recs.offsets, paired=True, insert_size=400, threads=8)
+    return lab.view(np.int32), top.view(np.int32)
+
+
+def assert_oracle(want, lab, top=None):
+    assert np.array_equal(lab.cpu().numpy(), want[0])
+    if top is not None:
+        assert np.array_equal(top.cpu().numpy(), want[1])
 
 
 @pytest.fixture(scope="module")
@@ -26,16 +45,24 @@ def setup():
     return torch, g, db, recs
 
 
+@pytest.fixture(scope="module")
+def want(setup):
+    _, g, _, recs = setup
+    return oracle_results(g, recs)
+
+
 def dev(torch, recs):
     r = torch.from_numpy(recs.text.copy()).cuda()
     o = torch.from_numpy(recs.offsets.view(np.int64).copy()).cuda()
     return r, o
 
 
-def test_all_launch_shapes_agree(setup):
+def test_all_launch_shapes_agree(setup, want):
     torch, g, db, recs = setup
     r, o = dev(torch, recs)
     ref = db.classify(r, o, recs.n_records, paired=True, insert_size=400, with_top=True)
+    torch.cuda.synchronize()
+    assert_oracle(want, *ref)
     for cap in (256, 512, 1024):
         for wpb in (2, 4, 8):
             for blocks in (1, 37, 16384):
@@ -49,7 +76,7 @@ def test_all_launch_shapes_agree(setup):
     mc.mc_db_set_launch_config(db.h, 512, 4, 16384)
 
 
-def test_autotune_keeps_results(setup):
+def test_autotune_keeps_results(setup, want):
     torch, g, db, recs = setup
     r, o = dev(torch, recs)
     ref, _ = db.classify(r, o, recs.n_records, paired=True, insert_size=400)
@@ -57,15 +84,17 @@ def test_autotune_keeps_results(setup):
     out = torch.empty(recs.n_records, dtype=torch.int32, device="cuda")
     cfg, ms = mc.mc_db_autotune(db.h, r, o, recs.n_records, mc.QueryOpts(4, 4, 0, 400, 1), out)
     assert ms > 0 and cfg == mc.mc_db_get_launch_config(db.h)
-    lab, _ = db.classify(r, o, recs.n_records, paired=True, insert_size=400)
+    lab, top = db.classify(r, o, recs.n_records, paired=True, insert_size=400, with_top=True)
     torch.cuda.synchronize()
     assert torch.equal(lab, ref) and torch.equal(out, ref)
+    assert_oracle(want, lab, top)     # the tuned shape against the oracle
     mc.mc_db_set_launch_config(db.h, 512, 4, 16384)
 
 
-def test_graph_replays_match_eager(setup):
+def test_graph_replays_match_eager(setup, want):
     torch, g, db, recs = setup
     other = synth.mixed_records(g, recs.n_records, seed=99)
+    want2 = oracle_results(g, other)
     r, o = dev(torch, recs)
     r2, o2 = dev(torch, other)
     n = recs.n_records
@@ -81,14 +110,15 @@ def test_graph_replays_match_eager(setup):
     go.copy_(o)
     graph = mc.ClassifyGraph(db.h, gr, go, n, opts, lab, top)
     for rep in range(4):
-        src, so, want = ((r, o, eager1) if rep % 2 == 0 else (r2, o2, eager2))
+        src, so, expect = ((r, o, eager1) if rep % 2 == 0 else (r2, o2, eager2))
         gr[:src.numel()].copy_(src)
         go.copy_(so)
         lab.fill_(-7)
         top.fill_(-7)
         graph.launch()
         torch.cuda.synchronize()
-        assert torch.equal(lab, want[0]) and torch.equal(top, want[1]), rep
+        assert torch.equal(lab, expect[0]) and torch.equal(top, expect[1]), rep
+        assert_oracle(want if rep % 2 == 0 else want2, lab, top)
         # eager work between replays
         db.classify(r2, o2, n, paired=True, insert_size=400)
         torch.cuda.synchronize()
@@ -111,7 +141,9 @@ def test_graph_recaptured_after_addition(setup):
     db.add_targets(g.text[int(off[4]):], g.lengths[4:], g.taxa[4:])
     graph.launch()
     torch.cuda.synchronize()
-    want, _ = db.classify(r, o, n, paired=True, insert_size=400)
+    now, _ = db.classify(r, o, n, paired=True, insert_size=400)
     torch.cuda.synchronize()
-    assert torch.equal(lab, want) and not torch.equal(before, want)
+    assert torch.equal(lab, now) and not torch.equal(before, now)
+    assert_oracle(oracle_results(g, recs, 4), before)
+    assert_oracle(oracle_results(g, recs), lab)
     graph.close()

@@ -34,8 +34,10 @@ def dev_off(torch, off):
     return torch.from_numpy(np.ascontiguousarray(off, dtype=np.uint64).view(np.int64)).cuda()
 
 
-def build_both(torch, g, k=16, w=128, s=16, cap=254, splits=None):
+def build_both(torch, g, k=16, w=128, s=16, cap=254, splits=None, path=None):
     gdb = mc.Database(k, w, s, cap)
+    if path:
+        mc.mc_db_set_insert_path(gdb.h, **path)
     odb = orc.OracleDB(k, w, s, cap)
     off = g.offsets
     for a, b in (splits or [(0, g.lengths.size)]):
@@ -271,23 +273,58 @@ def test_homopolymer_and_sentinel_feature(torch):
     assert gl[0] == 2
 
 
-def test_record_over_large_list_capacity_is_reported(torch):
-    """A record whose candidate list exceeds 16384 locations is reported and
-    left unclassified (both other records still match the oracle)."""
+def test_long_records_match_oracle(torch):
+    """Records whose candidate lists exceed the LDS passes (16,384 locations)
+    take the HBM-list pass and still equal the oracle: on 300 identical
+    genomes every feature holds 254 locations, so 2 x 600 bp mates gather
+    12 windows x 16 x 254 = 48,768 locations, 2 x 1,000 bp mates 73,152 and a
+    5,000 bp read 44 windows' worth; short records around them take the
+    fast and large-list passes in the same launch."""
     g = synth.repeated_genome(300, 20_000, seed=21)
     gdb, odb = build_both(torch, g)
     g0 = g.genome(0)
-    # 2 x 600 bp mates: 12 windows x 16 features x 254 locations > 16384
-    pieces = [g0[0:100].tobytes(), b"", g0[1000:1600].tobytes(), g0[5000:5600].tobytes(),
-              g0[100:250].tobytes(), g0[300:450].tobytes()]
+    pieces = [g0[0:100], g0[:0], g0[1000:1600], g0[5000:5600],        # short; 2 x 600
+              g0[100:250], g0[300:450],                                # 2 x 150
+              g0[2000:3000], synth.reverse_complement_text(g0[4000:5000]),   # 2 x 1,000
+              g0[7000:12000], g0[:0],                                  # 5,000 bp single
+              g0[15000:18000], g0[:0],                                 # 3,000 bp single
+              g0[300:400], g0[:0]]                                     # short
     off = np.zeros(len(pieces) + 1, np.uint64)
-    off[1:] = np.cumsum([len(p) for p in pieces])
-    reads = synth.Reads(np.frombuffer(b"".join(pieces), np.uint8), off, paired=True)
-    gl, gt, ol, ot = classify_both(torch, gdb, odb, reads, paired=True, min_hits=1)
+    off[1:] = np.cumsum([p.size for p in pieces])
+    reads = synth.Reads(np.concatenate(pieces), off, paired=True)
+    for opts in (dict(min_hits=1), dict(min_hits=1, insert_size=2500, top_m=8),
+                 dict(hit_diff=40, top_m=3)):
+        print(f"long records, options {opts}", flush=True)
+        gl, gt, ol, ot = classify_both(torch, gdb, odb, reads, paired=True, **opts)
+        assert_same_results(gl, gt, ol, ot)
+        assert mc.mc_db_query_status(gdb.h) == 0
+    assert (gl[1:5] != UNCL).all()
+
+
+def test_record_beyond_hbm_list_capacity_is_reported(torch):
+    """A record with more than 2^20 candidate locations (a 40 kbp read on 300
+    identical genomes: about 1.4M) is reported and left unclassified; the
+    records around it still match the oracle."""
+    g = synth.repeated_genome(300, 20_000, seed=21)
+    gdb, odb = build_both(torch, g)
+    g0 = g.genome(0)
+    pieces = [g0[0:100], np.concatenate([g0, g0]), g0[500:650]]
+    off = np.zeros(len(pieces) + 1, np.uint64)
+    off[1:] = np.cumsum([p.size for p in pieces])
+    reads = synth.Reads(np.concatenate(pieces), off)
+    r = dev_u8(torch, reads.text)
+    o = dev_off(torch, reads.offsets)
+    labels, top = gdb.classify(r, o, 3, min_hits=1, with_top=True)
+    torch.cuda.synchronize()
+    gl = labels.cpu().numpy().view(np.uint32)
+    gt = top.cpu().numpy().view(np.uint32)
     assert mc.mc_db_query_status(gdb.h) == 1
-    assert gl[1] == UNCL and (gt[1, :, 0] == UNCL).all()
+    assert gl[1] == UNCL and (gt[1, :, 0] == UNCL).all() and (gt[1, :, 1] == 0).all()
     keep = np.array([0, 2])
-    assert_same_results(gl[keep], gt[keep], ol[keep], ot[keep])
+    sub = synth.Reads(np.concatenate([pieces[0], pieces[2]]),
+                      np.array([0, 100, 250], np.uint64))
+    ol, ot = odb.classify(sub.text, sub.offsets, min_hits=1)
+    assert_same_results(gl[keep], gt[keep], ol, ot)
 
 
 # ------------------------------------------------- several tiles, ragged --
@@ -305,16 +342,16 @@ def test_clustered_midsize(torch):
 
 INSERT_MODES = {
     "slices": {},
-    "staged": {"MC_SLICE_STAGE": "512"},
-    "direct": {"MC_SLICE_DIRECT": "0"},
-    "global": {"MC_INSERT": "global", "MC_PART_MB": "1"},
-    "fine1024": {"MC_SLICE_SHIFT": "5", "MC_FINE_BITS": "10"},
-    "chunks": {"MC_CHUNK_SLOTS": "20000"},
+    "staged": {"stage_entries": 512},
+    "direct": {"direct": 1},
+    "global": {"global_insert": 1, "part_mb": 1},
+    "fine1024": {"slice_shift": 5, "fine_bits": 10},
+    "chunks": {"chunk_slots": 20000},
 }
 
 
 @pytest.mark.parametrize("mode", list(INSERT_MODES))
-def test_insert_modes_agree(torch, monkeypatch, mode):
+def test_insert_modes_agree(torch, mode):
     """Every insert path stores the oracle's pairs, over two add calls (the
     second fills buckets the first left partly full): the slice-local insert
     (default), the same with a 512-pair staging buffer (many rounds a slice),
@@ -324,10 +361,8 @@ def test_insert_modes_agree(torch, monkeypatch, mode):
     largest level-2 scatter, as the largest tables use), and an add built in
     chunks of about 20,000 pair slots (every chunk after the first inserts
     into a table that already holds entries)."""
-    for k, v in INSERT_MODES[mode].items():
-        monkeypatch.setenv(k, v)
     g = synth.clustered_genomes(4, 5, 2e6, seed=47, median_bp=1e5, clip=(3e3, 3e5))
-    db, odb = build_both(torch, g, splits=[(0, 7), (7, 20)])
+    db, odb = build_both(torch, g, splits=[(0, 7), (7, 20)], path=INSERT_MODES[mode])
     assert_same_table(db, odb)
     reads = synth.sample_reads(g, 3000, 150, seed=48)
     gl, gt, ol, ot = classify_both(torch, db, odb, reads)
@@ -335,15 +370,15 @@ def test_insert_modes_agree(torch, monkeypatch, mode):
 
 
 @pytest.mark.parametrize("mode", ["slices", "direct"])
-def test_sparse_fresh_table(torch, monkeypatch, mode):
+def test_sparse_fresh_table(torch, mode):
     """A first insert into a table far larger than its pairs (load factor
     1e-4, so most slices hold no pair): the insert that clears the new table
     as it writes must leave every other slot empty and every other counter
     zero; a second add then grows the table by a rehash."""
-    for k, v in INSERT_MODES[mode].items():
-        monkeypatch.setenv(k, v)
     g = synth.tiny_genomes(length=30_000)
     gdb = mc.Database(16, 128, 16, 254)
+    if INSERT_MODES[mode]:
+        mc.mc_db_set_insert_path(gdb.h, **INSERT_MODES[mode])
     gdb.reserve(0, 1e-4)
     odb = orc.OracleDB(16, 128, 16, 254)
     off = g.offsets
@@ -359,6 +394,73 @@ def test_sparse_fresh_table(torch, monkeypatch, mode):
     assert_same_table(gdb, odb)
     reads = synth.sample_reads(g, 1000, 100, seed=5)
     gl, gt, ol, ot = classify_both(torch, gdb, odb, reads, min_hits=1)
+    assert_same_results(gl, gt, ol, ot)
+
+
+def test_failed_add_is_rolled_back(torch):
+    """An add that fails after its inserts ran (forced from the host) leaves
+    no entry of its targets: the table equals the one before the call (its
+    slots turned into tombstones), the target count is unchanged, and the same
+    genomes added again afterwards give the oracle's table and results."""
+    g = synth.clustered_genomes(3, 4, 1.2e6, seed=51, median_bp=1e5, clip=(3e3, 3e5))
+    off = g.offsets
+    gdb = mc.Database()
+    gdb.add_targets(dev_u8(torch, g.text[:int(off[5])]), g.lengths[:5], g.taxa[:5])
+    f0, l0 = gdb.dump()
+    st0 = gdb.stats()
+    mc.mc_db_set_insert_path(gdb.h, fail_after=1)
+    with pytest.raises(mc.MCError) as e:
+        gdb.add_targets(dev_u8(torch, g.text[int(off[5]):]), g.lengths[5:], g.taxa[5:])
+    assert e.value.code == mc.MC_ERR_TABLE_FULL
+    f1, l1 = gdb.dump()
+    assert np.array_equal(f0, f1) and np.array_equal(l0, l1)
+    st1 = gdb.stats()
+    assert st1["n_targets"] == 5 and st1["n_pairs_stored"] == st0["n_pairs_stored"]
+    assert st1["n_tombstones"] > 0 and st1["n_features"] == st0["n_features"]
+    gdb.add_targets(dev_u8(torch, g.text[int(off[5]):]), g.lengths[5:], g.taxa[5:])
+    gdb.set_taxonomy(g.parents)
+    odb = orc.OracleDB()
+    odb.add_targets(g.text, g.lengths, g.taxa, threads=8)
+    odb.set_taxonomy(g.parents)
+    assert_same_table(gdb, odb)
+    st2 = gdb.stats()
+    assert st2["n_features"] == odb.num_features and st2["n_pairs_stored"] == odb.num_pairs
+    assert 0 < st2["load_factor"] < 1
+    reads = synth.sample_reads(g, 2000, 150, seed=52, foreign=0.05)
+    gl, gt, ol, ot = classify_both(torch, gdb, odb, reads)
+    assert_same_results(gl, gt, ol, ot)
+
+
+def test_addition_waits_for_classification_in_flight(torch):
+    """A classification queued on a side stream is not disturbed by an
+    addition issued right after it without any host synchronisation: it sees
+    the table as it was, and the next one sees the new targets."""
+    g = synth.tiny_genomes(length=60_000)
+    off = g.offsets
+    gdb = mc.Database()
+    gdb.add_targets(dev_u8(torch, g.text[:int(off[4])]), g.lengths[:4], g.taxa[:4])
+    gdb.set_taxonomy(g.parents)
+    reads = synth.sample_reads(g, 200_000, 100, seed=53)
+    r = dev_u8(torch, reads.text)
+    o = dev_off(torch, reads.offsets)
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        lab, top = gdb.classify(r, o, reads.n_records, with_top=True, stream=side)
+    gdb.add_targets(dev_u8(torch, g.text[int(off[4]):]), g.lengths[4:], g.taxa[4:])
+    side.synchronize()
+    gl = lab.cpu().numpy().view(np.uint32)
+    gt = top.cpu().numpy().view(np.uint32)
+    before = orc.OracleDB()
+    before.add_targets(g.text[:int(off[4])], g.lengths[:4], g.taxa[:4], threads=8)
+    before.set_taxonomy(g.parents)
+    ol, ot = before.classify(reads.text, reads.offsets, first=0, count=20_000, threads=8)
+    assert_same_results(gl[:20_000], gt[:20_000], ol, ot)
+    after = orc.OracleDB()
+    after.add_targets(g.text, g.lengths, g.taxa, threads=8)
+    after.set_taxonomy(g.parents)
+    small = synth.sample_reads(g, 3000, 100, seed=54)
+    gl, gt, ol, ot = classify_both(torch, gdb, after, small)
     assert_same_results(gl, gt, ol, ot)
 
 

@@ -46,8 +46,15 @@ def run(torch, g, reads, reserve):
     return out, table_bytes
 
 
+@pytest.fixture()
+def keep_blocks():
+    mc.mc_set_cached_memory_limit(64 << 30)
+    yield
+    mc.mc_set_cached_memory_limit(0)
+
+
 @pytest.mark.parametrize("reserve", [0, 20_000_000])
-def test_rebuild_on_reused_blocks(torch, sets, reserve):
+def test_rebuild_on_reused_blocks(torch, sets, reserve, keep_blocks):
     a, b, reads = sets
     print(f"reuse case: reserve={reserve}", flush=True)
     first, table_bytes = run(torch, a, reads, reserve)

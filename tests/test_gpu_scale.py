@@ -1,7 +1,9 @@
-"""Parity at the benchmark's full size, in the benchmark's launch configuration.
+"""Parity at the benchmark's full size, in the benchmark's launch configurations.
 
 The at-scale reference set (1,000 genomes, about 4 Gbp) is built on the GPU
-from HBM-resident text and all 10M reads are classified in one launch. The
+from HBM-resident text and all 10M reads are classified in one launch, once
+with the shape the benchmark times ({256 locations, 4 waves, 16,384
+workgroups}) and once with the library's default ({512, 4, 16,384}). The
 oracle cannot hold that index, so it checks what it can compute exactly:
 
 * a read sample of 3,000 reads spread over the set: the oracle indexes only
@@ -23,6 +25,7 @@ pytestmark = pytest.mark.gpu
 
 UNCL = 0xFFFFFFFF
 SLICE_HI = (1 << 20) - 1
+SHAPES = [(256, 4, 16384), (512, 4, 16384)]   # the benchmark's, the library default
 
 
 @pytest.mark.timeout(600)
@@ -40,10 +43,14 @@ def test_at_scale_sampled_parity():
     db.set_taxonomy(g.parents)
     r = torch.from_numpy(reads.text).cuda()
     o = torch.from_numpy(reads.offsets.view(np.int64)).cuda()
-    labels, top = db.classify(r, o, n, with_top=True)
-    torch.cuda.synchronize()
-    gl = labels.cpu().numpy().view(np.uint32)
-    gt = top.cpu().numpy().view(np.uint32)
+    results = {}
+    for shape in SHAPES:
+        print(f"[scale] classify with launch shape {shape}", flush=True)
+        mc.mc_db_set_launch_config(db.h, *shape)
+        labels, top = db.classify(r, o, n, with_top=True)
+        torch.cuda.synchronize()
+        results[shape] = (labels.cpu().numpy().view(np.uint32), top.cpu().numpy().view(np.uint32))
+        del labels, top
     st = db.stats()
     gf, gloc = db.dump(0, SLICE_HI)
     print(f"[scale] gpu done: {st['n_pairs_stored']} pairs, slice {gf.size}", flush=True)
@@ -52,8 +59,10 @@ def test_at_scale_sampled_parity():
     S = 128 - 16 + 1
     assert st["n_windows"] == int(sum(-(-(int(L) - 15) // S) for L in g.lengths))
     assert st["n_pairs_stored"] == st["n_pairs_inserted"]
-    valid = (gl == UNCL) | (gl < g.parents.size)
-    assert valid.all()
+    assert st["n_features"] <= st["n_pairs_stored"] and st["n_tombstones"] == 0
+    for gl, _ in results.values():
+        valid = (gl == UNCL) | (gl < g.parents.size)
+        assert valid.all()
     assert mc.mc_db_query_status(db.h) == 0
 
     # oracle on a sample and a feature slice
@@ -69,11 +78,11 @@ def test_at_scale_sampled_parity():
     of, oloc = odb.dump()
     keep = of <= SLICE_HI
     assert np.array_equal(gf, of[keep]) and np.array_equal(gloc, oloc[keep])
-    bad = []
-    for j, i in enumerate(sample):
-        ol, ot = odb.classify(reads.text, reads.offsets, first=int(i), count=1)
-        if ol[0] != gl[i] or not np.array_equal(ot[0], gt[i]):
-            bad.append(int(i))
-    print(f"[scale] sample of {sample.size}: {len(bad)} mismatches", flush=True)
-    assert not bad, bad[:10]
+    want = [odb.classify(reads.text, reads.offsets, first=int(i), count=1) for i in sample]
+    for shape, (gl, gt) in results.items():
+        bad = [int(i) for (ol, ot), i in zip(want, sample)
+               if ol[0] != gl[i] or not np.array_equal(ot[0], gt[i])]
+        print(f"[scale] shape {shape}, sample of {sample.size}: {len(bad)} mismatches",
+              flush=True)
+        assert not bad, (shape, bad[:10])
     db.close()

@@ -118,3 +118,41 @@ def test_budget_rejects_oversized_batch(torch):
     lab, _, _ = srv.wait(srv.submit(small.text, small.offsets))
     assert lab.size == 5
     srv.close()
+
+
+def test_ticket_waited_twice_is_rejected(torch):
+    g = synth.tiny_genomes(length=5000)
+    db = mc.Database()
+    db.add_targets(g.text, g.lengths, g.taxa)
+    db.set_taxonomy(g.parents)
+    srv = mc.Server(db, slots=2)
+    reads = synth.sample_reads(g, 50, 100, seed=2)
+    t = srv.submit(reads.text, reads.offsets)
+    lab, _, _ = srv.wait(t)
+    assert lab.size == 50
+    with pytest.raises(mc.MCError) as e:
+        srv.wait(t)
+    assert e.value.code == mc.MC_ERR_INVALID_ARG
+    srv.close()
+
+
+def test_budget_shared_by_slots(torch):
+    """Batches that each fit the budget but not all at once: slots take turns
+    (free slots give their buffers back), every batch completes with the
+    labels it gets alone."""
+    g = synth.tiny_genomes(length=20_000)
+    db = mc.Database()
+    db.add_targets(g.text, g.lengths, g.taxa)
+    db.set_taxonomy(g.parents)
+    reads = synth.sample_reads(g, 400_000, 100, seed=8)
+    cuts = [0, 150_000, 151_000, 300_000, 301_000, 400_000]
+    batches = [sub_batch(reads, a, b) for a, b in zip(cuts[:-1], cuts[1:])]
+    alone = [plain(torch, db, r, False) for r in batches]
+    # a 150k-read batch needs about 17 MB of device buffers; 40 MiB for four
+    # slots lets at most two large ones in flight
+    srv = mc.Server(db, slots=4, memory_budget=40 << 20, staging_bytes=1 << 20)
+    tickets = [srv.submit(r.text, r.offsets, with_top=True) for r in batches]
+    for (lab0, top0), t in zip(alone, tickets):
+        lab, top, _ = srv.wait(t)
+        assert np.array_equal(lab, lab0) and np.array_equal(top, top0)
+    srv.close()
