@@ -486,6 +486,7 @@ def large_leg(args, g, stream, torch, mc):
     else:
         shape = tuple(int(x) for x in args.large_shape.split(","))
         mc.mc_db_set_launch_config(db.h, *shape)
+    m = min(nk, 2_000_000)
     st0 = db.stats()
     cls = []
     for i in range(1 + 3):
@@ -499,8 +500,34 @@ def large_leg(args, g, stream, torch, mc):
     kt_cls = mc.mc_db_kernel_times(db.h)
     st = db.stats()
     kernel_labels = klab.cpu().numpy().view(np.uint32).copy()
-    del rt, ro, klab
     log(f"large: kernel classify {nk} reads {np.mean(cls):.2f} ms")
+    # the condensed layout (bucket table kept): conversion time, kernel rate
+    torch.cuda.synchronize()
+    t_c = time.perf_counter()
+    db.condense()
+    condense_ms = (time.perf_counter() - t_c) * 1e3
+    cst = db.stats()
+    if args.large_shape == "auto":
+        cshape, _ = mc.mc_db_autotune(db.h, rt, ro[:m + 1].contiguous(), m, opts, klab)
+    else:
+        cshape = shape
+    ccls = []
+    for i in range(1 + 3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        mc.mc_classify_ex(db.h, rt, ro, nk, opts, klab)
+        e1.record()
+        torch.cuda.synchronize()
+        if i:
+            ccls.append(e0.elapsed_time(e1))
+    cond_same = bool(np.array_equal(klab.cpu().numpy().view(np.uint32), kernel_labels))
+    condensed = {"condense_ms": condense_ms, "condensed_bytes": cst["condensed_bytes"],
+                 "launch_shape": list(cshape), "kernel_classify_ms": float(np.mean(ccls)),
+                 "kernel_reads_per_s": nk / (np.mean(ccls) * 1e-3),
+                 "labels_identical_to_bucket_table": cond_same}
+    log(f"large: condensed layout in {condense_ms:.0f} ms ({cst['condensed_bytes'] / 1e9:.1f} GB), "
+        f"kernel classify {np.mean(ccls):.2f} ms, identical {cond_same}")
+    del rt, ro, klab
 
     # the stream: batches in pinned host memory (views of one pinned buffer)
     B = args.large_batch
@@ -597,6 +624,7 @@ def large_leg(args, g, stream, torch, mc):
                   "probes_per_feature": q_probes / max(1, q_feats),
                   "classified_frac": float((kernel_labels != mc.MC_UNCLASSIFIED).mean())},
         "oracle_parity": parity,
+        "condensed": condensed,
     }
 
 
@@ -698,6 +726,30 @@ def main():
 
     st = live[0].stats()
     gpu_labels = labels.cpu().numpy().view(np.uint32)
+    # the same classification from the condensed layout of the last step's table
+    db = live[0]
+    torch.cuda.synchronize()
+    t_c = time.perf_counter()
+    db.condense()
+    condense_ms = (time.perf_counter() - t_c) * 1e3
+    cbytes = db.stats()["condensed_bytes"]
+    c_ms = []
+    for i in range(4):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        mc.mc_classify_ex(db.h, rtext, roff, n, opts, labels)
+        e1.record()
+        torch.cuda.synchronize()
+        if i:
+            c_ms.append(e0.elapsed_time(e1))
+    condensed = {"condense_ms": condense_ms, "condensed_bytes": cbytes,
+                 "classify_ms": float(np.mean(c_ms)),
+                 "reads_per_s": n / (np.mean(c_ms) * 1e-3),
+                 "launch_shape": list(shape),
+                 "labels_identical_to_bucket_table":
+                     bool(np.array_equal(labels.cpu().numpy().view(np.uint32), gpu_labels))}
+    log(f"condensed layout: {condense_ms:.0f} ms, {cbytes / 1e9:.2f} GB, classify "
+        f"{np.mean(c_ms):.2f} ms")
     live.pop().close()
     # one more build that starts from the genomes in pinned host memory
     h2d_build_ms = step(copy_in=True)[0]
@@ -787,6 +839,7 @@ def main():
                   "probes_per_feature": q_probes / max(1, q_feats),
                   "classified_frac": float((gpu_labels != mc.MC_UNCLASSIFIED).mean())},
         "roofline": roofline,
+        "condensed": condensed,
         "cpu_baseline": None,
     }
     if args.uneven_records > 0:

@@ -104,6 +104,8 @@ typedef struct mc_db_stats {
                                   the rollback of a failed add              */
     double load_factor;        /* occupied slots (stored + tombstones) over
                                   all slots of the table                    */
+    uint64_t condensed_bytes;  /* device bytes of the condensed layout (0 if
+                                  none, see mc_db_condense)                 */
 } mc_db_stats;
 
 /* Text of the calling thread's last error ("" if none). Never NULL. */
@@ -249,6 +251,26 @@ mc_graph* mc_classify_graph_create(mc_db* db, const char* reads, const uint64_t*
                                    uint32_t* out_labels, mc_tophit* out_top, void* stream);
 int mc_classify_graph_launch(mc_graph* g, void* stream);
 int mc_classify_graph_destroy(mc_graph* g);
+
+/* Condensed query layout (Sec. 4.2, Sec. 5.1). Converts the current bucket
+ * table (synchronously) into one 16-byte index entry per feature, in buckets
+ * of eight (one 128-byte line) sized for a load of about one half, plus an
+ * array with the ascending locations of every feature that has more than two
+ * (a feature with one or two holds them in its entry). Later classifications
+ * use it: a lookup reads one index line, and one contiguous run for features
+ * with more than two locations, instead of the feature's bucket chain.
+ * Results are the same as from the bucket table.
+ * release_table = 0: the bucket table stays; an add (mc_db_add_targets*)
+ *   drops the condensed layout and later classifications use the table again
+ *   until mc_db_condense is called anew.
+ * release_table = 1: the bucket table is freed (the query-only form): adds and
+ *   mc_db_reserve then fail with MC_ERR_STATE; mc_db_dump reads the condensed
+ *   layout; mc_db_get_stats reports its counts (no buckets, no tombstones).
+ * Device memory during the call: the layout itself plus 12 bytes per 256
+ * buckets of the table. Errors: MC_ERR_STATE (table already released),
+ * MC_ERR_CAPACITY (more than 8,192 entries homed in 256 consecutive buckets,
+ * which a table at the library's load factors does not reach), MC_ERR_OOM. */
+int mc_db_condense(mc_db* db, int release_table);
 
 /* Counters of the handle (synchronous; counts the table's slots). */
 int mc_db_get_stats(mc_db* db, mc_db_stats* out);

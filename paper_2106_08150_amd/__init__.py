@@ -42,6 +42,7 @@ EXPORTS = [
     "mc_db_set_launch_config", "mc_db_get_launch_config", "mc_db_autotune",
     "mc_classify_graph_create", "mc_classify_graph_launch", "mc_classify_graph_destroy",
     "mc_release_cached_memory", "mc_set_cached_memory_limit", "mc_db_set_insert_path",
+    "mc_db_condense",
 ]
 
 
@@ -60,7 +61,8 @@ class DbStats(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in (
         "n_targets", "n_windows", "n_pairs_inserted", "n_pairs_stored", "n_buckets",
         "table_bytes", "n_cap_candidates", "probe_sum", "n_rehash", "q_features",
-        "q_locations", "q_probes", "n_features", "n_tombstones")] + [("load_factor", C.c_double)]
+        "q_locations", "q_probes", "n_features", "n_tombstones")] + [
+        ("load_factor", C.c_double), ("condensed_bytes", C.c_uint64)]
 
     def as_dict(self) -> dict:
         return {n: (float(getattr(self, n)) if t is C.c_double else int(getattr(self, n)))
@@ -117,6 +119,7 @@ def lib():
         L.mc_release_cached_memory.restype, L.mc_release_cached_memory.argtypes = i32, []
         L.mc_set_cached_memory_limit.restype = i32
         L.mc_set_cached_memory_limit.argtypes = [u64]
+        L.mc_db_condense.restype, L.mc_db_condense.argtypes = i32, [vp, i32]
         L.mc_db_set_insert_path.restype = i32
         L.mc_db_set_insert_path.argtypes = [vp, C.POINTER(InsertPath)]
         L.mc_db_reserve.restype, L.mc_db_reserve.argtypes = i32, [vp, u64, C.c_double]
@@ -224,6 +227,10 @@ def mc_db_set_insert_path(db: int, **fields) -> None:
         return
     p = InsertPath(**fields)
     _check(lib().mc_db_set_insert_path(db, C.byref(p)))
+
+
+def mc_db_condense(db: int, release_table: bool = False) -> None:
+    _check(lib().mc_db_condense(db, int(release_table)))
 
 
 def mc_db_reserve(db: int, n_pairs: int, load_factor: float = 0.0) -> None:
@@ -401,6 +408,9 @@ class Database:
 
     def reserve(self, n_pairs: int, load_factor: float = 0.0):
         mc_db_reserve(self.h, n_pairs, load_factor)
+
+    def condense(self, release_table: bool = False):
+        mc_db_condense(self.h, release_table)
 
     def add_targets(self, genomes, lengths, taxon_ids):
         """Host arrays (numpy) or a device uint8 tensor for ``genomes``."""

@@ -130,6 +130,13 @@ struct mc_db {
     unsigned long long* chunk_first = nullptr;  // kChunkFirstLen
     // insert path forced by mc_db_set_insert_path (tests); zero = automatic
     mc_insert_path ipath{};
+    // condensed layout (mc_db_condense): classifications use it while it is set
+    unsigned int* cidx = nullptr;      // nbc buckets of kCondEntries 16-byte entries
+    uint64_t nbc = 0;
+    uint32_t* cval = nullptr;          // runs of locations
+    uint64_t cval_n = 0;
+    uint64_t c_features = 0, c_pairs = 0;
+    bool table_released = false;       // only the condensed layout is left
     // fast-path launch shape (set by mc_db_set_launch_config / mc_db_autotune)
     ClassifyConfig cfg;
     // bumped whenever device arrays a captured graph refers to may have moved
@@ -541,9 +548,22 @@ int build_chunk(mc_db* db, const uint8_t* genomes, const std::vector<TargetDesc>
     return MC_OK;
 }
 
+// Forget the condensed layout (after the bucket table changed).
+void drop_condensed(mc_db* db) {
+    if (!db->cidx) return;
+    (void)dev_free(db->cidx);
+    (void)dev_free(db->cval);
+    db->cidx = nullptr;
+    db->cval = nullptr;
+    db->nbc = db->cval_n = db->c_features = db->c_pairs = 0;
+    db->version += 1;
+}
+
 // Shared by the host and device entry points: genomes is a device pointer.
 int add_targets_dev(mc_db* db, const uint8_t* genomes, const uint64_t* lengths,
                     const uint32_t* taxa, uint32_t n, hipStream_t st) {
+    if (db->table_released)
+        return fail(MC_ERR_STATE, "the bucket table was released by mc_db_condense: no additions");
     if (n == 0) return MC_OK;
     if ((uint64_t)db->taxa.size() + n > MC_MAX_TARGETS)
         return fail(MC_ERR_CAPACITY, "at most %u targets (have %zu, adding %u)", MC_MAX_TARGETS,
@@ -563,6 +583,7 @@ int add_targets_dev(mc_db* db, const uint8_t* genomes, const uint64_t* lengths,
     // classifications queued earlier on any stream may still read the table
     // (and a graph replay its arrays): they finish before the table changes
     HIP_TRY(hipDeviceSynchronize());
+    drop_condensed(db);   // classifications use the bucket table from here on
     const uint32_t first_target = (uint32_t)db->taxa.size();
     int rc = MC_OK;
     uint64_t cand_need = std::min<uint64_t>(std::max<uint64_t>(upper, 1), kCandCapMax);
@@ -749,8 +770,14 @@ int classify_launch(mc_db* db, const char* reads, const uint64_t* offsets, uint3
     static_assert(kQOverflow == 0 && kQHuge == 1, "the per-launch queue counters lead");
     HIP_TRY(launch_fill_u32(w.counters, 2, 0u, st));
     QueryArgs a{};
-    a.table = db->table;
-    a.nb = db->nb;
+    if (db->cidx) {   // condensed layout
+        a.table = reinterpret_cast<const unsigned long long*>(db->cidx);
+        a.nb = db->nbc;
+        a.cval = db->cval;
+    } else {
+        a.table = db->table;
+        a.nb = db->nb;
+    }
     a.reads = reinterpret_cast<const uint8_t*>(reads);
     a.offsets = offsets;
     a.n_records = n_records;
@@ -937,6 +964,8 @@ int mc_db_destroy(mc_db* db) {
     for (auto& kv : db->ws) free_workspace(kv.second);
     for (uint32_t* q : db->retired) (void)dev_free(q);
     for (auto& t : db->timers) (void)drain(t, nullptr, nullptr);
+    (void)dev_free(db->cidx);
+    (void)dev_free(db->cval);
     (void)dev_free(db->pairs);
     (void)dev_free(db->parted);
     (void)dev_free(db->hist);
@@ -959,6 +988,7 @@ int mc_db_destroy(mc_db* db) {
 
 int mc_db_reserve(mc_db* db, uint64_t n_pairs, double load_factor) {
     if (int rc = check_db(db)) return rc;
+    if (db->table_released) return fail(MC_ERR_STATE, "the bucket table was released");
     if (load_factor < 0.0 || load_factor > 0.9 || std::isnan(load_factor))
         return fail(MC_ERR_INVALID_ARG, "load_factor %g not in (0, 0.9]", load_factor);
     DeviceGuard dg(db->device);
@@ -1100,10 +1130,16 @@ int mc_db_get_stats(mc_db* db, mc_db_stats* out) {
     int rc = dev_alloc(&cnt, 3);
     if (rc) return rc;
     unsigned long long census[3] = {0, 0, 0};   // live, tombstones, distinct features
-    hipError_t e = materialize(db, nullptr) == MC_OK ? hipSuccess : hipErrorUnknown;
-    if (e == hipSuccess) e = launch_fill_u64(cnt, 3, 0ull, nullptr);
-    if (e == hipSuccess) e = launch_census(db->table, db->nb, cnt, nullptr);
-    if (e == hipSuccess) e = hipMemcpy(census, cnt, sizeof census, hipMemcpyDeviceToHost);
+    hipError_t e = hipSuccess;
+    if (db->table_released) {   // the condensed layout's counts
+        census[0] = db->c_pairs;
+        census[2] = db->c_features;
+    } else {
+        e = materialize(db, nullptr) == MC_OK ? hipSuccess : hipErrorUnknown;
+        if (e == hipSuccess) e = launch_fill_u64(cnt, 3, 0ull, nullptr);
+        if (e == hipSuccess) e = launch_census(db->table, db->nb, cnt, nullptr);
+        if (e == hipSuccess) e = hipMemcpy(census, cnt, sizeof census, hipMemcpyDeviceToHost);
+    }
     (void)dev_free(cnt);
     if (e != hipSuccess) return fail(MC_ERR_HIP, "stats: %s", hipGetErrorString(e));
     *out = db->st;
@@ -1121,9 +1157,108 @@ int mc_db_get_stats(mc_db* db, mc_db_stats* out) {
     out->n_pairs_stored = census[0];
     out->n_tombstones = census[1];
     out->n_features = census[2];
-    out->n_buckets = db->nb;
-    out->table_bytes = db->nb * (kSlots * 8 + 4);
-    out->load_factor = db->nb ? (double)(census[0] + census[1]) / (double)(db->nb * kSlots) : 0.0;
+    out->n_buckets = db->table_released ? 0 : db->nb;
+    out->table_bytes = db->table_released ? 0 : db->nb * (kSlots * 8 + 4);
+    out->load_factor = db->nb && !db->table_released
+                           ? (double)(census[0] + census[1]) / (double)(db->nb * kSlots) : 0.0;
+    out->condensed_bytes = db->cidx ? db->nbc * kCondEntries * 16 + db->cval_n * 4 : 0;
+    return MC_OK;
+}
+
+int mc_db_condense(mc_db* db, int release_table) {
+    if (int rc = check_db(db)) return rc;
+    if (db->table_released) return fail(MC_ERR_STATE, "the bucket table was released");
+    DeviceGuard dg(db->device);
+    HIP_TRY(hipDeviceSynchronize());   // classifications in flight read the old layout
+    drop_condensed(db);
+    if (int rc = materialize(db, nullptr)) return rc;
+    CondArgs c{};
+    c.table = db->table;
+    c.nb = db->nb;
+    c.n_slices = (uint32_t)(((db->nb - 1) >> kCondSliceShift) + 1);
+    unsigned long long* tf = nullptr;
+    int rc = dev_alloc(&c.slice_feats, c.n_slices);
+    if (!rc) rc = dev_alloc(&c.slice_vals, (uint64_t)c.n_slices + 1);
+    if (!rc) rc = dev_alloc(&c.err, 2);
+    if (!rc) rc = dev_alloc(&tf, 1);
+    auto release = [&]() {
+        (void)dev_free(c.slice_feats);
+        (void)dev_free(c.slice_vals);
+        (void)dev_free(c.err);
+        (void)dev_free(tf);
+        (void)dev_free(c.fill);
+    };
+    if (rc) { release(); return rc; }
+    uint32_t err[2] = {0, 0};
+    unsigned long long total_feats = 0, total_vals = 0;
+    hipError_t e = launch_fill_u32(c.err, 2, 0u, nullptr);
+    if (e == hipSuccess) e = launch_condense_count(c, nullptr);
+    if (e == hipSuccess) e = launch_condense_scan(c, tf, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(err, c.err, sizeof err, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(&total_feats, tf, 8, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(&total_vals, c.slice_vals + c.n_slices, 8,
+                                       hipMemcpyDeviceToHost);
+    if (e != hipSuccess) { release(); return fail(MC_ERR_HIP, "condense: %s", hipGetErrorString(e)); }
+    if (err[0]) {
+        release();
+        return fail(MC_ERR_CAPACITY, "a slice of %u buckets holds more than %u entries",
+                    1u << kCondSliceShift, kCondCap);
+    }
+    // index buckets for about four entries of eight each (load 0.5)
+    c.nbc = std::max<uint64_t>(kMinBuckets, (total_feats + 3) / 4);
+    if (c.nbc > 0xFFFFFFFFull) { release(); return fail(MC_ERR_OOM, "index too large"); }
+    rc = dev_alloc(&c.idx, c.nbc * kCondEntries * 4);
+    if (!rc) rc = dev_alloc(&c.fill, c.nbc);
+    if (!rc) rc = dev_alloc(&c.val, std::max<uint64_t>(total_vals, 1));
+    if (rc) {
+        (void)dev_free(c.idx);
+        (void)dev_free(c.val);
+        release();
+        return rc;
+    }
+    e = launch_fill_u64(reinterpret_cast<unsigned long long*>(c.idx), c.nbc * kCondEntries * 2, 0ull,
+                        nullptr);
+    if (e == hipSuccess) e = launch_fill_u32(c.fill, c.nbc, 0u, nullptr);
+    if (e == hipSuccess) e = launch_condense_write(c, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(err, c.err, sizeof err, hipMemcpyDeviceToHost);
+    if (e != hipSuccess || err[1]) {
+        (void)dev_free(c.idx);
+        (void)dev_free(c.val);
+        release();
+        if (e != hipSuccess) return fail(MC_ERR_HIP, "condense: %s", hipGetErrorString(e));
+        return fail(MC_ERR_TABLE_FULL, "condensed index without a free entry");
+    }
+    release();
+    db->cidx = c.idx;
+    db->nbc = c.nbc;
+    db->cval = c.val;
+    db->cval_n = total_vals;
+    db->c_features = total_feats;
+    db->version += 1;
+    // pairs stored: features with one or two locations hold them inline
+    {
+        unsigned long long* cnt = nullptr;
+        if (dev_alloc(&cnt, 1) == MC_OK) {
+            unsigned long long n = 0;
+            if (launch_fill_u64(cnt, 1, 0ull, nullptr) == hipSuccess &&
+                launch_condense_dump(db->cidx, db->nbc, db->cval, 0u, 0xFFFFFFFFu, nullptr, 0,
+                                     cnt, nullptr) == hipSuccess &&
+                hipMemcpy(&n, cnt, 8, hipMemcpyDeviceToHost) == hipSuccess)
+                db->c_pairs = n;
+            (void)dev_free(cnt);
+        }
+    }
+    if (release_table) {
+        HIP_TRY(dev_free(db->table));
+        HIP_TRY(dev_free(db->bcount));
+        db->table = nullptr;
+        db->bcount = nullptr;
+        db->table_released = true;
+        (void)dev_free(db->pairs);
+        (void)dev_free(db->parted);
+        db->pairs = db->parted = nullptr;
+        db->pairs_cap = 0;
+    }
     return MC_OK;
 }
 
@@ -1160,8 +1295,14 @@ int mc_db_dump(mc_db* db, uint32_t feature_lo, uint32_t feature_hi, uint32_t* fe
     unsigned long long n = 0;
     std::vector<unsigned long long> host;
     hipError_t e = launch_fill_u64(cnt, 1, 0ull, nullptr);
-    if (e == hipSuccess) e = launch_dump(db->table, db->nb, feature_lo, feature_hi, buf, capacity,
-                                         cnt, nullptr);
+    if (e == hipSuccess) {
+        if (db->table_released)   // only the condensed layout is left
+            e = launch_condense_dump(db->cidx, db->nbc, db->cval, feature_lo, feature_hi, buf,
+                                     capacity, cnt, nullptr);
+        else
+            e = launch_dump(db->table, db->nb, feature_lo, feature_hi, buf, capacity, cnt,
+                            nullptr);
+    }
     if (e == hipSuccess) e = hipMemcpy(&n, cnt, 8, hipMemcpyDeviceToHost);
     if (e == hipSuccess && n <= capacity && n) {
         host.resize(n);

@@ -144,6 +144,9 @@ struct QueryArgs {
     uint32_t* counters;
     unsigned long long* qstats;   // kNumQueryStats running totals
     unsigned char* huge;          // kHugeBytes of HBM-list scratch (per-target bests zero)
+    // condensed layout (when cval is set): `table` holds nb index buckets of
+    // kCondEntries 16-byte entries, and cval the runs of locations
+    const uint32_t* cval;
 };
 
 enum QueryStat { kQsFeatures = 0, kQsLocations = 1, kQsProbes = 2, kNumQueryStats = 4 };
@@ -152,6 +155,32 @@ constexpr uint32_t kListSmall = 512;     // candidate locations per record, fast
 constexpr uint32_t kListLarge = 16384;   // large-list pass (one wave per workgroup)
 static_assert(kListLarge < 0x10000, "top-m keys pack a distinct-location index in 16 bits");
 constexpr uint32_t kMaxTopM = 8;
+
+// Condensed layout (Sec. 4.2, Sec. 5.1): per feature one 16-byte index entry
+// {feature, count, a, b} in buckets of kCondEntries entries (one 128-byte
+// line), count 0 = empty; a feature with at most two locations holds them in
+// a and b, one with more holds the 64-bit offset a | b << 32 of its run of
+// locations (ascending) in the value array. The home bucket of a feature is
+// home_bucket(feature, index buckets); entries of a bucket fill in order, a
+// feature lies between its home bucket and the first bucket that is not full.
+constexpr uint32_t kCondEntries = 8;
+constexpr uint32_t kCondInline = 2;
+constexpr uint32_t kCondSliceShift = 8;   // bucket-table buckets per conversion slice
+constexpr uint32_t kCondCap = 8192;       // entries homed in one slice (held in LDS)
+
+struct CondArgs {
+    const unsigned long long* table;   // bucket table
+    uint64_t nb;
+    uint32_t n_slices;
+    uint64_t nbc;                      // index buckets
+    uint32_t* slice_feats;             // count pass: distinct features per slice
+    unsigned long long* slice_vals;    // count pass: run values per slice; then their
+                                       // exclusive prefix (n_slices + 1)
+    unsigned int* idx;                 // nbc * kCondEntries * 4 u32
+    uint32_t* fill;                    // entries claimed per index bucket
+    uint32_t* val;                     // run values
+    uint32_t* err;                     // [0]: a slice over kCondCap entries, [1]: no free entry
+};
 
 // Launchers (return hipError_t of the launch).
 // Build pipeline: sketch (pairs + partition histogram, or the sketch export),
@@ -195,6 +224,15 @@ bool classify_config_valid(const ClassifyConfig& c);
 hipError_t launch_classify_fast(const QueryArgs& a, const ClassifyConfig& c, hipStream_t st);
 hipError_t launch_classify_large(const QueryArgs& a, hipStream_t st);
 hipError_t launch_classify_huge(const QueryArgs& a, hipStream_t st);
+// Condensed layout build: the count pass (per slice), the prefix of the run
+// values, and the write pass (runs and index entries).
+hipError_t launch_condense_count(const CondArgs& c, hipStream_t st);
+hipError_t launch_condense_scan(const CondArgs& c, unsigned long long* total_feats,
+                                hipStream_t st);
+hipError_t launch_condense_write(const CondArgs& c, hipStream_t st);
+hipError_t launch_condense_dump(const unsigned int* idx, uint64_t nbc, const uint32_t* val,
+                                uint32_t lo, uint32_t hi, unsigned long long* out, uint64_t cap,
+                                unsigned long long* count, hipStream_t st);
 
 // Device of a database handle (for threads that must select it).
 int db_device(const struct ::mc_db* db);

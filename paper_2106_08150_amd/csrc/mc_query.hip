@@ -153,6 +153,127 @@ __device__ bool lookup(const QueryArgs& a, const uint32_t* F, uint32_t nf, uint2
     return true;
 }
 
+// Condensed layout: a work item is a (feature, index bucket) pair; 8-lane
+// group g reads item 8q + g's index line, one 16-byte entry a lane. A feature
+// has exactly one entry: found, its locations are appended (inline ones at
+// once; a run is noted in `runs` and copied after the batch, all runs of the
+// batch by the whole wave with one flat index, so that their loads are in
+// flight together); not found in a full bucket, the feature's next bucket is
+// queued. runs: 96 words of LDS owned by the wave. Returns false once the
+// list outgrew LCAP.
+template <uint32_t LCAP>
+__device__ bool lookup_cond(const QueryArgs& a, const uint32_t* F, uint32_t nf, uint2* ring,
+                            uint32_t* list, uint32_t* runs, uint32_t& nlist, uint32_t& probes) {
+    constexpr int NB = 4;
+    constexpr uint32_t G = 8;
+    const uint32_t lane = (uint32_t)lane_id();
+    const uint32_t g = lane >> 3;
+    const uint32_t nb = (uint32_t)a.nb;
+    for (uint32_t i = lane; i < nf; i += kWave) {
+        const uint2 it = make_uint2(F[i], (uint32_t)home_bucket(F[i], a.nb));
+        ring[i] = it;
+        if (i < kRingMirror) ring[i + kRing] = it;
+    }
+    wave_lds_sync();
+    const uint4* ent = reinterpret_cast<const uint4*>(a.table) + (lane & 7u);
+    uint32_t head = 0, tail = nf;
+    while (head < tail) {
+        __builtin_amdgcn_s_waitcnt(kWaitVmem0);
+        const uint32_t c = min(tail - head, G * NB);
+        uint32_t f[NB], b[NB];
+        uint4 e[NB];
+        const uint2* batch = ring + ((head & (kRing - 1u)) + g);
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const uint2 it = batch[G * q];
+            f[q] = it.x;
+            b[q] = it.y;
+        }
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+            if (G * q < c) e[q] = ent[(uint64_t)b[q] * kCondEntries];
+        head += c;
+        uint32_t nrun = 0;   // runs of this batch (at most one a group and q: 32)
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            if (G * q >= c) break;
+            const uint32_t nv = min(c - G * q, G);
+            probes += nv;
+            const bool valid = g < nv;
+            const bool mine = valid && e[q].x == f[q] && e[q].y != 0u;
+            const bool inl = mine && e[q].y <= kCondInline;
+            const bool run = mine && e[q].y > kCondInline;
+            const uint64_t hitA = ballot(inl), hitB = ballot(inl && e[q].y == 2u);
+            const uint64_t hitR = ballot(run);
+            if (hitA | hitR) {
+                const uint32_t nA = popc64(hitA);
+                if (nlist + nA + popc64(hitB) > LCAP) return false;
+                if (inl) {
+                    list[rank_below(hitA, nlist)] = e[q].z;
+                    if (e[q].y == 2u) list[rank_below(hitB, nlist + nA)] = e[q].w;
+                }
+                nlist += nA + popc64(hitB);
+                if (run) {
+                    const uint32_t r = nrun + rank_below(hitR);
+                    runs[3 * r + 0] = e[q].y;
+                    runs[3 * r + 1] = e[q].z;
+                    runs[3 * r + 2] = e[q].w;
+                }
+                nrun += popc64(hitR);
+            }
+            // a group that did not find its feature in a full line goes on
+            const uint64_t found = ballot(mine);
+            const bool gfound = ((found >> (lane & ~7u)) & 0xFFull) != 0;
+            const bool open = valid && e[q].y != 0u && !gfound;
+            const uint64_t full = ballot(open) & kLastSlots;
+            if (full) {
+                if (open && (lane & 7u) == 7u) {
+                    const uint32_t nxt = b[q] + 1u == nb ? 0u : b[q] + 1u;
+                    const uint32_t pos = (tail + rank_below(full)) & (kRing - 1u);
+                    ring[pos] = make_uint2(f[q], nxt);
+                    if (pos < kRingMirror) ring[pos + kRing] = make_uint2(f[q], nxt);
+                }
+                tail += popc64(full);
+            }
+        }
+        if (nrun) {
+            // lane r holds run r; an inclusive scan of the counts gives every
+            // run's first list position
+            wave_lds_sync();
+            uint32_t cnt = 0, off_lo = 0, off_hi = 0;
+            if (lane < nrun) {
+                cnt = runs[3 * lane + 0];
+                off_lo = runs[3 * lane + 1];
+                off_hi = runs[3 * lane + 2];
+            }
+            uint32_t incl = cnt;
+#pragma unroll
+            for (int d = 1; d < 32; d <<= 1) {
+                const uint32_t y = shfl_idx(incl, lane >= (uint32_t)d ? (int)lane - d : (int)lane);
+                if (lane >= (uint32_t)d) incl += y;
+            }
+            const uint32_t total = uniform(shfl_idx(incl, (int)nrun - 1));
+            if (nlist + total > LCAP) return false;
+            wave_lds_sync();
+            // runs[3r] = first position of run r (past the runs: above every
+            // position), runs[3r + 1..2] = its offset in the value array
+            if (lane < 32u) runs[3 * lane] = lane < nrun ? incl - cnt : 0xFFFFFFFFu;
+            wave_lds_sync();
+            for (uint32_t i = lane; i < total; i += kWave) {
+                uint32_t r = 0;   // the last run whose first position is <= i
+#pragma unroll
+                for (uint32_t step = 16; step > 0; step >>= 1)
+                    if (runs[3 * (r + step)] <= i) r += step;
+                const uint64_t off = ((uint64_t)runs[3 * r + 2] << 32) | runs[3 * r + 1];
+                list[nlist + i] = a.cval[off + (i - runs[3 * r])];
+            }
+            nlist += total;
+        }
+        wave_lds_sync();
+    }
+    return true;
+}
+
 template <int K>
 __device__ __forceinline__ void sort_regs(uint32_t* list, uint32_t n) {
     const int lane = lane_id();
@@ -283,7 +404,7 @@ struct WaveStats {
     uint32_t features = 0, locations = 0, probes = 0;
 };
 
-template <uint32_t LCAP, int KPL>
+template <uint32_t LCAP, int KPL, bool C>
 __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>& L, bool big,
                                 const Threshold& th, WaveStats& ws) {
     const int lane = lane_id();
@@ -332,7 +453,12 @@ __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>
         // buffer could overflow (one call site keeps the loop compact)
         if (nf && (p + 2 >= nwt || nf + 2 * a.s > kMaxFeat)) {
             ws.features += nf;
-            fits = lookup<LCAP>(a, L.sk.feats, nf, L.ring, L.list, nlist, ws.probes);
+            if constexpr (C)   // the stage and scratch areas hold the runs meanwhile
+                fits = lookup_cond<LCAP>(a, L.sk.feats, nf, L.ring, L.list,
+                                         reinterpret_cast<uint32_t*>(L.sk.stage), nlist,
+                                         ws.probes);
+            else
+                fits = lookup<LCAP>(a, L.sk.feats, nf, L.ring, L.list, nlist, ws.probes);
             nf = 0;
         }
     }
@@ -450,7 +576,7 @@ __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>
 // about 5.7 KB of LDS a wave, which holds a CU to 28 waves: seven a SIMD (at
 // most 72 VGPRs). A 256-entry list takes about 3.7 KB, so eight waves a SIMD
 // fit (64 VGPRs).
-template <uint32_t LCAP, int WPB, int KPL>
+template <uint32_t LCAP, int WPB, int KPL, bool C>
 __global__ __launch_bounds__(WPB * 64)
 __attribute__((amdgpu_waves_per_eu(LCAP <= 256 ? 8 : 7)))
 void k_classify(QueryArgs a, int big) {
@@ -464,7 +590,7 @@ void k_classify(QueryArgs a, int big) {
     const Threshold th(a.S, a.s);
     for (uint32_t it = blockIdx.x * WPB + wave; it < n_iter; it += gridDim.x * WPB) {
         const uint32_t rec = big ? uniform(a.queue[it]) : it;
-        classify_record<LCAP, KPL>(a, rec, L[wave], big != 0, th, ws);
+        classify_record<LCAP, KPL, C>(a, rec, L[wave], big != 0, th, ws);
     }
     // work of records that go on to the large-list pass counts in both passes
     if (lane_id() == 0 && a.qstats) {
@@ -552,7 +678,7 @@ __device__ __forceinline__ unsigned long long block_max_u64(unsigned long long v
     return m;
 }
 
-template <int KPL>
+template <int KPL, bool C>
 __device__ void classify_huge_record(const QueryArgs& a, uint32_t rec, const HugeRegion& h,
                                      HugeLds& L, const Threshold& th) {
     const uint32_t tid = threadIdx.x, lane = (uint32_t)lane_id(), wave = tid >> 6;
@@ -610,6 +736,35 @@ __device__ void classify_huge_record(const QueryArgs& a, uint32_t rec, const Hug
     const u64x2* slot2 = reinterpret_cast<const u64x2*>(a.table) + (lane & 7u);
     const uint32_t nb = (uint32_t)a.nb;
     uint32_t probes = 0;
+    if constexpr (C) {   // condensed layout: one entry a feature
+        const uint4* ent = reinterpret_cast<const uint4*>(a.table) + (lane & 7u);
+        for (uint32_t fi = tid >> 3; fi < nf && !L.overflow; fi += kHugeThreads / 8) {
+            const uint32_t f = h.feats[fi];
+            uint32_t b = (uint32_t)home_bucket(f, a.nb);
+            for (;;) {
+                const uint4 e = ent[(uint64_t)b * kCondEntries];
+                probes += (lane & 7u) == 0 ? 1u : 0u;
+                const bool mine = e.x == f && e.y != 0u;
+                if (mine) {
+                    const uint32_t pos = atomicAdd(&L.nloc, e.y);
+                    if (pos + e.y > kHugeLocs) {
+                        L.overflow = 1;
+                    } else if (e.y <= kCondInline) {
+                        h.locs[pos] = e.z;
+                        if (e.y == 2u) h.locs[pos + 1] = e.w;
+                    } else {
+                        const uint64_t off = ((uint64_t)e.w << 32) | e.z;
+                        for (uint32_t k = 0; k < e.y; ++k) h.locs[pos + k] = a.cval[off + k];
+                    }
+                }
+                const uint64_t found = ballot(mine);
+                const uint32_t last = (lane & ~7u) | 7u;
+                const bool full = shfl_idx(e.y != 0u ? 1u : 0u, (int)last) != 0u;
+                if (((found >> (lane & ~7u)) & 0xFFull) != 0 || !full) break;
+                b = b + 1u == nb ? 0u : b + 1u;
+            }
+        }
+    } else
     for (uint32_t fi = tid >> 3; fi < nf && !L.overflow; fi += kHugeThreads / 8) {
         const uint32_t f = h.feats[fi];
         uint32_t b = (uint32_t)home_bucket(f, a.nb);
@@ -740,45 +895,60 @@ __device__ void classify_huge_record(const QueryArgs& a, uint32_t rec, const Hug
 
 // Workgroup r uses region r of the huge scratch and takes records r,
 // r + kHugeGroups, ... of the HBM-list queue (its ids start at n_records).
-template <int KPL>
+template <int KPL, bool C>
 __global__ __launch_bounds__(kHugeThreads) void k_classify_huge(QueryArgs a) {
     __shared__ HugeLds L;
     const uint32_t n_iter = uniform(a.counters[kQHuge]);
     const HugeRegion h = huge_region(a.huge, blockIdx.x);
     const Threshold th(a.S, a.s);
     for (uint32_t it = blockIdx.x; it < n_iter; it += gridDim.x)
-        classify_huge_record<KPL>(a, uniform(a.queue[a.n_records + it]), h, L, th);
+        classify_huge_record<KPL, C>(a, uniform(a.queue[a.n_records + it]), h, L, th);
 }
 
-template <uint32_t LCAP, int WPB, int KPL>
+template <uint32_t LCAP, int WPB, int KPL, bool C>
 hipError_t launch_fast_t(const QueryArgs& a, uint32_t max_blocks, hipStream_t st) {
     uint64_t blocks = ((uint64_t)a.n_records + WPB - 1) / WPB;
     if (blocks > max_blocks) blocks = max_blocks;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL((k_classify<LCAP, WPB, KPL>), dim3((unsigned)blocks), dim3(WPB * 64), 0,
+    hipLaunchKernelGGL((k_classify<LCAP, WPB, KPL, C>), dim3((unsigned)blocks), dim3(WPB * 64), 0,
                        st, a, 0);
     return hipGetLastError();
 }
 
 // Tuned variants exist for windows of at most 128 k-mers (two per lane); other
 // window sizes use the default list capacity and workgroup shape.
-template <int KPL>
+template <int KPL, bool C>
 hipError_t launch_fast_k(const QueryArgs& a, const ClassifyConfig& c, hipStream_t st) {
     if constexpr (KPL == 2) {
         const uint32_t key = c.list_cap * 16 + c.waves_per_block;
         switch (key) {
-            case 256 * 16 + 2: return launch_fast_t<256, 2, KPL>(a, c.max_blocks, st);
-            case 256 * 16 + 4: return launch_fast_t<256, 4, KPL>(a, c.max_blocks, st);
-            case 256 * 16 + 8: return launch_fast_t<256, 8, KPL>(a, c.max_blocks, st);
-            case 512 * 16 + 2: return launch_fast_t<512, 2, KPL>(a, c.max_blocks, st);
-            case 512 * 16 + 8: return launch_fast_t<512, 8, KPL>(a, c.max_blocks, st);
-            case 1024 * 16 + 2: return launch_fast_t<1024, 2, KPL>(a, c.max_blocks, st);
-            case 1024 * 16 + 4: return launch_fast_t<1024, 4, KPL>(a, c.max_blocks, st);
-            case 1024 * 16 + 8: return launch_fast_t<1024, 8, KPL>(a, c.max_blocks, st);
+            case 256 * 16 + 2: return launch_fast_t<256, 2, KPL, C>(a, c.max_blocks, st);
+            case 256 * 16 + 4: return launch_fast_t<256, 4, KPL, C>(a, c.max_blocks, st);
+            case 256 * 16 + 8: return launch_fast_t<256, 8, KPL, C>(a, c.max_blocks, st);
+            case 512 * 16 + 2: return launch_fast_t<512, 2, KPL, C>(a, c.max_blocks, st);
+            case 512 * 16 + 8: return launch_fast_t<512, 8, KPL, C>(a, c.max_blocks, st);
+            case 1024 * 16 + 2: return launch_fast_t<1024, 2, KPL, C>(a, c.max_blocks, st);
+            case 1024 * 16 + 4: return launch_fast_t<1024, 4, KPL, C>(a, c.max_blocks, st);
+            case 1024 * 16 + 8: return launch_fast_t<1024, 8, KPL, C>(a, c.max_blocks, st);
             default: break;
         }
     }
-    return launch_fast_t<kListSmall, 4, KPL>(a, c.max_blocks, st);
+    return launch_fast_t<kListSmall, 4, KPL, C>(a, c.max_blocks, st);
+}
+
+template <int KPL>
+hipError_t launch_fast_c(const QueryArgs& a, const ClassifyConfig& c, hipStream_t st) {
+    return a.cval ? launch_fast_k<KPL, true>(a, c, st) : launch_fast_k<KPL, false>(a, c, st);
+}
+
+template <bool C>
+void launch_large_c(const QueryArgs& a, hipStream_t st) {
+    if (a.S <= 64)
+        hipLaunchKernelGGL((k_classify<kListLarge, 1, 1, C>), dim3(512), dim3(64), 0, st, a, 1);
+    else if (a.S <= 128)
+        hipLaunchKernelGGL((k_classify<kListLarge, 1, 2, C>), dim3(512), dim3(64), 0, st, a, 1);
+    else
+        hipLaunchKernelGGL((k_classify<kListLarge, 1, 4, C>), dim3(512), dim3(64), 0, st, a, 1);
 }
 
 }  // namespace
@@ -791,28 +961,30 @@ bool classify_config_valid(const ClassifyConfig& c) {
 
 hipError_t launch_classify_fast(const QueryArgs& a, const ClassifyConfig& c, hipStream_t st) {
     if (a.n_records == 0) return hipSuccess;
-    if (a.S <= 64) return launch_fast_k<1>(a, c, st);
-    if (a.S <= 128) return launch_fast_k<2>(a, c, st);
-    return launch_fast_k<4>(a, c, st);
+    if (a.S <= 64) return launch_fast_c<1>(a, c, st);
+    if (a.S <= 128) return launch_fast_c<2>(a, c, st);
+    return launch_fast_c<4>(a, c, st);
 }
 
 hipError_t launch_classify_huge(const QueryArgs& a, hipStream_t st) {
     if (a.n_records == 0) return hipSuccess;
     const dim3 grid(kHugeGroups), blk(kHugeThreads);
-    if (a.S <= 64) hipLaunchKernelGGL(k_classify_huge<1>, grid, blk, 0, st, a);
-    else if (a.S <= 128) hipLaunchKernelGGL(k_classify_huge<2>, grid, blk, 0, st, a);
-    else hipLaunchKernelGGL(k_classify_huge<4>, grid, blk, 0, st, a);
+    if (a.cval) {
+        if (a.S <= 64) hipLaunchKernelGGL((k_classify_huge<1, true>), grid, blk, 0, st, a);
+        else if (a.S <= 128) hipLaunchKernelGGL((k_classify_huge<2, true>), grid, blk, 0, st, a);
+        else hipLaunchKernelGGL((k_classify_huge<4, true>), grid, blk, 0, st, a);
+    } else {
+        if (a.S <= 64) hipLaunchKernelGGL((k_classify_huge<1, false>), grid, blk, 0, st, a);
+        else if (a.S <= 128) hipLaunchKernelGGL((k_classify_huge<2, false>), grid, blk, 0, st, a);
+        else hipLaunchKernelGGL((k_classify_huge<4, false>), grid, blk, 0, st, a);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_classify_large(const QueryArgs& a, hipStream_t st) {
     if (a.n_records == 0) return hipSuccess;
-    if (a.S <= 64)
-        hipLaunchKernelGGL((k_classify<kListLarge, 1, 1>), dim3(512), dim3(64), 0, st, a, 1);
-    else if (a.S <= 128)
-        hipLaunchKernelGGL((k_classify<kListLarge, 1, 2>), dim3(512), dim3(64), 0, st, a, 1);
-    else
-        hipLaunchKernelGGL((k_classify<kListLarge, 1, 4>), dim3(512), dim3(64), 0, st, a, 1);
+    if (a.cval) launch_large_c<true>(a, st);
+    else launch_large_c<false>(a, st);
     return hipGetLastError();
 }
 

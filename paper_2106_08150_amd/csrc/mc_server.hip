@@ -53,9 +53,13 @@ struct Done {
 
 // One in-flight slot: a worker thread with its own stream, device buffers and
 // pinned staging. The dispatcher hands it one batch at a time.
+// Chunks of one batch (see mc_server::process).
+constexpr uint64_t kChunkRecords = 131072;
+constexpr uint32_t kMaxChunks = 16;
+
 struct Slot {
     hipStream_t stream = nullptr;
-    hipEvent_t copied = nullptr; // its batch's reads are on the device
+    hipEvent_t copied[kMaxChunks] = {};   // chunk c of its batch is on the device
     char* d_buf = nullptr;
     uint64_t d_cap = 0;
     uint64_t d_plan = 0;         // device bytes granted by admission (guarded by the
@@ -180,9 +184,16 @@ struct mc_server {
         }
     };
 
+    // A batch is classified in chunks of at least kChunkRecords records (at
+    // most kMaxChunks of them): the copy of chunk c + 1 overlaps the
+    // classification of chunk c, and the labels of chunk c come back while
+    // later chunks are classified. The reads keep their offsets: the
+    // classification's reads pointer is the device buffer shifted by the
+    // batch's first offset, so the caller's offsets are copied unchanged.
     int process(Slot& s, Job& j) {
         CopyTurn turn{*this, j.order};
-        const uint64_t seg = (j.opts.paired ? 2ull : 1ull) * j.n;   // offsets - 1
+        const uint64_t per = j.opts.paired ? 2ull : 1ull;
+        const uint64_t seg = per * j.n;   // offsets - 1
         const uint64_t base = j.offsets[0];
         const uint64_t rb = j.offsets[seg] - base;
         const uint64_t off_offsets = align256(rb);
@@ -197,35 +208,48 @@ struct mc_server {
         }
         int rc = grow(s, total, std::max(plan, total));
         if (rc != MC_OK) return rc;
-        uint64_t* ho = reinterpret_cast<uint64_t*>(s.h_buf + off_offsets);
-        for (uint64_t i = 0; i <= seg; ++i) ho[i] = j.offsets[i] - base;
+        std::memcpy(s.h_buf + off_offsets, j.offsets, (seg + 1) * 8);
         if (!j.pinned) std::memcpy(s.h_buf, j.reads + base, rb);
-        hipError_t e;
+        const char* src = j.pinned ? j.reads + base : s.h_buf;   // pinned: direct DMA
+        const uint64_t chunk = std::max<uint64_t>(kChunkRecords, (j.n + kMaxChunks - 1) / kMaxChunks);
+        const uint32_t n_chunks = (uint32_t)((j.n + chunk - 1) / chunk);
         turn.wait();
-        if (j.pinned) {   // direct DMA from the caller's pinned buffer
-            e = hipMemcpyAsync(s.d_buf, j.reads + base, rb, hipMemcpyHostToDevice, copy_stream);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(s.d_buf + off_offsets, s.h_buf + off_offsets,
-                                   off_labels - off_offsets, hipMemcpyHostToDevice, copy_stream);
-        } else {
-            e = hipMemcpyAsync(s.d_buf, s.h_buf, off_labels, hipMemcpyHostToDevice, copy_stream);
+        hipError_t e = hipMemcpyAsync(s.d_buf + off_offsets, s.h_buf + off_offsets,
+                                      (seg + 1) * 8, hipMemcpyHostToDevice, copy_stream);
+        for (uint32_t c = 0; c < n_chunks && e == hipSuccess; ++c) {
+            const uint64_t r0 = c * chunk, r1 = std::min<uint64_t>(j.n, r0 + chunk);
+            const uint64_t lo = j.offsets[per * r0] - base, hi = j.offsets[per * r1] - base;
+            if (hi > lo)
+                e = hipMemcpyAsync(s.d_buf + lo, src + lo, hi - lo, hipMemcpyHostToDevice,
+                                   copy_stream);
+            if (e == hipSuccess) e = hipEventRecord(s.copied[c], copy_stream);
         }
-        if (e == hipSuccess) e = hipEventRecord(s.copied, copy_stream);
         turn.pass();
-        if (e == hipSuccess) e = hipStreamWaitEvent(s.stream, s.copied, 0);
         if (e != hipSuccess) return MC_ERR_HIP;
-        {
-            std::lock_guard<std::mutex> lk(launch_mu);
-            rc = mc_classify_ex(db, s.d_buf, reinterpret_cast<const uint64_t*>(s.d_buf + off_offsets),
-                                j.n, &j.opts, reinterpret_cast<uint32_t*>(s.d_buf + off_labels),
-                                j.out_top ? reinterpret_cast<mc_tophit*>(s.d_buf + off_top) : nullptr,
-                                s.stream);
+        const char* reads = s.d_buf - base;   // reads + offsets[i] lies in the buffer
+        const uint64_t* d_off = reinterpret_cast<const uint64_t*>(s.d_buf + off_offsets);
+        uint32_t* d_lab = reinterpret_cast<uint32_t*>(s.d_buf + off_labels);
+        mc_tophit* d_top = j.out_top ? reinterpret_cast<mc_tophit*>(s.d_buf + off_top) : nullptr;
+        for (uint32_t c = 0; c < n_chunks; ++c) {
+            const uint64_t r0 = c * chunk, r1 = std::min<uint64_t>(j.n, r0 + chunk);
+            if (hipStreamWaitEvent(s.stream, s.copied[c], 0) != hipSuccess) return MC_ERR_HIP;
+            {
+                std::lock_guard<std::mutex> lk(launch_mu);
+                rc = mc_classify_ex(db, reads, d_off + per * r0, (uint32_t)(r1 - r0), &j.opts,
+                                    d_lab + r0, d_top ? d_top + r0 * j.opts.top_m : nullptr,
+                                    s.stream);
+            }
+            if (rc != MC_OK) return rc;
+            e = hipMemcpyAsync(s.h_buf + off_labels + r0 * 4, d_lab + r0, (r1 - r0) * 4,
+                               hipMemcpyDeviceToHost, s.stream);
+            if (e == hipSuccess && d_top)
+                e = hipMemcpyAsync(s.h_buf + off_top + r0 * j.opts.top_m * sizeof(mc_tophit),
+                                   d_top + r0 * j.opts.top_m,
+                                   (r1 - r0) * j.opts.top_m * sizeof(mc_tophit),
+                                   hipMemcpyDeviceToHost, s.stream);
+            if (e != hipSuccess) return MC_ERR_HIP;
         }
-        if (rc != MC_OK) return rc;
-        if (hipMemcpyAsync(s.h_buf + off_labels, s.d_buf + off_labels, total - off_labels,
-                           hipMemcpyDeviceToHost, s.stream) != hipSuccess ||
-            hipStreamSynchronize(s.stream) != hipSuccess)
-            return MC_ERR_HIP;
+        if (hipStreamSynchronize(s.stream) != hipSuccess) return MC_ERR_HIP;
         std::memcpy(j.out_labels, s.h_buf + off_labels, (size_t)j.n * 4);
         if (j.out_top) std::memcpy(j.out_top, s.h_buf + off_top, top_bytes);
         return MC_OK;
@@ -366,7 +390,8 @@ mc_server* mc_server_create(mc_db* db, const mc_server_opts* opts) {
     const uint64_t initial = std::min(round_grain(s->staging), s->budget / s->n_slots);
     for (auto& sl : s->slots) {
         ok = ok && hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess;
-        ok = ok && hipEventCreateWithFlags(&sl.copied, hipEventDisableTiming) == hipSuccess;
+        for (auto& ev : sl.copied)
+            ok = ok && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
         ok = ok && mc_server::grow(sl, s->staging, initial) == MC_OK;
         sl.d_plan = sl.d_cap;
     }
@@ -508,7 +533,8 @@ int mc_server_destroy(mc_server* srv) {
         (void)hipFree(s.d_buf);
         (void)hipHostFree(s.h_buf);
         if (s.stream) (void)hipStreamDestroy(s.stream);
-        if (s.copied) (void)hipEventDestroy(s.copied);
+        for (auto& ev : s.copied)
+            if (ev) (void)hipEventDestroy(ev);
     }
     if (srv->copy_stream) {
         (void)hipStreamSynchronize(srv->copy_stream);
