@@ -321,15 +321,28 @@ def uneven_leg(args, g, gtext, torch, mc, synth):
     ref = labels.clone()
     m = min(n, 2_000_000)
     sub_o = o[:2 * m + 1].contiguous()
+    # one launch shape for all records, tuned
     cfg, _ = mc.mc_db_autotune(db.h, r, sub_o, m, opts, labels)
+    flat_ms = timed(lambda: mc.mc_classify_ex(db.h, r, o, n, opts, labels))
+    same = bool(torch.equal(labels, ref))
+    # size classes: single-end records (at most 3 windows) and pairs, each
+    # class with its own tuned shape
+    mc.mc_db_set_routing(db.h, [3], [cfg, cfg])
+    mc.mc_db_autotune(db.h, r, sub_o, m, opts, labels)
+    _, class_shapes = mc.mc_db_get_routing(db.h)
+    routed_ms = timed(lambda: mc.mc_classify_ex(db.h, r, o, n, opts, labels))
+    same &= bool(torch.equal(labels, ref))
+    if flat_ms <= routed_ms:   # the graph replays the faster plan
+        mc.mc_db_set_routing(db.h, [], [cfg])
     graph = mc.ClassifyGraph(db.h, r, o, n, opts, labels)
     graph_ms = timed(graph.launch)
-    same = bool(torch.equal(labels, ref))
+    same &= bool(torch.equal(labels, ref))
     graph.close()
     db.close()
     del r, o, labels, ref
-    log(f"uneven: {n} records ({mates} mates), default {default_ms:.2f} ms, tuned "
-        f"{cfg} + graph {graph_ms:.2f} ms, identical {same}")
+    log(f"uneven: {n} records ({mates} mates), default {default_ms:.2f} ms, tuned {cfg} "
+        f"{flat_ms:.2f} ms, size classes {class_shapes} {routed_ms:.2f} ms, graph "
+        f"{graph_ms:.2f} ms, identical {same}")
     return {
         "workload": (f"{n} records in one paired-layout offsets array: 50% single-end "
                      "U{50..250} bp, 50% pairs 2 x 150 bp (fragment N(400, 50)), 1% "
@@ -338,6 +351,10 @@ def uneven_leg(args, g, gtext, torch, mc, synth):
         "default_config_ms": default_ms,
         "tuned_config": {"list_capacity": cfg[0], "waves_per_block": cfg[1],
                          "max_blocks": cfg[2]},
+        "tuned_ms": flat_ms,
+        "size_classes": {"max_windows": [3], "tuned_shapes": [list(x) for x in class_shapes],
+                         "ms": routed_ms},
+        "graph_plan": "size classes" if routed_ms < flat_ms else "one tuned shape",
         "graph_ms": graph_ms,
         "records_per_s": n / (graph_ms * 1e-3),
         "mates_per_s": mates / (graph_ms * 1e-3),

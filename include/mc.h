@@ -229,12 +229,34 @@ typedef struct mc_launch_config {
 int mc_db_set_launch_config(mc_db* db, const mc_launch_config* cfg);
 int mc_db_get_launch_config(mc_db* db, mc_launch_config* cfg);
 
+/* Size-class routing of uneven batches (Sec. 5.5: size-specialised launches
+ * of the sort, here of the whole classification). Before the fast path, a
+ * routing pass on the device groups the records by their number of windows
+ * (both mates): class c takes the records with at most max_windows[c] windows
+ * not taken by an earlier class, the last class all others; each class is
+ * classified by its own launch with its own shape. n_classes = 1 (the
+ * default) classifies all records in one launch. mc_db_set_launch_config sets
+ * the shape of every class; mc_db_autotune tunes each class's shape in turn
+ * and keeps them in the handle (one tuned shape per size class). Results never
+ * depend on the routing. max_windows must ascend; shapes as for
+ * mc_db_set_launch_config. */
+#define MC_MAX_CLASSES 4
+typedef struct mc_route_config {
+    uint32_t n_classes;
+    uint32_t max_windows[MC_MAX_CLASSES];
+    mc_launch_config shape[MC_MAX_CLASSES];
+} mc_route_config;
+int mc_db_set_routing(mc_db* db, const mc_route_config* routing);
+int mc_db_get_routing(mc_db* db, mc_route_config* routing);
+
 /* Autotuner: classifies the given batch (device buffers, as mc_classify_ex)
  * with the current and every supported launch shape (best of three timed
  * runs after a warm-up each), checks that all give identical labels
  * (MC_ERR_STATE otherwise), keeps the fastest in the handle for later calls
  * (the current shape stays unless another is more than 2% faster) and reports
- * it (best and best_ms may be NULL). Synchronous on `stream`. */
+ * it (best and best_ms may be NULL). With size classes (mc_db_set_routing)
+ * each class is tuned in turn, the others keeping their shapes; best reports
+ * class 0's. Synchronous on `stream`. */
 int mc_db_autotune(mc_db* db, const char* reads, const uint64_t* offsets, uint32_t n_records,
                    const mc_query_opts* opts, uint32_t* out_labels, void* stream,
                    mc_launch_config* best, double* best_ms);

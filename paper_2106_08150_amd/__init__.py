@@ -42,7 +42,7 @@ EXPORTS = [
     "mc_db_set_launch_config", "mc_db_get_launch_config", "mc_db_autotune",
     "mc_classify_graph_create", "mc_classify_graph_launch", "mc_classify_graph_destroy",
     "mc_release_cached_memory", "mc_set_cached_memory_limit", "mc_db_set_insert_path",
-    "mc_db_condense",
+    "mc_db_condense", "mc_db_set_routing", "mc_db_get_routing",
 ]
 
 
@@ -85,6 +85,11 @@ class LaunchConfig(C.Structure):
         return (self.list_capacity, self.waves_per_block, self.max_blocks)
 
 
+class RouteConfig(C.Structure):
+    _fields_ = [("n_classes", C.c_uint32), ("max_windows", C.c_uint32 * 4),
+                ("shape", LaunchConfig * 4)]
+
+
 class ServerOpts(C.Structure):
     _fields_ = [("slots", C.c_uint32), ("memory_budget", C.c_uint64),
                 ("staging_bytes", C.c_uint64)]
@@ -120,6 +125,10 @@ def lib():
         L.mc_set_cached_memory_limit.restype = i32
         L.mc_set_cached_memory_limit.argtypes = [u64]
         L.mc_db_condense.restype, L.mc_db_condense.argtypes = i32, [vp, i32]
+        L.mc_db_set_routing.restype = i32
+        L.mc_db_set_routing.argtypes = [vp, C.POINTER(RouteConfig)]
+        L.mc_db_get_routing.restype = i32
+        L.mc_db_get_routing.argtypes = [vp, C.POINTER(RouteConfig)]
         L.mc_db_set_insert_path.restype = i32
         L.mc_db_set_insert_path.argtypes = [vp, C.POINTER(InsertPath)]
         L.mc_db_reserve.restype, L.mc_db_reserve.argtypes = i32, [vp, u64, C.c_double]
@@ -327,6 +336,26 @@ def mc_db_get_launch_config(db: int) -> tuple:
     c = LaunchConfig()
     _check(lib().mc_db_get_launch_config(db, C.byref(c)))
     return c.as_tuple()
+
+
+def mc_db_set_routing(db: int, max_windows, shapes) -> None:
+    """Size classes: max_windows of every class but the last (ascending) and one
+    (list capacity, waves per workgroup, largest grid) shape per class."""
+    shapes = list(shapes)
+    r = RouteConfig()
+    r.n_classes = len(shapes)
+    for i, m in enumerate(max_windows):
+        r.max_windows[i] = m
+    for i, sh in enumerate(shapes):
+        r.shape[i] = LaunchConfig(*sh)
+    _check(lib().mc_db_set_routing(db, C.byref(r)))
+
+
+def mc_db_get_routing(db: int) -> tuple:
+    r = RouteConfig()
+    _check(lib().mc_db_get_routing(db, C.byref(r)))
+    n = r.n_classes
+    return ([r.max_windows[i] for i in range(n - 1)], [r.shape[i].as_tuple() for i in range(n)])
 
 
 def mc_db_autotune(db: int, reads, offsets, n_records: int, opts: QueryOpts, out_labels,

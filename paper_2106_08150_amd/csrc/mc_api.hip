@@ -56,12 +56,22 @@ constexpr uint64_t kPartBytes = 256ull << 20;           // target table bytes pe
 constexpr uint64_t kMinBuckets = 64;
 constexpr uint64_t kCandCapMax = 1ull << 24;
 
+// Launch plan of the fast path: size classes and one shape per class (one
+// class: every record in one launch with shape[0]).
+struct LaunchPlan {
+    RouteConfig route;
+    ClassifyConfig shape[kMaxRoutes];
+};
+
 struct Workspace {
-    uint32_t* queue = nullptr;               // 2 * queue_cap record ids
+    uint32_t* queue = nullptr;               // 3 * queue_cap record ids: large-list pass,
+                                             // HBM-list pass, size classes
+    uint32_t* route_meta = nullptr;          // kRouteMetaWords
     uint64_t queue_cap = 0;                  // records
     uint32_t* counters = nullptr;            // kNumQueryCounters
     unsigned long long* qstats = nullptr;    // kNumQueryStats
     unsigned char* huge = nullptr;           // kHugeBytes (HBM-list pass)
+    uint32_t huge_groups = 0;                // regions in huge (0 = kHugeGroups)
 };
 
 
@@ -137,8 +147,9 @@ struct mc_db {
     uint64_t cval_n = 0;
     uint64_t c_features = 0, c_pairs = 0;
     bool table_released = false;       // only the condensed layout is left
-    // fast-path launch shape (set by mc_db_set_launch_config / mc_db_autotune)
-    ClassifyConfig cfg;
+    // fast-path launch plan (mc_db_set_launch_config / mc_db_set_routing /
+    // mc_db_autotune)
+    LaunchPlan plan;
     // bumped whenever device arrays a captured graph refers to may have moved
     uint64_t version = 1;
     // profiling: one timer per profiled kernel kind (MC_K_*)
@@ -714,6 +725,7 @@ int init_workspace(Workspace& w, hipStream_t st) {
     if (int rc = dev_alloc(&w.counters, kNumQueryCounters)) return rc;
     if (int rc = dev_alloc(&w.qstats, kNumQueryStats)) return rc;
     if (int rc = dev_alloc(&w.huge, kHugeBytes)) return rc;
+    if (int rc = dev_alloc(&w.route_meta, kRouteMetaWords)) return rc;
     HIP_TRY(launch_fill_u32(w.counters, kNumQueryCounters, 0u, st));
     HIP_TRY(launch_fill_u64(w.qstats, kNumQueryStats, 0ull, st));
     for (uint32_t r = 0; r < kHugeGroups; ++r)
@@ -731,7 +743,7 @@ Workspace* workspace(mc_db* db, hipStream_t st, uint64_t n_records, int* rc) {
     if (n_records > w.queue_cap) {
         uint32_t* q = nullptr;
         const uint64_t c = std::max<uint64_t>(std::max<uint64_t>(n_records, 1024), 2 * w.queue_cap);
-        if ((*rc = dev_alloc(&q, 2 * c))) return nullptr;
+        if ((*rc = dev_alloc(&q, 3 * c))) return nullptr;
         if (w.queue) db->retired.push_back(w.queue);
         w.queue = q;
         w.queue_cap = c;
@@ -766,7 +778,7 @@ int check_classify(mc_db* db, const char* reads, const uint64_t* offsets, uint32
 // synchronisation: usable under stream capture).
 int classify_launch(mc_db* db, const char* reads, const uint64_t* offsets, uint32_t n_records,
                     const mc_query_opts& opts, uint32_t* out_labels, mc_tophit* out_top,
-                    Workspace& w, const ClassifyConfig& cfg, hipStream_t st, bool profile) {
+                    Workspace& w, const LaunchPlan& plan, hipStream_t st, bool profile) {
     static_assert(kQOverflow == 0 && kQHuge == 1, "the per-launch queue counters lead");
     HIP_TRY(launch_fill_u32(w.counters, 2, 0u, st));
     QueryArgs a{};
@@ -796,11 +808,21 @@ int classify_launch(mc_db* db, const char* reads, const uint64_t* offsets, uint3
     a.counters = w.counters;
     a.qstats = w.qstats;
     a.huge = w.huge;
+    a.huge_groups = w.huge_groups;
+    a.route_queue = w.queue + 2 * w.queue_cap;
+    a.route_meta = w.route_meta;
+    auto fast = [&]() -> hipError_t {
+        if (plan.route.n <= 1) return launch_classify_fast(a, plan.shape[0], st);
+        hipError_t e = launch_fill_u32(w.route_meta, kRouteMetaWords, 0u, st);
+        if (e == hipSuccess) e = launch_route(a, plan.route, st);
+        for (uint32_t c = 0; c < plan.route.n && e == hipSuccess; ++c)
+            e = launch_classify_class(a, plan.shape[c], c, st);
+        return e;
+    };
     if (profile) {
-        HIP_TRY(timed_launch(db, db->timers[MC_K_CLASSIFY], st,
-                             [&] { return launch_classify_fast(a, cfg, st); }));
+        HIP_TRY(timed_launch(db, db->timers[MC_K_CLASSIFY], st, fast));
     } else {
-        HIP_TRY(launch_classify_fast(a, cfg, st));
+        HIP_TRY(fast());
     }
     HIP_TRY(launch_classify_large(a, st));
     HIP_TRY(launch_classify_huge(a, st));
@@ -810,7 +832,7 @@ int classify_launch(mc_db* db, const char* reads, const uint64_t* offsets, uint3
 int alloc_workspace(Workspace& w, uint64_t n_records, hipStream_t st) {
     if (int rc = init_workspace(w, st)) return rc;
     w.queue_cap = std::max<uint64_t>(n_records, 1);
-    return dev_alloc(&w.queue, 2 * w.queue_cap);
+    return dev_alloc(&w.queue, 3 * w.queue_cap);
 }
 
 void free_workspace(Workspace& w) {
@@ -818,6 +840,7 @@ void free_workspace(Workspace& w) {
     (void)dev_free(w.counters);
     (void)dev_free(w.qstats);
     (void)dev_free(w.huge);
+    (void)dev_free(w.route_meta);
     w = Workspace();
 }
 
@@ -863,7 +886,7 @@ int capture_graph(mc_graph* g, hipStream_t st) {
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         rc = classify_launch(db, g->reads, g->offsets, g->n, g->opts, g->out_labels, g->out_top,
-                             g->ws, db->cfg, cs, false);
+                             g->ws, db->plan, cs, false);
         hipGraph_t graph = nullptr;
         hipError_t e2 = hipStreamEndCapture(cs, &graph);
         if (e2 != hipSuccess && rc == MC_OK) rc = fail(MC_ERR_HIP, "graph capture failed");
@@ -885,6 +908,31 @@ int capture_graph(mc_graph* g, hipStream_t st) {
 
 namespace mc {
 int db_device(const struct ::mc_db* db) { return db->device; }
+
+int classify_into(struct ::mc_db* db, const char* reads, const uint64_t* offsets,
+                  uint32_t n_records, const mc_query_opts* opts, uint32_t* out_labels,
+                  mc_tophit* out_top, const ScratchView& scratch, hipStream_t st) {
+    if (int rc = check_classify(db, reads, offsets, n_records, opts, out_labels)) return rc;
+    if (n_records == 0) return MC_OK;
+    if (n_records > scratch.queue_cap)
+        return fail(MC_ERR_INVALID_ARG, "%u records exceed the scratch's %llu", n_records,
+                    (unsigned long long)scratch.queue_cap);
+    DeviceGuard dg(db->device);
+    Workspace w;
+    w.counters = scratch.counters;
+    w.route_meta = scratch.route_meta;
+    w.queue = scratch.queue;
+    w.queue_cap = scratch.queue_cap;
+    w.huge = scratch.huge;
+    w.huge_groups = scratch.huge_groups;
+    // what the passes expect at zero: the counters and the per-target bests
+    HIP_TRY(launch_fill_u32(w.counters, kNumQueryCounters, 0u, st));
+    for (uint32_t r = 0; r < scratch.huge_groups; ++r)
+        HIP_TRY(launch_fill_u64(reinterpret_cast<unsigned long long*>(w.huge + r * kHugeRegionBytes),
+                                kHugeTargets, 0ull, st));
+    return classify_launch(db, reads, offsets, n_records, *opts, out_labels, out_top, w, db->plan,
+                           st, false);
+}
 int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
 }  // namespace mc
 
@@ -1093,7 +1141,7 @@ int mc_classify_ex(mc_db* db, const char* reads, const uint64_t* offsets, uint32
     Workspace* w = workspace(db, st, n_records, &rc);
     if (!w) return rc;
     return classify_launch(db, reads, offsets, n_records, *opts, out_labels, out_top, *w,
-                           db->cfg, st, db->profiling);
+                           db->plan, st, db->profiling);
 }
 
 int mc_classify(mc_db* db, const char* reads, const uint64_t* offsets, uint32_t n_reads,
@@ -1374,7 +1422,7 @@ int mc_db_set_launch_config(mc_db* db, const mc_launch_config* cfg) {
     if (!cfg) return fail(MC_ERR_INVALID_ARG, "cfg is NULL");
     ClassifyConfig c{cfg->list_capacity, cfg->waves_per_block, cfg->max_blocks};
     if (!classify_config_valid(c)) return fail(MC_ERR_INVALID_ARG, "unsupported launch config");
-    db->cfg = c;
+    for (auto& x : db->plan.shape) x = c;
     db->version += 1;
     return MC_OK;
 }
@@ -1382,9 +1430,9 @@ int mc_db_set_launch_config(mc_db* db, const mc_launch_config* cfg) {
 int mc_db_get_launch_config(mc_db* db, mc_launch_config* cfg) {
     if (int rc = check_db(db)) return rc;
     if (!cfg) return fail(MC_ERR_INVALID_ARG, "cfg is NULL");
-    cfg->list_capacity = db->cfg.list_cap;
-    cfg->waves_per_block = db->cfg.waves_per_block;
-    cfg->max_blocks = db->cfg.max_blocks;
+    cfg->list_capacity = db->plan.shape[0].list_cap;
+    cfg->waves_per_block = db->plan.shape[0].waves_per_block;
+    cfg->max_blocks = db->plan.shape[0].max_blocks;
     return MC_OK;
 }
 
@@ -1405,45 +1453,94 @@ int mc_db_autotune(mc_db* db, const char* reads, const uint64_t* offsets, uint32
     const uint32_t caps[] = {256, 512, 1024};
     const uint32_t wpbs[] = {2, 4, 8};
     const uint32_t grids[] = {2048, 8192, 16384, 32768, 1u << 30};
-    // the current shape first: it is kept unless another is faster by more than
-    // 2% (timings are the best of three runs after a warm-up run)
-    std::vector<ClassifyConfig> cands{db->cfg};
-    for (uint32_t lc : caps)
-        for (uint32_t wp : wpbs)
-            for (uint32_t gb : grids) cands.push_back(ClassifyConfig{lc, wp, gb});
-    ClassifyConfig win = db->cfg;
+    // each size class in turn (the others keep their shapes); per class the
+    // current shape first: it is kept unless another is faster by more than 2%
+    // (timings are the best of three runs after a warm-up run). The tuned
+    // shapes stay in the handle: a cache of one shape per size class.
+    LaunchPlan plan = db->plan;
     double win_ms = 1e30;
     bool first = true;
-    for (const ClassifyConfig& c : cands) {
-        double ms = 1e30;
-        for (int rep = 0; rep < 4; ++rep) {
-            float t = 0.f;
-            HIP_TRY(hipEventRecord(e0, st));
-            rc = classify_launch(db, reads, offsets, n_records, *opts, out_labels, nullptr, *w, c,
-                                 st, false);
-            if (rc) return rc;
-            HIP_TRY(hipEventRecord(e1, st));
-            HIP_TRY(hipEventSynchronize(e1));
-            HIP_TRY(hipEventElapsedTime(&t, e0, e1));
-            if (rep > 0) ms = std::min(ms, (double)t);
+    for (uint32_t cls = 0; cls < std::max<uint32_t>(1, plan.route.n); ++cls) {
+        std::vector<ClassifyConfig> cands{plan.shape[cls]};
+        for (uint32_t lc : caps)
+            for (uint32_t wp : wpbs)
+                for (uint32_t gb : grids) cands.push_back(ClassifyConfig{lc, wp, gb});
+        ClassifyConfig win = plan.shape[cls];
+        double cls_ms = 1e30;
+        bool cls_first = true;
+        for (const ClassifyConfig& c : cands) {
+            LaunchPlan trial = plan;
+            trial.shape[cls] = c;
+            double ms = 1e30;
+            for (int rep = 0; rep < 4; ++rep) {
+                float t = 0.f;
+                HIP_TRY(hipEventRecord(e0, st));
+                rc = classify_launch(db, reads, offsets, n_records, *opts, out_labels, nullptr,
+                                     *w, trial, st, false);
+                if (rc) return rc;
+                HIP_TRY(hipEventRecord(e1, st));
+                HIP_TRY(hipEventSynchronize(e1));
+                HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+                if (rep > 0) ms = std::min(ms, (double)t);
+            }
+            HIP_TRY(hipMemcpy(first ? ref.data() : cur.data(), out_labels,
+                              (size_t)n_records * 4, hipMemcpyDeviceToHost));
+            if (!first && cur != ref)
+                return fail(MC_ERR_STATE, "launch shapes disagree (class %u: %u, %u, %u)", cls,
+                            c.list_cap, c.waves_per_block, c.max_blocks);
+            first = false;
+            if (cls_first || ms < 0.98 * cls_ms) {
+                cls_ms = ms;
+                win = c;
+            }
+            cls_first = false;
         }
-        HIP_TRY(hipMemcpy(first ? ref.data() : cur.data(), out_labels, (size_t)n_records * 4,
-                          hipMemcpyDeviceToHost));
-        if (!first && cur != ref)
-            return fail(MC_ERR_STATE, "launch shapes disagree (%u, %u, %u)", c.list_cap,
-                        c.waves_per_block, c.max_blocks);
-        if (first || ms < 0.98 * win_ms) {
-            win_ms = ms;
-            win = c;
-        }
-        first = false;
+        plan.shape[cls] = win;
+        win_ms = cls_ms;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    db->cfg = win;
+    db->plan = plan;
     db->version += 1;
-    if (best) *best = mc_launch_config{win.list_cap, win.waves_per_block, win.max_blocks};
+    const ClassifyConfig& w0 = plan.shape[0];
+    if (best) *best = mc_launch_config{w0.list_cap, w0.waves_per_block, w0.max_blocks};
     if (best_ms) *best_ms = win_ms;
+    return MC_OK;
+}
+
+int mc_db_set_routing(mc_db* db, const mc_route_config* r) {
+    if (int rc = check_db(db)) return rc;
+    if (!r) return fail(MC_ERR_INVALID_ARG, "routing is NULL");
+    if (r->n_classes < 1 || r->n_classes > kMaxRoutes)
+        return fail(MC_ERR_INVALID_ARG, "n_classes %u not in 1..%u", r->n_classes, kMaxRoutes);
+    LaunchPlan p;
+    p.route.n = r->n_classes;
+    for (uint32_t c = 0; c < kMaxRoutes; ++c) {
+        const uint32_t lim = c < r->n_classes ? c : r->n_classes - 1;
+        p.shape[c] = ClassifyConfig{r->shape[lim].list_capacity, r->shape[lim].waves_per_block,
+                                    r->shape[lim].max_blocks};
+        if (c < r->n_classes && !classify_config_valid(p.shape[c]))
+            return fail(MC_ERR_INVALID_ARG, "unsupported launch shape of class %u", c);
+        p.route.max_windows[c] = c + 1 < r->n_classes ? r->max_windows[c] : 0;
+        if (c + 1 < r->n_classes && c > 0 && r->max_windows[c] <= r->max_windows[c - 1])
+            return fail(MC_ERR_INVALID_ARG, "max_windows must ascend");
+    }
+    db->plan = p;
+    db->version += 1;
+    return MC_OK;
+}
+
+int mc_db_get_routing(mc_db* db, mc_route_config* r) {
+    if (int rc = check_db(db)) return rc;
+    if (!r) return fail(MC_ERR_INVALID_ARG, "routing is NULL");
+    *r = mc_route_config{};
+    r->n_classes = db->plan.route.n;
+    for (uint32_t c = 0; c < kMaxRoutes; ++c) {
+        r->max_windows[c] = db->plan.route.max_windows[c];
+        r->shape[c] = mc_launch_config{db->plan.shape[c].list_cap,
+                                       db->plan.shape[c].waves_per_block,
+                                       db->plan.shape[c].max_blocks};
+    }
     return MC_OK;
 }
 

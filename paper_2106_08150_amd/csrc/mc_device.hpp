@@ -259,11 +259,35 @@ __device__ __forceinline__ bool kmer_at(const Word* W, uint32_t x, uint32_t k, u
 }
 
 // ------------------------------------------------------- bitonic in regs --
+// Lanes of a compare-exchange step of a bitonic network over elements
+// r * 64 + lane that keep the smaller key: those whose block of `size` runs
+// ascending ((element & size) == 0) and that are the lower partner
+// ((lane & stride) == 0), or neither. A constant of the step.
+__host__ __device__ constexpr uint64_t keep_low_lanes(int size, int stride, int r) {
+    uint64_t m = 0;
+    for (int l = 0; l < 64; ++l) {
+        const bool asc = (((r * 64) + l) & size) == 0;
+        const bool lower = (l & stride) == 0;
+        if (asc == lower) m |= 1ull << l;
+    }
+    return m;
+}
+
+// The lanes of a constant 64-bit mask as a per-lane predicate. The mask is
+// written by two scalar moves of immediates where it is used (volatile, so
+// they are not hoisted): a mask computed once outside the enclosing loops
+// would stay live in scalar registers across them and be spilled.
+__device__ __forceinline__ bool lanes_of(uint64_t mask) {
+    uint32_t lo, hi;
+    asm volatile("s_mov_b32 %0, %1" : "=s"(lo) : "i"((uint32_t)mask));
+    asm volatile("s_mov_b32 %0, %1" : "=s"(hi) : "i"((uint32_t)(mask >> 32)));
+    return __builtin_amdgcn_inverse_ballot_w64(((uint64_t)hi << 32) | lo);
+}
+
 // Ascending sort of 64*KPL keys held KPL per lane; element index r*64 + lane.
 template <int KPL>
 __device__ __forceinline__ void wave_sort(uint32_t (&v)[KPL]) {
     constexpr int N = kWave * KPL;
-    const int lane = lane_id();
 #pragma unroll
     for (int size = 2; size <= N; size <<= 1) {
 #pragma unroll
@@ -284,12 +308,9 @@ __device__ __forceinline__ void wave_sort(uint32_t (&v)[KPL]) {
             } else {
 #pragma unroll
                 for (int r = 0; r < KPL; ++r) {
-                    const int e = r * kWave + lane;
                     uint32_t o = xor_lanes_c(v[r], stride);
-                    const bool asc = (e & size) == 0;
-                    const bool lower = (lane & stride) == 0;
                     uint32_t lo = v[r] < o ? v[r] : o, hi = v[r] < o ? o : v[r];
-                    v[r] = (asc == lower) ? lo : hi;
+                    v[r] = lanes_of(keep_low_lanes(size, stride, r)) ? lo : hi;
                 }
             }
         }
@@ -453,17 +474,15 @@ __device__ __forceinline__ uint32_t sketch_window_rare(const Word* W, uint32_t x
 }
 
 // Ascending bitonic sort of each 32-lane half of the wave (one key per lane).
+// (For size <= 32 the step masks of keep_low_lanes are those of each half.)
 __device__ __forceinline__ void wave_sort_halves(uint32_t& v) {
-    const int lane = lane_id();
 #pragma unroll
     for (int size = 2; size <= 32; size <<= 1) {
 #pragma unroll
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
             uint32_t o = xor_lanes_c(v, stride);
-            const bool asc = ((lane & 31) & size) == 0;
-            const bool lower = (lane & stride) == 0;
             uint32_t lo = v < o ? v : o, hi = v < o ? o : v;
-            v = (asc == lower) ? lo : hi;
+            v = lanes_of(keep_low_lanes(size, stride, 0)) ? lo : hi;
         }
     }
 }

@@ -143,10 +143,27 @@ struct QueryArgs {
     uint32_t* queue;              // record ids: [0, n) large-list pass, [n, 2n) HBM-list pass
     uint32_t* counters;
     unsigned long long* qstats;   // kNumQueryStats running totals
-    unsigned char* huge;          // kHugeBytes of HBM-list scratch (per-target bests zero)
+    unsigned char* huge;          // HBM-list scratch: huge_groups regions of kHugeRegionBytes
+                                  // (per-target bests zero)
+    uint32_t huge_groups;         // regions (workgroups of the HBM-list pass), 0 = kHugeGroups
     // condensed layout (when cval is set): `table` holds nb index buckets of
     // kCondEntries 16-byte entries, and cval the runs of locations
     const uint32_t* cval;
+    // size classes (routed launches): record ids grouped by class, and per
+    // class c its count at route_meta[c] and first id at route_meta[kMaxRoutes + c]
+    uint32_t* route_queue;
+    uint32_t* route_meta;         // kRouteMetaWords
+};
+
+// Routing of records into size classes by their number of windows: class c
+// takes the records with at most max_windows[c] windows not taken by an
+// earlier class (the last class takes the rest); each class has its own
+// launch shape.
+constexpr uint32_t kMaxRoutes = 4;
+constexpr uint32_t kRouteMetaWords = 3 * kMaxRoutes;   // counts, first ids, cursors
+struct RouteConfig {
+    uint32_t n = 1;
+    uint32_t max_windows[kMaxRoutes] = {0, 0, 0, 0};
 };
 
 enum QueryStat { kQsFeatures = 0, kQsLocations = 1, kQsProbes = 2, kNumQueryStats = 4 };
@@ -223,6 +240,11 @@ bool classify_config_valid(const ClassifyConfig& c);
 // over the records the fast path queued.
 hipError_t launch_classify_fast(const QueryArgs& a, const ClassifyConfig& c, hipStream_t st);
 hipError_t launch_classify_large(const QueryArgs& a, hipStream_t st);
+// Routing: the records' size classes into route_queue / route_meta, then one
+// fast-path launch per class with that class's shape.
+hipError_t launch_route(const QueryArgs& a, const RouteConfig& r, hipStream_t st);
+hipError_t launch_classify_class(const QueryArgs& a, const ClassifyConfig& c, uint32_t cls,
+                                 hipStream_t st);
 hipError_t launch_classify_huge(const QueryArgs& a, hipStream_t st);
 // Condensed layout build: the count pass (per slice), the prefix of the run
 // values, and the write pass (runs and index entries).
@@ -236,6 +258,26 @@ hipError_t launch_condense_dump(const unsigned int* idx, uint64_t nbc, const uin
 
 // Device of a database handle (for threads that must select it).
 int db_device(const struct ::mc_db* db);
+
+// Device scratch of one classification supplied by the caller: counters
+// (kNumQueryCounters u32), routing data (kRouteMetaWords u32), record queues
+// (3 * queue_cap u32) and huge_groups regions of the HBM-list pass.
+struct ScratchView {
+    uint32_t* counters;
+    uint32_t* route_meta;
+    uint32_t* queue;
+    uint64_t queue_cap;
+    unsigned char* huge;
+    uint32_t huge_groups;
+};
+// A classification (as mc_classify_ex) that takes every device buffer beyond
+// its inputs and outputs from `scratch` and allocates nothing: the scratch is
+// cleared where it must start at zero (fill kernels on `st`), no statistics
+// are kept and the too-long count stays in scratch.counters[kQTooLong].
+// n_records must not exceed scratch.queue_cap.
+int classify_into(struct ::mc_db* db, const char* reads, const uint64_t* offsets,
+                  uint32_t n_records, const struct mc_query_opts* opts, uint32_t* out_labels,
+                  struct mc_tophit* out_top, const ScratchView& scratch, hipStream_t st);
 
 // Set the calling thread's mc_last_error text; returns code.
 int set_error(int code, const char* msg);

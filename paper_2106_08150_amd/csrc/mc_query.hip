@@ -5,6 +5,7 @@
 // `sws` consecutive windows per target, keeps the top m targets and labels the
 // record, by LCA when the top scores are close. Records whose list does not
 // fit the fast path's LDS are queued for a second pass with a larger list.
+#include <algorithm>
 #include <cstddef>
 
 #include "mc_device.hpp"
@@ -579,17 +580,27 @@ __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>
 template <uint32_t LCAP, int WPB, int KPL, bool C>
 __global__ __launch_bounds__(WPB * 64)
 __attribute__((amdgpu_waves_per_eu(LCAP <= 256 ? 8 : 7)))
-void k_classify(QueryArgs a, int big) {
+void k_classify(QueryArgs a, int big, int cls) {
     __shared__ QueryLds<LCAP> L[WPB];
     const int wave = (int)uniform(threadIdx.x >> 6);
     for (uint32_t i = (uint32_t)lane_id(); i < kRing + kRingMirror; i += kWave)
         L[wave].ring[i] = make_uint2(0u, 0u);   // any item must name a bucket of the table
     wave_lds_sync();
-    const uint32_t n_iter = big ? uniform(a.counters[kQOverflow]) : a.n_records;
+    // the records of this launch: all of them, those queued for the large-list
+    // pass (big), or those of size class cls >= 0 (routed); the id arrays are
+    // read where they are used (no registers held across the record loop)
+    const uint32_t n_iter = big ? uniform(a.counters[kQOverflow])
+                                : cls >= 0 ? uniform(a.route_meta[cls]) : a.n_records;
     WaveStats ws;
     const Threshold th(a.S, a.s);
     for (uint32_t it = blockIdx.x * WPB + wave; it < n_iter; it += gridDim.x * WPB) {
-        const uint32_t rec = big ? uniform(a.queue[it]) : it;
+        uint32_t rec = it;
+        if (big) {
+            rec = uniform(MC_COLD(queue)[it]);
+        } else if (cls >= 0) {
+            const uint32_t* const meta = MC_COLD(route_meta);
+            rec = uniform(MC_COLD(route_queue)[meta[kMaxRoutes + cls] + it]);
+        }
         classify_record<LCAP, KPL, C>(a, rec, L[wave], big != 0, th, ws);
     }
     // work of records that go on to the large-list pass counts in both passes
@@ -906,49 +917,122 @@ __global__ __launch_bounds__(kHugeThreads) void k_classify_huge(QueryArgs a) {
 }
 
 template <uint32_t LCAP, int WPB, int KPL, bool C>
-hipError_t launch_fast_t(const QueryArgs& a, uint32_t max_blocks, hipStream_t st) {
+hipError_t launch_fast_t(const QueryArgs& a, uint32_t max_blocks, int cls, hipStream_t st) {
     uint64_t blocks = ((uint64_t)a.n_records + WPB - 1) / WPB;
     if (blocks > max_blocks) blocks = max_blocks;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL((k_classify<LCAP, WPB, KPL, C>), dim3((unsigned)blocks), dim3(WPB * 64), 0,
-                       st, a, 0);
+                       st, a, 0, cls);
     return hipGetLastError();
 }
 
 // Tuned variants exist for windows of at most 128 k-mers (two per lane); other
 // window sizes use the default list capacity and workgroup shape.
 template <int KPL, bool C>
-hipError_t launch_fast_k(const QueryArgs& a, const ClassifyConfig& c, hipStream_t st) {
+hipError_t launch_fast_k(const QueryArgs& a, const ClassifyConfig& c, int cls, hipStream_t st) {
     if constexpr (KPL == 2) {
         const uint32_t key = c.list_cap * 16 + c.waves_per_block;
         switch (key) {
-            case 256 * 16 + 2: return launch_fast_t<256, 2, KPL, C>(a, c.max_blocks, st);
-            case 256 * 16 + 4: return launch_fast_t<256, 4, KPL, C>(a, c.max_blocks, st);
-            case 256 * 16 + 8: return launch_fast_t<256, 8, KPL, C>(a, c.max_blocks, st);
-            case 512 * 16 + 2: return launch_fast_t<512, 2, KPL, C>(a, c.max_blocks, st);
-            case 512 * 16 + 8: return launch_fast_t<512, 8, KPL, C>(a, c.max_blocks, st);
-            case 1024 * 16 + 2: return launch_fast_t<1024, 2, KPL, C>(a, c.max_blocks, st);
-            case 1024 * 16 + 4: return launch_fast_t<1024, 4, KPL, C>(a, c.max_blocks, st);
-            case 1024 * 16 + 8: return launch_fast_t<1024, 8, KPL, C>(a, c.max_blocks, st);
+            case 256 * 16 + 2: return launch_fast_t<256, 2, KPL, C>(a, c.max_blocks, cls, st);
+            case 256 * 16 + 4: return launch_fast_t<256, 4, KPL, C>(a, c.max_blocks, cls, st);
+            case 256 * 16 + 8: return launch_fast_t<256, 8, KPL, C>(a, c.max_blocks, cls, st);
+            case 512 * 16 + 2: return launch_fast_t<512, 2, KPL, C>(a, c.max_blocks, cls, st);
+            case 512 * 16 + 8: return launch_fast_t<512, 8, KPL, C>(a, c.max_blocks, cls, st);
+            case 1024 * 16 + 2: return launch_fast_t<1024, 2, KPL, C>(a, c.max_blocks, cls, st);
+            case 1024 * 16 + 4: return launch_fast_t<1024, 4, KPL, C>(a, c.max_blocks, cls, st);
+            case 1024 * 16 + 8: return launch_fast_t<1024, 8, KPL, C>(a, c.max_blocks, cls, st);
             default: break;
         }
     }
-    return launch_fast_t<kListSmall, 4, KPL, C>(a, c.max_blocks, st);
+    return launch_fast_t<kListSmall, 4, KPL, C>(a, c.max_blocks, cls, st);
 }
 
 template <int KPL>
-hipError_t launch_fast_c(const QueryArgs& a, const ClassifyConfig& c, hipStream_t st) {
-    return a.cval ? launch_fast_k<KPL, true>(a, c, st) : launch_fast_k<KPL, false>(a, c, st);
+hipError_t launch_fast_c(const QueryArgs& a, const ClassifyConfig& c, int cls, hipStream_t st) {
+    return a.cval ? launch_fast_k<KPL, true>(a, c, cls, st)
+                  : launch_fast_k<KPL, false>(a, c, cls, st);
+}
+
+hipError_t launch_fast_any(const QueryArgs& a, const ClassifyConfig& c, int cls, hipStream_t st) {
+    if (a.n_records == 0) return hipSuccess;
+    if (a.S <= 64) return launch_fast_c<1>(a, c, cls, st);
+    if (a.S <= 128) return launch_fast_c<2>(a, c, cls, st);
+    return launch_fast_c<4>(a, c, cls, st);
+}
+
+// Windows of record rec (both mates), as the classification counts them.
+__device__ __forceinline__ uint64_t record_windows(const QueryArgs& a, uint32_t rec) {
+    uint64_t o0, o1, o2;
+    if (a.paired) {
+        o0 = a.offsets[2ull * rec]; o1 = a.offsets[2ull * rec + 1]; o2 = a.offsets[2ull * rec + 2];
+    } else {
+        o0 = a.offsets[rec]; o1 = a.offsets[rec + 1ull]; o2 = o1;
+    }
+    if (o1 < o0 || o2 < o1) return 0;
+    uint64_t nw = 0;
+    const uint64_t len[2] = {o1 - o0, o2 - o1};
+    for (int sg = 0; sg < 2; ++sg)
+        nw += len[sg] < a.k ? 0 : (len[sg] - a.k + 1 + a.S - 1) / a.S;
+    return nw;
+}
+
+__device__ __forceinline__ uint32_t size_class(uint64_t nw, const RouteConfig& r) {
+    for (uint32_t c = 0; c + 1 < r.n; ++c)
+        if (nw <= r.max_windows[c]) return c;
+    return r.n - 1;
+}
+
+// Routing, pass 1: records per size class (wave-aggregated counters).
+__global__ __launch_bounds__(256) void k_route_count(QueryArgs a, RouteConfig r) {
+    uint32_t cnt[kMaxRoutes] = {0, 0, 0, 0};
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n_records;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        cnt[size_class(record_windows(a, (uint32_t)i), r)] += 1;
+    for (uint32_t c = 0; c < r.n; ++c) {
+        uint32_t v = cnt[c];
+#pragma unroll
+        for (int m = 1; m < kWave; m <<= 1) v += shfl_xor(v, m);
+        if (lane_id() == 0 && v) atomicAdd(&a.route_meta[c], v);
+    }
+}
+
+// Routing, pass 2: first ids of the classes (their counts' prefix), cursors.
+__global__ void k_route_scan(QueryArgs a, RouteConfig r) {
+    if (threadIdx.x != 0) return;
+    uint32_t run = 0;
+    for (uint32_t c = 0; c < r.n; ++c) {
+        a.route_meta[kMaxRoutes + c] = run;
+        a.route_meta[2 * kMaxRoutes + c] = run;
+        run += a.route_meta[c];
+    }
+}
+
+// Routing, pass 3: every record's id at its class's cursor.
+__global__ __launch_bounds__(256) void k_route_scatter(QueryArgs a, RouteConfig r) {
+    const uint64_t step = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x; i0 < a.n_records; i0 += step) {
+        const uint64_t i = i0 + threadIdx.x;
+        const bool in = i < a.n_records;
+        const uint32_t c = in ? size_class(record_windows(a, (uint32_t)i), r) : kMaxRoutes;
+        for (uint32_t k = 0; k < r.n; ++k) {
+            const uint64_t m = ballot(c == k);
+            if (!m) continue;
+            uint32_t base = 0;
+            if (lane_id() == 0) base = atomicAdd(&a.route_meta[2 * kMaxRoutes + k], popc64(m));
+            base = shfl_idx(base, 0);
+            if (c == k) a.route_queue[base + rank_below(m)] = (uint32_t)i;
+        }
+    }
 }
 
 template <bool C>
 void launch_large_c(const QueryArgs& a, hipStream_t st) {
     if (a.S <= 64)
-        hipLaunchKernelGGL((k_classify<kListLarge, 1, 1, C>), dim3(512), dim3(64), 0, st, a, 1);
+        hipLaunchKernelGGL((k_classify<kListLarge, 1, 1, C>), dim3(512), dim3(64), 0, st, a, 1, -1);
     else if (a.S <= 128)
-        hipLaunchKernelGGL((k_classify<kListLarge, 1, 2, C>), dim3(512), dim3(64), 0, st, a, 1);
+        hipLaunchKernelGGL((k_classify<kListLarge, 1, 2, C>), dim3(512), dim3(64), 0, st, a, 1, -1);
     else
-        hipLaunchKernelGGL((k_classify<kListLarge, 1, 4, C>), dim3(512), dim3(64), 0, st, a, 1);
+        hipLaunchKernelGGL((k_classify<kListLarge, 1, 4, C>), dim3(512), dim3(64), 0, st, a, 1, -1);
 }
 
 }  // namespace
@@ -960,15 +1044,26 @@ bool classify_config_valid(const ClassifyConfig& c) {
 }
 
 hipError_t launch_classify_fast(const QueryArgs& a, const ClassifyConfig& c, hipStream_t st) {
+    return launch_fast_any(a, c, -1, st);
+}
+
+hipError_t launch_route(const QueryArgs& a, const RouteConfig& r, hipStream_t st) {
     if (a.n_records == 0) return hipSuccess;
-    if (a.S <= 64) return launch_fast_c<1>(a, c, st);
-    if (a.S <= 128) return launch_fast_c<2>(a, c, st);
-    return launch_fast_c<4>(a, c, st);
+    const unsigned grid = (unsigned)std::min<uint64_t>(4096, (a.n_records + 255) / 256);
+    hipLaunchKernelGGL(k_route_count, dim3(grid), dim3(256), 0, st, a, r);
+    hipLaunchKernelGGL(k_route_scan, dim3(1), dim3(64), 0, st, a, r);
+    hipLaunchKernelGGL(k_route_scatter, dim3(grid), dim3(256), 0, st, a, r);
+    return hipGetLastError();
+}
+
+hipError_t launch_classify_class(const QueryArgs& a, const ClassifyConfig& c, uint32_t cls,
+                                 hipStream_t st) {
+    return launch_fast_any(a, c, (int)cls, st);
 }
 
 hipError_t launch_classify_huge(const QueryArgs& a, hipStream_t st) {
     if (a.n_records == 0) return hipSuccess;
-    const dim3 grid(kHugeGroups), blk(kHugeThreads);
+    const dim3 grid(a.huge_groups ? a.huge_groups : kHugeGroups), blk(kHugeThreads);
     if (a.cval) {
         if (a.S <= 64) hipLaunchKernelGGL((k_classify_huge<1, true>), grid, blk, 0, st, a);
         else if (a.S <= 128) hipLaunchKernelGGL((k_classify_huge<2, true>), grid, blk, 0, st, a);

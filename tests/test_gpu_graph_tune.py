@@ -147,3 +147,35 @@ def test_graph_recaptured_after_addition(setup):
     assert_oracle(oracle_results(g, recs, 4), before)
     assert_oracle(oracle_results(g, recs), lab)
     graph.close()
+
+
+def test_size_class_routing(setup, want):
+    """Records routed into size classes (at most 2 windows, at most 4, the
+    rest), each classified by its own launch shape: the oracle's results, in
+    eager launches, after per-class autotuning and in a captured graph."""
+    torch, g, db, recs = setup
+    r, o = dev(torch, recs)
+    n = recs.n_records
+    mc.mc_db_set_routing(db.h, [2, 4], [(256, 8, 16384), (512, 4, 64), (1024, 2, 16384)])
+    assert mc.mc_db_get_routing(db.h) == ([2, 4], [(256, 8, 16384), (512, 4, 64),
+                                                     (1024, 2, 16384)])
+    lab, top = db.classify(r, o, n, paired=True, insert_size=400, with_top=True)
+    torch.cuda.synchronize()
+    assert_oracle(want, lab, top)
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    mc.mc_db_autotune(db.h, r, o, n, mc.QueryOpts(4, 4, 0, 400, 1), out)
+    bounds, shapes = mc.mc_db_get_routing(db.h)
+    assert bounds == [2, 4] and len(shapes) == 3
+    assert_oracle(want, out)
+    lab2 = torch.empty(n, dtype=torch.int32, device="cuda")
+    graph = mc.ClassifyGraph(db.h, r, o, n, mc.QueryOpts(4, 4, 0, 400, 1), lab2)
+    for _ in range(3):
+        lab2.fill_(-7)
+        graph.launch()
+        torch.cuda.synchronize()
+        assert_oracle(want, lab2)
+    graph.close()
+    with pytest.raises(mc.MCError):
+        mc.mc_db_set_routing(db.h, [4, 2], [(256, 4, 64)] * 3)
+    mc.mc_db_set_routing(db.h, [], [(512, 4, 16384)])
+    mc.mc_db_set_launch_config(db.h, 512, 4, 16384)
