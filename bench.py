@@ -656,7 +656,8 @@ def main():
     import paper_2106_08150_amd as mc
     from paper_2106_08150_amd import synth
 
-    mc.lib()   # fails loudly without the HIP library
+    if not os.path.exists(mc.LIB_PATH):   # fail loudly without the HIP library (loaded below,
+        mc.lib()                          # after the forked generators and torch)
     t0 = time.perf_counter()
     # every input is generated before the process touches the GPU (the large
     # sets by forked workers)
@@ -679,6 +680,7 @@ def main():
     import torch
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    mc.lib()
     props = torch.cuda.get_device_properties(dev)
     g_pinned = torch.empty(g.text.size, dtype=torch.uint8, pin_memory=True)
     g_pinned.numpy()[:] = g.text

@@ -189,10 +189,11 @@ int mc_classify(mc_db* db, const char* reads, const uint64_t* offsets, uint32_t 
                 uint32_t* out_labels, void* stream);
 
 /* Classify with options (see mc_query_opts). out_top: device array of
- * n_records * top_m entries, or NULL. Records whose merged candidate list
- * exceeds 16384 locations (about four windows of 16 features each at the
- * 254 cap) are labelled MC_UNCLASSIFIED and counted; mc_db_query_status
- * reports them. */
+ * n_records * top_m entries, or NULL. Records of any length are classified
+ * up to 16384 sketch elements and 2^20 merged candidate locations (a 40 kbp
+ * read against 300 copies of one genome exceeds that); a record beyond
+ * either limit is labelled MC_UNCLASSIFIED and counted, and
+ * mc_db_query_status reports it. */
 int mc_classify_ex(mc_db* db, const char* reads, const uint64_t* offsets, uint32_t n_records,
                    const mc_query_opts* opts, uint32_t* out_labels, mc_tophit* out_top,
                    void* stream);

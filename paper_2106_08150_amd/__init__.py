@@ -108,12 +108,19 @@ _lib = None
 
 
 def lib():
-    """The loaded libmc.so (raises if it has not been built)."""
+    """The loaded libmc.so (raises if it has not been built).
+
+    torch is imported first: its HIP runtime then serves libmc.so too (the
+    library's libamdhip64.so.7 dependency resolves to the copy torch loaded).
+    Loaded the other way round, the process would hold two HIP runtimes, and
+    device pointers and streams from torch would not be valid in the library.
+    """
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
                               "(python -m paper_2106_08150_amd.build)")
+        import torch  # noqa: F401  (one HIP runtime: torch's)
         L = C.CDLL(LIB_PATH)
         u32, u64, vp, i32 = C.c_uint32, C.c_uint64, C.c_void_p, C.c_int
         L.mc_last_error.restype = C.c_char_p

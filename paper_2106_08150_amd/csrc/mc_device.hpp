@@ -259,19 +259,65 @@ __device__ __forceinline__ bool kmer_at(const Word* W, uint32_t x, uint32_t k, u
 }
 
 // ------------------------------------------------------- bitonic in regs --
-// Lanes of a compare-exchange step of a bitonic network over elements
-// r * 64 + lane that keep the smaller key: those whose block of `size` runs
-// ascending ((element & size) == 0) and that are the lower partner
-// ((lane & stride) == 0), or neither. A constant of the step.
-__host__ __device__ constexpr uint64_t keep_low_lanes(int size, int stride, int r) {
+// Lanes of a compare-exchange step of a bitonic network that keep the smaller
+// key: those whose block of `size` runs ascending ((element & size) == 0) and
+// that are the lower partner ((lane & stride) == 0), or neither. The elements
+// are r * 64 + lane, or, for two independent 32-lane networks (halves), lane
+// & 31. A constant of the step.
+__host__ __device__ constexpr uint64_t keep_low_lanes(int size, int stride, int r,
+                                                      bool halves = false) {
     uint64_t m = 0;
     for (int l = 0; l < 64; ++l) {
-        const bool asc = (((r * 64) + l) & size) == 0;
+        const int e = halves ? (l & 31) : r * 64 + l;
+        const bool asc = (e & size) == 0;
         const bool lower = (l & stride) == 0;
         if (asc == lower) m |= 1ull << l;
     }
     return m;
 }
+static_assert(keep_low_lanes(2, 1, 0) == 0x9999999999999999ull, "first step: up, down, ...");
+static_assert(keep_low_lanes(64, 32, 0) == 0x00000000FFFFFFFFull, "last merge runs ascending");
+static_assert(keep_low_lanes(64, 1, 1) == 0xAAAAAAAAAAAAAAAAull, "second register descends");
+static_assert(keep_low_lanes(32, 16, 0, true) == 0x0000FFFF0000FFFFull,
+              "both halves' last merge runs ascending");
+static_assert(keep_low_lanes(16, 8, 0, true) == keep_low_lanes(16, 8, 0), "halves agree below 32");
+
+// Compile-time check of the step masks: the networks of wave_sort (KPL keys a
+// lane) and wave_sort_halves, run on the host over a few key patterns with
+// these masks, leave every sequence ascending.
+template <int KPL>
+constexpr bool bitonic_masks_sort(bool halves, uint32_t seed) {
+    constexpr int N = 64 * KPL;
+    uint32_t v[N] = {};
+    for (int e = 0; e < N; ++e) v[e] = ((uint32_t)e * 2654435761u + seed) % 97u;   // duplicates too
+    const int top = halves ? 32 : N;
+    for (int size = 2; size <= top; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            uint64_t mask[KPL] = {};
+            for (int r = 0; r < KPL && stride < 64; ++r)
+                mask[r] = keep_low_lanes(size, stride, r, halves);
+            uint32_t nv[N] = {};
+            for (int e = 0; e < N; ++e) {
+                const int r = e / 64, l = e % 64;
+                const uint32_t o = v[e ^ stride];
+                const uint32_t lo = v[e] < o ? v[e] : o, hi = v[e] < o ? o : v[e];
+                const bool low = stride >= 64
+                                     ? ((((r * 64) & size) == 0) == ((e & stride) == 0))
+                                     : ((mask[r] >> l) & 1u) != 0;
+                nv[e] = low ? lo : hi;
+            }
+            for (int e = 0; e < N; ++e) v[e] = nv[e];
+        }
+    for (int e = 1; e < N; ++e)
+        if ((!halves || (e & 31) != 0) && v[e - 1] > v[e]) return false;
+    return true;
+}
+static_assert(bitonic_masks_sort<1>(false, 0) && bitonic_masks_sort<1>(false, 5),
+              "64-key network");
+static_assert(bitonic_masks_sort<2>(false, 1) && bitonic_masks_sort<4>(false, 3),
+              "128- and 256-key networks");
+static_assert(bitonic_masks_sort<1>(true, 0) && bitonic_masks_sort<1>(true, 7),
+              "two 32-key networks");
 
 // The lanes of a constant 64-bit mask as a per-lane predicate. The mask is
 // written by two scalar moves of immediates where it is used (volatile, so
@@ -474,7 +520,6 @@ __device__ __forceinline__ uint32_t sketch_window_rare(const Word* W, uint32_t x
 }
 
 // Ascending bitonic sort of each 32-lane half of the wave (one key per lane).
-// (For size <= 32 the step masks of keep_low_lanes are those of each half.)
 __device__ __forceinline__ void wave_sort_halves(uint32_t& v) {
 #pragma unroll
     for (int size = 2; size <= 32; size <<= 1) {
@@ -482,7 +527,7 @@ __device__ __forceinline__ void wave_sort_halves(uint32_t& v) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
             uint32_t o = xor_lanes_c(v, stride);
             uint32_t lo = v < o ? v : o, hi = v < o ? o : v;
-            v = lanes_of(keep_low_lanes(size, stride, 0)) ? lo : hi;
+            v = lanes_of(keep_low_lanes(size, stride, 0, true)) ? lo : hi;
         }
     }
 }

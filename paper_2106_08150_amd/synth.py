@@ -266,6 +266,19 @@ def _large_cluster(args) -> None:
         substitute_inplace(rng, dst, d)
 
 
+def _gpu_runtime_in_use() -> bool:
+    """Whether this process has initialised a GPU through torch, or loaded
+    libmc.so on a machine with a GPU (its HIP runtime must not be shared with
+    forked children). Counting devices does not initialise one."""
+    import sys
+    torch = sys.modules.get("torch")
+    if torch is not None and torch.cuda.is_initialized():
+        return True
+    mc = sys.modules.get("paper_2106_08150_amd")
+    return (mc is not None and getattr(mc, "_lib", None) is not None and torch is not None
+            and torch.cuda.device_count() > 0)
+
+
 def large_genomes(seed: int = 501, total_bp: float = 3.0e10, n_clusters: int = 750,
                   per_cluster: int = 10, div_lo: float = 0.01, div_hi: float = 0.20,
                   level1: int = 150, workers: int = 16, progress=None) -> Genomes:
@@ -278,10 +291,9 @@ def large_genomes(seed: int = 501, total_bp: float = 3.0e10, n_clusters: int = 7
     import multiprocessing as mp
     import sys
     global _LARGE_TEXT
-    torch = sys.modules.get("torch")
-    if torch is not None and torch.cuda.is_initialized():
+    if _gpu_runtime_in_use():
         raise RuntimeError("large_genomes forks worker processes: call it before the process "
-                           "touches a GPU")
+                           "touches a GPU or loads the HIP library")
     rng = rng_for(seed)
     n = n_clusters * per_cluster
     raw = np.exp(rng.normal(np.log(4e6), 0.4, size=n))
@@ -358,10 +370,9 @@ def stream_reads(genomes: Genomes, n: int, seed: int, length: int = 150, error: 
     import multiprocessing as mp
     import sys
     global _READS_JOB
-    torch = sys.modules.get("torch")
-    if torch is not None and torch.cuda.is_initialized():
+    if _gpu_runtime_in_use():
         raise RuntimeError("stream_reads forks worker processes: call it before the process "
-                           "touches a GPU")
+                           "touches a GPU or loads the HIP library")
     size = n * length
     buf = mmap.mmap(-1, max(size, 1), flags=mmap.MAP_SHARED | mmap.MAP_ANONYMOUS)
     text = np.frombuffer(buf, dtype=np.uint8, count=size)
