@@ -198,6 +198,27 @@ int mc_classify_ex(mc_db* db, const char* reads, const uint64_t* offsets, uint32
                    const mc_query_opts* opts, uint32_t* out_labels, mc_tophit* out_top,
                    void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * classification as mc_classify_ex, bit for bit, with every device buffer
+ * beyond the caller's inputs and outputs taken from a fixed scratch array of
+ * MC_NOALLOC_SCRATCH_BYTES that the library holds on each device it runs on
+ * until the process ends (its address is looked up on the first call on a
+ * device). It calls no allocating routine. n_records must not exceed
+ * MC_NOALLOC_MAX_RECORDS (MC_ERR_INVALID_ARG otherwise, nothing launched).
+ * All calls on one device share that device's scratch: calls that overlap on
+ * one GPU (other streams, other threads, other handles) race and must be
+ * ordered by the caller. The scratch's counters are cleared by each call;
+ * records too long for every pass are labelled MC_UNCLASSIFIED but not
+ * reported through mc_db_query_status, and the handle's query statistics are
+ * not updated. The handle must not change (additions, taxonomy, condensing)
+ * while a call is in flight. */
+#define MC_NOALLOC_MAX_RECORDS   1048576u
+#define MC_NOALLOC_SCRATCH_BYTES 33817088u
+int mc_classify_noalloc(mc_db* db, const char* reads, const uint64_t* offsets,
+                        uint32_t n_records, const mc_query_opts* opts, uint32_t* out_labels,
+                        mc_tophit* out_top, void* stream);
+
 /* Waits for `stream`, then reports (and clears) the number of records since
  * the last call whose candidate list was too long (MC_ERR_LIST if > 0). */
 int mc_db_query_status(mc_db* db, void* stream, uint64_t* n_too_long);

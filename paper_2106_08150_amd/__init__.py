@@ -42,8 +42,9 @@ EXPORTS = [
     "mc_db_set_launch_config", "mc_db_get_launch_config", "mc_db_autotune",
     "mc_classify_graph_create", "mc_classify_graph_launch", "mc_classify_graph_destroy",
     "mc_release_cached_memory", "mc_set_cached_memory_limit", "mc_db_set_insert_path",
-    "mc_db_condense", "mc_db_set_routing", "mc_db_get_routing",
+    "mc_db_condense", "mc_db_set_routing", "mc_db_get_routing", "mc_classify_noalloc",
 ]
+NOALLOC_MAX_RECORDS = 1 << 20   # MC_NOALLOC_MAX_RECORDS
 
 
 class MCError(RuntimeError):
@@ -148,6 +149,8 @@ def lib():
         L.mc_classify.argtypes = [vp, vp, vp, u32, vp, vp]
         L.mc_classify_ex.restype = i32
         L.mc_classify_ex.argtypes = [vp, vp, vp, u32, C.POINTER(QueryOpts), vp, vp, vp]
+        L.mc_classify_noalloc.restype = i32
+        L.mc_classify_noalloc.argtypes = [vp, vp, vp, u32, C.POINTER(QueryOpts), vp, vp, vp]
         L.mc_db_query_status.restype = i32
         L.mc_db_query_status.argtypes = [vp, vp, C.POINTER(u64)]
         L.mc_db_get_stats.restype = i32
@@ -286,6 +289,15 @@ def mc_classify_ex(db: int, reads, offsets, n_records: int, opts: QueryOpts, out
     top = _dev_ptr(out_top) if out_top is not None else None
     _check(lib().mc_classify_ex(db, _dev_ptr(reads), _dev_ptr(offsets), n_records,
                                 C.byref(opts), _dev_ptr(out_labels), top, _stream(stream)))
+
+
+def mc_classify_noalloc(db: int, reads, offsets, n_records: int, opts: QueryOpts, out_labels,
+                        out_top=None, stream=None) -> None:
+    """As mc_classify_ex, with the library's fixed per-device scratch (no
+    device allocation; at most NOALLOC_MAX_RECORDS records a call)."""
+    top = _dev_ptr(out_top) if out_top is not None else None
+    _check(lib().mc_classify_noalloc(db, _dev_ptr(reads), _dev_ptr(offsets), n_records,
+                                     C.byref(opts), _dev_ptr(out_labels), top, _stream(stream)))
 
 
 def mc_db_query_status(db: int, stream=None) -> int:

@@ -13,7 +13,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmc.so")
-SOURCES = ["mc_api.hip", "mc_build.hip", "mc_query.hip", "mc_server.hip", "mc_condense.hip"]
+SOURCES = ["mc_api.hip", "mc_build.hip", "mc_query.hip", "mc_server.hip", "mc_condense.hip",
+           "mc_noalloc.hip"]
 PEAKS_LIB = os.path.join(HERE, "libmc_peaks.so")
 PEAKS_SOURCES = ["mc_peaks.hip"]
 ARCH = os.environ.get("MC_OFFLOAD_ARCH", "gfx950")
