@@ -69,7 +69,7 @@ struct Workspace {
     uint32_t* route_meta = nullptr;          // kRouteMetaWords
     uint64_t queue_cap = 0;                  // records
     uint32_t* counters = nullptr;            // kNumQueryCounters
-    unsigned long long* qstats = nullptr;    // kNumQueryStats
+    unsigned long long* qstats = nullptr;    // kQsWords
     unsigned char* huge = nullptr;           // kHugeBytes (HBM-list pass)
     uint32_t huge_groups = 0;                // regions in huge (0 = kHugeGroups)
 };
@@ -723,11 +723,11 @@ int check_db(mc_db* db) {
 // (the pass leaves them at zero).
 int init_workspace(Workspace& w, hipStream_t st) {
     if (int rc = dev_alloc(&w.counters, kNumQueryCounters)) return rc;
-    if (int rc = dev_alloc(&w.qstats, kNumQueryStats)) return rc;
+    if (int rc = dev_alloc(&w.qstats, kQsWords)) return rc;
     if (int rc = dev_alloc(&w.huge, kHugeBytes)) return rc;
     if (int rc = dev_alloc(&w.route_meta, kRouteMetaWords)) return rc;
     HIP_TRY(launch_fill_u32(w.counters, kNumQueryCounters, 0u, st));
-    HIP_TRY(launch_fill_u64(w.qstats, kNumQueryStats, 0ull, st));
+    HIP_TRY(launch_fill_u64(w.qstats, kQsWords, 0ull, st));
     for (uint32_t r = 0; r < kHugeGroups; ++r)
         HIP_TRY(launch_fill_u64(reinterpret_cast<unsigned long long*>(w.huge + r * kHugeRegionBytes),
                                 kHugeTargets, 0ull, st));
@@ -1193,12 +1193,14 @@ int mc_db_get_stats(mc_db* db, mc_db_stats* out) {
     *out = db->st;
     for (auto& kv : db->ws) {
         if (!kv.second.qstats) continue;
-        unsigned long long q[kNumQueryStats];
+        std::vector<unsigned long long> q(kQsWords);
         HIP_TRY(hipStreamSynchronize(kv.first));
-        HIP_TRY(hipMemcpy(q, kv.second.qstats, sizeof q, hipMemcpyDeviceToHost));
-        out->q_features += q[kQsFeatures];
-        out->q_locations += q[kQsLocations];
-        out->q_probes += q[kQsProbes];
+        HIP_TRY(hipMemcpy(q.data(), kv.second.qstats, kQsWords * 8ull, hipMemcpyDeviceToHost));
+        for (uint32_t c = 0; c < kQsCopies; ++c) {
+            out->q_features += q[c * kQsStride + kQsFeatures];
+            out->q_locations += q[c * kQsStride + kQsLocations];
+            out->q_probes += q[c * kQsStride + kQsProbes];
+        }
     }
     out->n_targets = db->taxa.size();
     out->n_windows = db->n_windows;

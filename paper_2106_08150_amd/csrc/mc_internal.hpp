@@ -142,7 +142,7 @@ struct QueryArgs {
     uint32_t* out_top;            // n_records * top_m * 3 u32, or null
     uint32_t* queue;              // record ids: [0, n) large-list pass, [n, 2n) HBM-list pass
     uint32_t* counters;
-    unsigned long long* qstats;   // kNumQueryStats running totals
+    unsigned long long* qstats;   // kQsWords: kQsCopies partial totals (or null)
     unsigned char* huge;          // HBM-list scratch: huge_groups regions of kHugeRegionBytes
                                   // (per-target bests zero)
     uint32_t huge_groups;         // regions (workgroups of the HBM-list pass), 0 = kHugeGroups
@@ -167,6 +167,14 @@ struct RouteConfig {
 };
 
 enum QueryStat { kQsFeatures = 0, kQsLocations = 1, kQsProbes = 2, kNumQueryStats = 4 };
+// The query statistics are kept as kQsCopies partial totals, each on its own
+// 128-byte line: a wave adds its counts to copy (wave id mod kQsCopies), so
+// the waves of a launch do not all queue their atomics on one line (at about
+// 12 ns an atomic, three a wave cost a launch of 16,384 four-wave workgroups
+// 2.4 ms on a single line). The host sums the copies.
+constexpr uint32_t kQsCopies = 64;
+constexpr uint32_t kQsStride = 16;                     // u64 words between copies
+constexpr uint32_t kQsWords = kQsCopies * kQsStride;
 
 constexpr uint32_t kListSmall = 512;     // candidate locations per record, fast path
 constexpr uint32_t kListLarge = 16384;   // large-list pass (one wave per workgroup)

@@ -110,9 +110,12 @@ __device__ bool lookup(const QueryArgs& a, const uint32_t* F, uint32_t nf, uint2
             f[q] = it.x;
             b[q] = it.y;
         }
+        // groups past the batch's last item load nothing (their lines would
+        // be fetched only to be ignored); `valid` below keeps their
+        // unloaded values out of every result
 #pragma unroll
         for (int q = 0; q < NB; ++q)
-            if (G * q < c) sl[q] = slot2[(uint64_t)b[q] * (kSlots / 2)];
+            if (G * q + g < c) sl[q] = slot2[(uint64_t)b[q] * (kSlots / 2)];
         head += c;
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
@@ -191,8 +194,8 @@ __device__ bool lookup_cond(const QueryArgs& a, const uint32_t* F, uint32_t nf, 
             b[q] = it.y;
         }
 #pragma unroll
-        for (int q = 0; q < NB; ++q)
-            if (G * q < c) e[q] = ent[(uint64_t)b[q] * kCondEntries];
+        for (int q = 0; q < NB; ++q)   // idle groups load nothing (see lookup)
+            if (G * q + g < c) e[q] = ent[(uint64_t)b[q] * kCondEntries];
         head += c;
         uint32_t nrun = 0;   // runs of this batch (at most one a group and q: 32)
 #pragma unroll
@@ -605,9 +608,10 @@ void k_classify(QueryArgs a, int big, int cls) {
     }
     // work of records that go on to the large-list pass counts in both passes
     if (lane_id() == 0 && a.qstats) {
-        if (ws.features) atomicAdd(&a.qstats[kQsFeatures], (unsigned long long)ws.features);
-        if (ws.locations) atomicAdd(&a.qstats[kQsLocations], (unsigned long long)ws.locations);
-        if (ws.probes) atomicAdd(&a.qstats[kQsProbes], (unsigned long long)ws.probes);
+        unsigned long long* q = a.qstats + ((blockIdx.x * WPB + wave) % kQsCopies) * kQsStride;
+        if (ws.features) atomicAdd(&q[kQsFeatures], (unsigned long long)ws.features);
+        if (ws.locations) atomicAdd(&q[kQsLocations], (unsigned long long)ws.locations);
+        if (ws.probes) atomicAdd(&q[kQsProbes], (unsigned long long)ws.probes);
     }
 }
 
@@ -894,11 +898,12 @@ __device__ void classify_huge_record(const QueryArgs& a, uint32_t rec, const Hug
         o[2] = hit ? L.sel_b[tid] : 0u;
     }
     if (a.qstats) {
+        unsigned long long* q = a.qstats + ((blockIdx.x * kHugeWaves + wave) % kQsCopies) * kQsStride;
         for (int m = 1; m < kWave; m <<= 1) probes += shfl_xor(probes, m);
-        if (lane == 0 && probes) atomicAdd(&a.qstats[kQsProbes], (unsigned long long)probes);
+        if (lane == 0 && probes) atomicAdd(&q[kQsProbes], (unsigned long long)probes);
         if (tid == 0) {
-            atomicAdd(&a.qstats[kQsFeatures], (unsigned long long)nf);
-            atomicAdd(&a.qstats[kQsLocations], (unsigned long long)n);
+            atomicAdd(&q[kQsFeatures], (unsigned long long)nf);
+            atomicAdd(&q[kQsLocations], (unsigned long long)n);
         }
     }
     __syncthreads();
