@@ -94,6 +94,11 @@ def parse():
     ap.add_argument("--large-shape", type=str, default="auto",
                     help="launch shape of the large leg: 'auto' (mc_db_autotune on the first 2M "
                          "reads) or list capacity, waves per workgroup, largest grid")
+    ap.add_argument("--served-parity", type=int, default=0,
+                    help="records of the served trace checked against the (feature-filtered) "
+                         "oracle on the database after all its on-demand additions, plus a "
+                         "table slice (0 = skip: the oracle's scan of 10 Gbp takes about a "
+                         "minute of host time)")
     ap.add_argument("--large-parity", type=int, default=0,
                     help="reads of the large stream checked against the (feature-filtered) "
                          "oracle, plus a table slice (0 = skip: the oracle's scan of 30 Gbp "
@@ -203,7 +208,16 @@ def oracle_sample_parity(g, reads, sample, gl, gt, slice_hi, gf, gloc, threads):
     odb = oracle.OracleDB(K, WINDOW, SKETCH, CAP)
     odb.set_filter(np.unique(np.concatenate(feats)))
     odb.set_filter_range(0, slice_hi)
-    odb.add_targets(g.text, g.lengths, g.taxa, threads=threads)
+    # the genomes in pieces of about 2 Gbp (target ids run on), with a line each
+    off = g.offsets.astype(np.int64)
+    cuts = np.searchsorted(off, np.arange(0, off[-1], 2e9))[1:].tolist() + [g.lengths.size]
+    a = 0
+    for b in cuts:
+        if b <= a:
+            continue
+        odb.add_targets(g.text[off[a]:off[b]], g.lengths[a:b], g.taxa[a:b], threads=threads)
+        log(f"oracle: scanned {b}/{g.lengths.size} genomes")
+        a = b
     odb.set_taxonomy(g.parents)
     of, oloc = odb.dump()
     keep = of <= slice_hi
@@ -427,7 +441,11 @@ def served_leg(args, g, gtext, torch, mc, synth):
                         "labels_identical": bool(same)})
         log(f"load {load:.2f}: served p50 {pct(s_lat, 50):.2f} p99 {pct(s_lat, 99):.2f} ms, "
             f"plain p50 {pct(p_lat, 50):.2f} p99 {pct(p_lat, 99):.2f} ms, identical {same}")
+    parity = None
+    if args.served_parity > 0 and adds:
+        parity = served_parity(args, g, gtext, reads, adds, add_pairs, torch, mc)
     return {
+        "oracle_parity": parity,
         "trace": (f"{nb} batches, Poisson arrivals, sizes log-uniform 1e3..1e6 reads of "
                   f"100-250 bp (1% substitutions, 5% foreign), {len(adds)} addition(s) of 20 "
                   f"genomes; the database: {g.lengths.size} genomes, "
@@ -439,6 +457,62 @@ def served_leg(args, g, gtext, torch, mc, synth):
         "loads": results,
         "labels_identical": bool(same_all),
     }
+
+
+def records_subset(reads, sample):
+    """Text and u64 offsets of the single-end records `sample` of `reads`."""
+    off = reads.offsets.astype(np.int64)
+    pieces = [reads.text[off[i]:off[i + 1]] for i in sample]
+    o = np.zeros(len(pieces) + 1, np.int64)
+    o[1:] = np.cumsum([p.size for p in pieces])
+    return np.concatenate(pieces), o
+
+
+def served_parity(args, g, gtext, reads, adds, add_pairs, torch, mc):
+    """The served leg's database after every on-demand addition (built the
+    way the served loop grows it: the reference set, then each addition with
+    its extended taxonomy) against the feature-filtered oracle on all those
+    genomes: a sample of the trace's records (labels and top hits) and a slice
+    of the table (features <= 2^20 - 1)."""
+    from paper_2106_08150_amd import synth
+    dev = gtext.device
+    db = mc.Database(K, WINDOW, SKETCH, CAP)
+    db.reserve(windows_of(g.lengths) * SKETCH + add_pairs)
+    db.add_targets(gtext, g.lengths, g.taxa)
+    db.set_taxonomy(g.parents)
+    texts, lens, taxa, parents = [g.text], [g.lengths], [g.taxa], g.parents
+    for i in sorted(adds):
+        add, par = adds[i]
+        db.add_targets(add.text, add.lengths, add.taxa)
+        db.set_taxonomy(par)
+        texts.append(add.text)
+        lens.append(add.lengths)
+        taxa.append(add.taxa)
+        parents = par
+    full = synth.Genomes(np.concatenate(texts), np.concatenate(lens), np.concatenate(taxa),
+                         parents)
+    sample = np.sort(np.random.default_rng(11).choice(reads.n_records, args.served_parity,
+                                                      replace=False))
+    txt, off = records_subset(reads, sample)
+    lab, top = db.classify(torch.from_numpy(txt).to(dev), torch.from_numpy(off).to(dev),
+                           sample.size, with_top=True)
+    torch.cuda.synchronize()
+    gl = lab.cpu().numpy().view(np.uint32)
+    gt = top.cpu().numpy().view(np.uint32)
+    slice_hi = (1 << 20) - 1
+    gf, gloc = db.dump(0, slice_hi)
+    st = db.stats()
+    db.close()
+    t0 = time.perf_counter()
+    bad, table_ok = oracle_sample_parity(full, reads, sample, gl, gt, slice_hi, gf, gloc,
+                                         min(16, os.cpu_count() or 1))
+    log(f"served: oracle parity after {len(adds)} addition(s) on {sample.size} records: "
+        f"{bad} mismatches, table slice equal {table_ok}")
+    return {"sample_records": int(sample.size), "mismatches": bad,
+            "genomes": int(full.lengths.size), "gbp": float(full.lengths.sum()) / 1e9,
+            "additions": len(adds), "table_slice_features_le": slice_hi,
+            "table_slice_pairs": int(gf.size), "table_slice_equal": table_ok,
+            "n_pairs_stored": st["n_pairs_stored"], "oracle_s": time.perf_counter() - t0}
 
 
 def large_leg(args, g, stream, torch, mc):

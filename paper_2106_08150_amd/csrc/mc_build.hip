@@ -70,8 +70,10 @@ __global__ __launch_bounds__(kBuildThreads) void k_sketch(BuildArgs a) {
         uintptr_t bhi = tstart + (uint64_t)(j0 + nwin - 1) * a.S + a.w;
         if (bhi > tend) bhi = tend;
         __syncthreads();
-        stage_words(L.words, blo, bhi, tstart, tend, tid, kBuildThreads);
-        __syncthreads();
+        // a tile without a non-base byte (the common case) skips the
+        // per-k-mer validity test
+        const bool dirty =
+            __syncthreads_or(stage_words(L.words, blo, bhi, tstart, tend, tid, kBuildThreads));
         const uintptr_t A0 = blo & ~(uintptr_t)15;
         const uint64_t n_starts = td.len - a.k + 1;
         // each wave sketches pairs of windows (2i, 2i+1) of the tile
@@ -86,7 +88,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_sketch(BuildArgs a) {
             uint32_t* sk = L.feats[wave];
             uint32_t n[2];
             sketch_pair<KPL>(L.words, x0[0], nk[0], L.words, x0[1], nk[1], a.k, a.s, th, sk,
-                             sk + kMaxSketch, L.scratch[wave], n[0], n[1]);
+                             sk + kMaxSketch, L.scratch[wave], n[0], n[1], dirty, dirty);
             wave_lds_sync();
             // entry e of the pair: window e / s, sketch slot e % s
             const uint32_t npair = wv + 1 < nwin ? 2u : 1u;

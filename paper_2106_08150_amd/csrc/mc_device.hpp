@@ -179,15 +179,18 @@ __device__ __forceinline__ uint32_t pack_fields(uint32_t v) {
 // ((x >> 1) ^ (x >> 2)) & 3 maps A/a C/c G/g T/t to 0 1 2 3; a byte is a base
 // iff it equals "acgt"[code] once lower-cased (v_perm looks the letter up).
 // c8: the 4 codes (those of invalid bases are arbitrary), first base in bits
-// 7..6; m8: 0b11 in the positions of invalid bases.
-__device__ __forceinline__ void encode4(uint32_t x, uint32_t ok, uint32_t& c8, uint32_t& m8) {
+// 7..6; m8: 0b11 in the positions of invalid bases. Returns whether a byte
+// inside the sequence is not a base.
+__device__ __forceinline__ bool encode4(uint32_t x, uint32_t ok, uint32_t& c8, uint32_t& m8) {
     const uint32_t c = ((x >> 1) ^ (x >> 2)) & 0x03030303u;
     const uint32_t expect = __builtin_amdgcn_perm(0u, 0x74676361u, c);
     const uint32_t diff = (x | 0x20202020u) ^ expect;           // zero byte: a base
     const uint32_t t = (diff & 0x7F7F7F7Fu) + 0x7F7F7F7Fu;
-    const uint32_t inv = (t | diff | ~ok) & 0x80808080u;         // 0x80 per invalid base
+    const uint32_t bad = (t | diff) & ok & 0x80808080u;          // 0x80 per non-base inside
+    const uint32_t inv = bad | (~ok & 0x80808080u);               // 0x80 per invalid base
     c8 = pack_fields(c);
     m8 = pack_fields((inv >> 6) | (inv >> 7));
+    return bad != 0u;
 }
 
 // 0x80 in the bytes [lo, hi) of a dword (0 <= lo < hi <= 4).
@@ -199,8 +202,9 @@ __device__ __forceinline__ uint32_t inside_bytes(uint32_t lo, uint32_t hi) {
 // [vlo, vhi) count as invalid. A word that overlaps [vlo, vhi) is read with
 // one 16-byte load: an aligned 16-byte block never crosses a page, so it lies
 // in the same mapped page as the valid byte it contains. A word that does not
-// overlap is not read at all.
-__device__ __forceinline__ Word load_word(uintptr_t a, uintptr_t vlo, uintptr_t vhi) {
+// overlap is not read at all. `bad` is set if a byte inside [vlo, vhi) is not
+// a base.
+__device__ __forceinline__ Word load_word(uintptr_t a, uintptr_t vlo, uintptr_t vhi, bool& bad) {
     if (a + 16 <= vlo || a >= vhi) return Word{0u, 0xFFFFFFFFu};
     // the address is global memory; saying so gives a global (not flat) load
     typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -214,7 +218,7 @@ __device__ __forceinline__ Word load_word(uintptr_t a, uintptr_t vlo, uintptr_t 
         const uint32_t dlo = lo > 4u * i ? min(lo - 4u * i, 4u) : 0u;
         const uint32_t dhi = hi > 4u * i ? min(hi - 4u * i, 4u) : 0u;
         const uint32_t ok = dlo < dhi ? inside_bytes(dlo, dhi) : 0u;
-        encode4(i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w, ok, c[i], m[i]);
+        bad |= encode4(i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w, ok, c[i], m[i]);
     }
     Word w;
     w.code = (c[0] << 24) | (c[1] << 16) | (c[2] << 8) | c[3];
@@ -226,36 +230,51 @@ __device__ __forceinline__ Word load_word(uintptr_t a, uintptr_t vlo, uintptr_t 
 // dword d of word d >> 2 goes to byte 3 - (d & 3) of that word's code and mask
 // (first base in the top byte). Bytes outside [vlo, vhi) count as invalid; a
 // dword that does not overlap them is not read. Aligned 4-byte loads never
-// cross a page.
-__device__ __forceinline__ void stage_dword(Word* W, uintptr_t A0, uint32_t d, uintptr_t vlo,
+// cross a page. Returns whether a byte inside [vlo, vhi) is not a base.
+__device__ __forceinline__ bool stage_dword(Word* W, uintptr_t A0, uint32_t d, uintptr_t vlo,
                                             uintptr_t vhi) {
     const uintptr_t a = A0 + 4u * d;
     uint32_t c8 = 0u, m8 = 0xFFu;
+    bool bad = false;
     if (a + 4 > vlo && a < vhi) {
         const uint32_t x = *reinterpret_cast<const __attribute__((address_space(1))) uint32_t*>(a);
         const uint32_t lo = vlo > a ? (uint32_t)(vlo - a) : 0u;
         const uint32_t hi = vhi - a < 4 ? (uint32_t)(vhi - a) : 4u;
-        encode4(x, inside_bytes(lo, hi), c8, m8);
+        bad = encode4(x, inside_bytes(lo, hi), c8, m8);
     }
     uint8_t* w = reinterpret_cast<uint8_t*>(W + (d >> 2));
     w[3 - (d & 3u)] = (uint8_t)c8;
     w[7 - (d & 3u)] = (uint8_t)m8;
+    return bad;
+}
+
+// Canonical k-mer (k <= 16) starting o bases into word pair (a, b): the
+// forward k-mer by a funnel shift, the reverse complement by complementing,
+// aligning to the top and reversing the 2-bit groups. Without kCheck the
+// caller knows every base of the k-mer is valid; with it, returns false if
+// one is not.
+template <bool kCheck>
+__device__ __forceinline__ bool kmer_of(const Word& a, const Word& b, uint32_t o, uint32_t k,
+                                        uint32_t& canon) {
+    // the top 32 bits of (a:b) << 2o: a funnel shift for o > 0, a itself for 0
+    const uint32_t top = o ? __builtin_amdgcn_alignbit(a.code, b.code, 32u - 2u * o) : a.code;
+    const uint32_t fwd = top >> (32 - 2 * k);
+    bool bad = false;
+    if constexpr (kCheck) {
+        const uint32_t mtop = o ? __builtin_amdgcn_alignbit(a.mask, b.mask, 32u - 2u * o) : a.mask;
+        bad = (mtop >> (32 - 2 * k)) != 0u;
+    }
+    uint32_t r = __builtin_bitreverse32((~fwd) << (32 - 2 * k));
+    r = ((r >> 1) & 0x55555555u) | ((r & 0x55555555u) << 1);
+    canon = fwd < r ? fwd : r;
+    return !bad;
 }
 
 // Canonical k-mer starting x bases after the first staged word (k <= 16).
 // Returns false if any of its bases is invalid.
 __device__ __forceinline__ bool kmer_at(const Word* W, uint32_t x, uint32_t k, uint32_t& canon) {
-    uint32_t q = x >> 4, o = x & 15u;
-    Word a = W[q], b = W[q + 1];
-    uint64_t v = ((uint64_t)a.code << 32) | b.code;
-    uint32_t fwd = (uint32_t)((v << (2 * o)) >> (64 - 2 * k));
-    uint64_t mv = ((uint64_t)a.mask << 32) | b.mask;
-    bool bad = ((mv << (2 * o)) >> (64 - 2 * k)) != 0ull;
-    // reverse complement: complement, align to the top, reverse 2-bit groups
-    uint32_t r = __builtin_bitreverse32((~fwd) << (32 - 2 * k));
-    r = ((r >> 1) & 0x55555555u) | ((r & 0x55555555u) << 1);
-    canon = fwd < r ? fwd : r;
-    return !bad;
+    const uint32_t q = x >> 4, o = x & 15u;
+    return kmer_of<true>(W[q], W[q + 1], o, k, canon);
 }
 
 // ------------------------------------------------------- bitonic in regs --
@@ -419,10 +438,15 @@ struct Threshold {
 // bases after the first staged word: key[r] belongs to k-mer r*64 + lane and is
 // 0xFFFFFFFF for an invalid k-mer or past nk. Returns whether some valid k-mer
 // hashed to 0xFFFFFFFF (that value then still counts as a distinct feature).
-template <int KPL>
-__device__ __forceinline__ bool window_keys(const Word* W, uint32_t x0, uint32_t nk, uint32_t k,
-                                            uint32_t (&key)[KPL]) {
+// kCheck = false: the caller knows the window holds no invalid base. K-mer
+// r*64 + lane starts 4r words after k-mer lane, at the same offset in its word.
+template <int KPL, bool kCheck>
+__device__ __forceinline__ bool window_keys_t(const Word* W, uint32_t x0, uint32_t nk, uint32_t k,
+                                              uint32_t (&key)[KPL]) {
     const int lane = lane_id();
+    const uint32_t x = x0 + (uint32_t)lane;
+    const Word* Wq = W + (x >> 4);
+    const uint32_t o = x & 15u;
     bool top = false;
 #pragma unroll
     for (int r = 0; r < KPL; ++r) {
@@ -430,7 +454,7 @@ __device__ __forceinline__ bool window_keys(const Word* W, uint32_t x0, uint32_t
         key[r] = 0xFFFFFFFFu;
         if (i < nk) {
             uint32_t c;
-            if (kmer_at(W, x0 + i, k, c)) {
+            if (kmer_of<kCheck>(Wq[4 * r], Wq[4 * r + 1], o, k, c)) {
                 uint32_t h = h1(c);
                 key[r] = h;
                 top |= (h == 0xFFFFFFFFu);
@@ -438,6 +462,12 @@ __device__ __forceinline__ bool window_keys(const Word* W, uint32_t x0, uint32_t
         }
     }
     return ballot(top) != 0;
+}
+
+template <int KPL>
+__device__ __forceinline__ bool window_keys(const Word* W, uint32_t x0, uint32_t nk, uint32_t k,
+                                            uint32_t (&key)[KPL]) {
+    return window_keys_t<KPL, true>(W, x0, nk, k, key);
 }
 
 // The s smallest distinct keys of one window (its nk keys as left by
@@ -576,21 +606,26 @@ __device__ __forceinline__ uint32_t half_candidates(const uint32_t (&key)[KPL], 
 // A window whose candidates do not decide its sketch is redone alone (its
 // staged words must still be in place). All pointers are to LDS. Writes
 // skA[0..nA) and skB[0..nB). scratch: 64 words of LDS owned by the wave.
+// dirtyA / dirtyB (wave-uniform): the window may hold an invalid base; when
+// false its k-mers skip the validity test.
 template <int KPL>
 __device__ __forceinline__ void sketch_pair(const Word* WA, uint32_t xA, uint32_t nkA,
                                             const Word* WB, uint32_t xB, uint32_t nkB,
                                             uint32_t k, uint32_t s, const Threshold& th,
                                             uint32_t* skA, uint32_t* skB,
-                                            uint32_t* scratch, uint32_t& nA, uint32_t& nB) {
+                                            uint32_t* scratch, uint32_t& nA, uint32_t& nB,
+                                            bool dirtyA = true, bool dirtyB = true) {
     const int lane = lane_id();
     int modeA, modeB;
     uint32_t cA, cB;
     bool topA, topB;
     {
         uint32_t key[KPL];
-        topA = window_keys<KPL>(WA, xA, nkA, k, key);
+        topA = dirtyA ? window_keys_t<KPL, true>(WA, xA, nkA, k, key)
+                      : window_keys_t<KPL, false>(WA, xA, nkA, k, key);
         cA = half_candidates<KPL>(key, nkA, s, th, scratch, modeA);
-        topB = window_keys<KPL>(WB, xB, nkB, k, key);
+        topB = dirtyB ? window_keys_t<KPL, true>(WB, xB, nkB, k, key)
+                      : window_keys_t<KPL, false>(WB, xB, nkB, k, key);
         cB = half_candidates<KPL>(key, nkB, s, th, scratch + 32, modeB);
     }
     wave_lds_sync();
@@ -639,12 +674,16 @@ __device__ __forceinline__ void sketch_pair(const Word* WA, uint32_t xA, uint32_
 
 // Stage the bytes [lo, hi) into words relative to A0 = lo & ~15, one word per
 // participating thread (tid in [0, nthreads)); bytes outside [vlo, vhi) are
-// invalid. Returns nothing; callers synchronise before reading W.
-__device__ __forceinline__ void stage_words(Word* W, uintptr_t lo, uintptr_t hi, uintptr_t vlo,
+// invalid. Returns whether a word of this thread holds a byte inside
+// [vlo, vhi) that is not a base; callers synchronise before reading W.
+__device__ __forceinline__ bool stage_words(Word* W, uintptr_t lo, uintptr_t hi, uintptr_t vlo,
                                             uintptr_t vhi, int tid, int nthreads) {
     uintptr_t A0 = lo & ~(uintptr_t)15;
     int nw = (int)((hi - A0 + 15) / 16) + 1;
-    for (int q = tid; q < nw; q += nthreads) W[q] = load_word(A0 + 16 * (uintptr_t)q, vlo, vhi);
+    bool bad = false;
+    for (int q = tid; q < nw; q += nthreads)
+        W[q] = load_word(A0 + 16 * (uintptr_t)q, vlo, vhi, bad);
+    return bad;
 }
 
 // ------------------------------------------------------------ LCA / taxa --

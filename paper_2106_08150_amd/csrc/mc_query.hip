@@ -393,15 +393,22 @@ __device__ __forceinline__ uint32_t staged_words(const WinRef& r) {
 
 // Stage two windows at once, A's words into W[0..) and B's into
 // W[kStageWords..), one dword (4 bases) per lane: a 150-base read's two
-// windows take a single pass of the wave.
-__device__ __forceinline__ void stage_pair(Word* W, const WinRef& A, const WinRef& B, int lane) {
+// windows take a single pass of the wave. dirtyA / dirtyB (wave-uniform): a
+// staged byte of that window's mate is not a base.
+__device__ __forceinline__ void stage_pair(Word* W, const WinRef& A, const WinRef& B, int lane,
+                                           bool& dirtyA, bool& dirtyB) {
     const uint32_t ndA = 4u * staged_words(A), nd = ndA + 4u * staged_words(B);
+    bool badA = false, badB = false;
     for (uint32_t q = (uint32_t)lane; q < nd; q += kWave) {
         const bool second = q >= ndA;
         const WinRef& r = second ? B : A;
-        stage_dword(W + (second ? kStageWords : 0), r.lo & ~(uintptr_t)15, second ? q - ndA : q,
-                    r.vlo, r.vhi);
+        const bool bad = stage_dword(W + (second ? kStageWords : 0), r.lo & ~(uintptr_t)15,
+                                     second ? q - ndA : q, r.vlo, r.vhi);
+        badA |= bad && !second;
+        badB |= bad && second;
     }
+    dirtyA = ballot(badA) != 0;
+    dirtyB = ballot(badB) != 0;
 }
 
 struct WaveStats {
@@ -439,12 +446,13 @@ __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>
         WinRef wr[2];
         for (int h = 0; h < 2; ++h) wr[h] = window_ref(a, p + h, nwt, nws[0], o0, o1, len);
         wave_lds_sync();
-        stage_pair(L.sk.stage, wr[0], wr[1], lane);
+        bool dirtyA, dirtyB;
+        stage_pair(L.sk.stage, wr[0], wr[1], lane, dirtyA, dirtyB);
         wave_lds_sync();
         uint32_t nA, nB;
         sketch_pair<KPL>(L.sk.stage, wr[0].x0, wr[0].nk, L.sk.stage + kStageWords, wr[1].x0, wr[1].nk,
                          a.k, a.s, th, L.sk.feats + nf, L.sk.feats + nf + a.s, L.sk.scratch, nA,
-                         nB);
+                         nB, dirtyA, dirtyB);
         wave_lds_sync();
         if (nA < a.s && nB) {      // close the gap after A's features
             const uint32_t f = (uint32_t)lane < nB ? L.sk.feats[nf + a.s + lane] : 0u;
@@ -514,8 +522,25 @@ __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>
     // u, so the wave maximum of the keys is the highest score and, among equal
     // scores, the smallest location (smallest target, then window). Each of
     // the m rounds takes one wave maximum and then drops the chosen target.
+    //
+    // Without a top-hit output only the label needs the list, and the rounds
+    // stop once it is decided: after the first round if its score is below
+    // min_hits (unclassified), else at the first score more than hit_diff
+    // below the best (a clear lead after the second round; later entries
+    // with lower scores take no part in the LCA).
     uint32_t nsel = 0;
     const uint32_t top_m = MC_COLD(top_m);
+    const bool whole_list = MC_COLD(out_top) != nullptr;
+    const uint32_t min_hits = MC_COLD(min_hits), hit_diff = MC_COLD(hit_diff);
+    uint32_t c_best = 0;
+    auto decided = [&](uint32_t m, uint32_t score) {
+        if (whole_list) return false;
+        if (m == 0) {
+            c_best = score;
+            return score < min_hits;
+        }
+        return (uint64_t)score + hit_diff < c_best;
+    };
     if (U <= (uint32_t)kWave) {          // one distinct location per lane
         uint32_t key = 0, t = kNone;
         if ((uint32_t)lane < U) {
@@ -531,8 +556,9 @@ __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>
                 L.sel_s[m] = k >> 16;
                 L.sel_b[m] = loc & kWindowMask;
             }
-            if (t == loc >> kWindowBits) key = 0;
             nsel = m + 1;
+            if (decided(m, k >> 16)) break;
+            if (t == loc >> kWindowBits) key = 0;
         }
         wave_lds_sync();
     } else {
@@ -555,16 +581,16 @@ __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>
             }
             wave_lds_sync();
             nsel = m + 1;
+            if (decided(m, k >> 16)) break;
         }
     }
 
     // label: the best target's taxon on a clear lead, else the LCA of the
     // taxa of the listed targets within hit_diff of the best score
     uint32_t label = kNone;
-    if (nsel > 0 && L.sel_s[0] >= MC_COLD(min_hits)) {
+    if (nsel > 0 && L.sel_s[0] >= min_hits) {
         const uint32_t c1 = L.sel_s[0], c2 = nsel > 1 ? L.sel_s[1] : 0u;
         const uint32_t* const taxon = MC_COLD(target_taxon);
-        const uint32_t hit_diff = MC_COLD(hit_diff);
         label = uniform(taxon[L.sel_t[0]]);
         if (c1 - c2 <= hit_diff) {
             for (uint32_t x = 1; x < nsel; ++x)
@@ -724,12 +750,13 @@ __device__ void classify_huge_record(const QueryArgs& a, uint32_t rec, const Hug
         WinRef wr[2];
         for (int x = 0; x < 2; ++x) wr[x] = window_ref(a, p + x, nwt, nws[0], o0, o1, len);
         wave_lds_sync();
-        stage_pair(L.stage[wave], wr[0], wr[1], (int)lane);
+        bool dirtyA, dirtyB;
+        stage_pair(L.stage[wave], wr[0], wr[1], (int)lane, dirtyA, dirtyB);
         wave_lds_sync();
         uint32_t nA, nB;
         sketch_pair<KPL>(L.stage[wave], wr[0].x0, wr[0].nk, L.stage[wave] + kStageWords, wr[1].x0,
                          wr[1].nk, a.k, a.s, th, L.sk[wave], L.sk[wave] + 64, L.scratch[wave], nA,
-                         nB);
+                         nB, dirtyA, dirtyB);
         wave_lds_sync();
         uint32_t base = 0;
         if (lane == 0) base = atomicAdd(&L.nfeat, nA + nB);
