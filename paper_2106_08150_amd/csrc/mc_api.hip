@@ -909,6 +909,25 @@ int capture_graph(mc_graph* g, hipStream_t st) {
 namespace mc {
 int db_device(const struct ::mc_db* db) { return db->device; }
 
+int prepare_workspace(struct ::mc_db* db, hipStream_t st, uint64_t n_records) {
+    if (int rc = check_db(db)) return rc;
+    DeviceGuard dg(db->device);
+    int rc = MC_OK;
+    (void)workspace(db, st, n_records, &rc);
+    return rc;
+}
+
+int release_workspace(struct ::mc_db* db, hipStream_t st) {
+    if (int rc = check_db(db)) return rc;
+    auto it = db->ws.find(st);
+    if (it == db->ws.end()) return MC_OK;
+    DeviceGuard dg(db->device);
+    HIP_TRY(hipStreamSynchronize(st));
+    free_workspace(it->second);
+    db->ws.erase(it);
+    return MC_OK;
+}
+
 int classify_into(struct ::mc_db* db, const char* reads, const uint64_t* offsets,
                   uint32_t n_records, const mc_query_opts* opts, uint32_t* out_labels,
                   mc_tophit* out_top, const ScratchView& scratch, hipStream_t st) {

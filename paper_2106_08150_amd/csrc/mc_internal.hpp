@@ -267,6 +267,14 @@ hipError_t launch_condense_dump(const unsigned int* idx, uint64_t nbc, const uin
 // Device of a database handle (for threads that must select it).
 int db_device(const struct ::mc_db* db);
 
+// The query workspace of stream `st` made ready now for classifications of up
+// to n_records records (a server creates its slots' workspaces up front, so
+// that no batch pays for their allocation), and its release once the stream
+// is retired (the stream is synchronised first). Callers serialise calls on
+// one handle.
+int prepare_workspace(struct ::mc_db* db, hipStream_t st, uint64_t n_records);
+int release_workspace(struct ::mc_db* db, hipStream_t st);
+
 // Device scratch of one classification supplied by the caller: counters
 // (kNumQueryCounters u32), routing data (kRouteMetaWords u32), record queues
 // (3 * queue_cap u32) and huge_groups regions of the HBM-list pass.

@@ -320,11 +320,9 @@ __device__ void sort_lds(uint32_t* list, uint32_t n, uint32_t P) {
     }
 }
 
-// Lists of more than 128 locations: out of line, with an LDS pointer so that
-// the out-of-line code keeps LDS instructions.
+// Lists of more than 128 locations.
 template <uint32_t LCAP>
-__device__ __attribute__((noinline)) void sort_list_long(MC_LDS uint32_t* lds_list, uint32_t n) {
-    uint32_t* list = (uint32_t*)lds_list;
+__device__ __forceinline__ void sort_list_long_body(uint32_t* list, uint32_t n) {
     uint32_t P = 256;
     while (P < n) P <<= 1;
     switch (P) {
@@ -335,12 +333,23 @@ __device__ __attribute__((noinline)) void sort_list_long(MC_LDS uint32_t* lds_li
     }
 }
 
+// The fast paths' copy is out of line (the hot loop stays small in the
+// instruction cache), with an LDS pointer so that the out-of-line code keeps
+// LDS instructions. The large-list pass, which every classification launches,
+// inlines it: there the out-of-line call needed a stack frame in scratch
+// memory.
+template <uint32_t LCAP>
+__device__ __attribute__((noinline)) void sort_list_long(MC_LDS uint32_t* lds_list, uint32_t n) {
+    sort_list_long_body<LCAP>((uint32_t*)lds_list, n);
+}
+
 // Ascending sort of list[0..n) in LDS.
 template <uint32_t LCAP>
 __device__ __forceinline__ void sort_list(uint32_t* list, uint32_t n) {
     if (n <= 64) sort_regs<1>(list, n);
     else if (n <= 128) sort_regs<2>(list, n);
-    else sort_list_long<LCAP>((MC_LDS uint32_t*)list, n);
+    else if constexpr (LCAP <= 1024) sort_list_long<LCAP>((MC_LDS uint32_t*)list, n);
+    else sort_list_long_body<LCAP>(list, n);
 }
 
 // Label and top-m list of a record (lane x writes the x-th top hit).
@@ -605,10 +614,20 @@ __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>
 // occupancy pays for a few spilled scalar registers. A 512-entry list takes
 // about 5.7 KB of LDS a wave, which holds a CU to 28 waves: seven a SIMD (at
 // most 72 VGPRs). A 256-entry list takes about 3.7 KB, so eight waves a SIMD
-// fit (64 VGPRs).
+// fit (64 VGPRs). A 1,024-entry list (9.7 KB) allows four waves a SIMD and
+// the large-list pass (about 130 KB) one workgroup a CU: their register
+// budgets follow, so that no variant spills vector registers to scratch
+// memory (a kernel with scratch makes the runtime set up scratch for the
+// hardware queue it runs on, milliseconds on a queue's first such launch).
+// The condensed layout's lookups need a few more registers: seven waves.
+template <uint32_t LCAP, bool C>
+constexpr int classify_waves_per_simd() {
+    return LCAP <= 256 ? (C ? 7 : 8) : LCAP <= 512 ? 7 : LCAP <= 1024 ? 4 : 1;
+}
+
 template <uint32_t LCAP, int WPB, int KPL, bool C>
 __global__ __launch_bounds__(WPB * 64)
-__attribute__((amdgpu_waves_per_eu(LCAP <= 256 ? 8 : 7)))
+__attribute__((amdgpu_waves_per_eu(classify_waves_per_simd<LCAP, C>())))
 void k_classify(QueryArgs a, int big, int cls) {
     __shared__ QueryLds<LCAP> L[WPB];
     const int wave = (int)uniform(threadIdx.x >> 6);

@@ -102,6 +102,9 @@ struct mc_server {
     std::mutex copy_mu;
     std::condition_variable copy_cv;
     uint64_t copy_turn = 0;      // order of the next batch to copy in
+    std::mutex launch_turn_mu;
+    std::condition_variable launch_cv;
+    uint64_t launch_turn = 0;    // order of the next batch to launch its kernels
     uint64_t next_order = 0;
     std::condition_variable cv_queue, cv_done, cv_slot;
     bool stopping = false;
@@ -157,26 +160,29 @@ struct mc_server {
     }
 
     // Stage, copy in, classify, copy out and hand back one batch (worker thread).
-    // A batch's turn on the copy stream: taken once, on every path (a batch
-    // that fails before its copy still passes the turn on).
-    struct CopyTurn {
-        mc_server& srv;
+    // A batch's turn in one of the server's admission-ordered sequences (the
+    // copies in, the launches): taken once, on every path (a batch that fails
+    // early still passes its turns on).
+    struct Turn {
+        std::mutex& mu;
+        std::condition_variable& cv;
+        uint64_t& next;
         uint64_t order;
         bool passed = false;
         void wait() {
-            std::unique_lock<std::mutex> lk(srv.copy_mu);
-            srv.copy_cv.wait(lk, [&] { return srv.copy_turn == order; });
+            std::unique_lock<std::mutex> lk(mu);
+            cv.wait(lk, [&] { return next == order; });
         }
         void pass() {
             if (passed) return;
             passed = true;
             {
-                std::lock_guard<std::mutex> lk(srv.copy_mu);
-                srv.copy_turn += 1;
+                std::lock_guard<std::mutex> lk(mu);
+                next += 1;
             }
-            srv.copy_cv.notify_all();
+            cv.notify_all();
         }
-        ~CopyTurn() {
+        ~Turn() {
             if (!passed) {
                 wait();
                 pass();
@@ -186,12 +192,16 @@ struct mc_server {
 
     // A batch is classified in chunks of at least kChunkRecords records (at
     // most kMaxChunks of them): the copy of chunk c + 1 overlaps the
-    // classification of chunk c, and the labels of chunk c come back while
-    // later chunks are classified. The reads keep their offsets: the
-    // classification's reads pointer is the device buffer shifted by the
-    // batch's first offset, so the caller's offsets are copied unchanged.
+    // classification of chunk c. Batches copy in, and launch their kernels,
+    // in admission order (an older batch's kernels are queued before a
+    // younger one's, so it is not slowed down by batches that came after
+    // it); their kernels and the copies back overlap on the slots' streams.
+    // The reads keep their offsets: the classification's reads pointer is
+    // the device buffer shifted by the batch's first offset, so the caller's
+    // offsets are copied unchanged.
     int process(Slot& s, Job& j) {
-        CopyTurn turn{*this, j.order};
+        Turn turn{copy_mu, copy_cv, copy_turn, j.order};
+        Turn launch{launch_turn_mu, launch_cv, launch_turn, j.order};
         const uint64_t per = j.opts.paired ? 2ull : 1ull;
         const uint64_t seg = per * j.n;   // offsets - 1
         const uint64_t base = j.offsets[0];
@@ -226,29 +236,35 @@ struct mc_server {
         }
         turn.pass();
         if (e != hipSuccess) return MC_ERR_HIP;
+        launch.wait();
         const char* reads = s.d_buf - base;   // reads + offsets[i] lies in the buffer
         const uint64_t* d_off = reinterpret_cast<const uint64_t*>(s.d_buf + off_offsets);
         uint32_t* d_lab = reinterpret_cast<uint32_t*>(s.d_buf + off_labels);
         mc_tophit* d_top = j.out_top ? reinterpret_cast<mc_tophit*>(s.d_buf + off_top) : nullptr;
         for (uint32_t c = 0; c < n_chunks; ++c) {
             const uint64_t r0 = c * chunk, r1 = std::min<uint64_t>(j.n, r0 + chunk);
-            if (hipStreamWaitEvent(s.stream, s.copied[c], 0) != hipSuccess) return MC_ERR_HIP;
-            {
-                std::lock_guard<std::mutex> lk(launch_mu);
-                rc = mc_classify_ex(db, reads, d_off + per * r0, (uint32_t)(r1 - r0), &j.opts,
-                                    d_lab + r0, d_top ? d_top + r0 * j.opts.top_m : nullptr,
-                                    s.stream);
-            }
+            // the worker waits for the chunk's copy itself: a wait queued on
+            // the slot's stream would sit in a hardware queue that streams
+            // share (more streams than hardware queues) and hold up the work
+            // of other slots queued behind it until this batch's copy is done
+            if (hipEventSynchronize(s.copied[c]) != hipSuccess) return MC_ERR_HIP;
+            std::lock_guard<std::mutex> lk(launch_mu);
+            rc = mc_classify_ex(db, reads, d_off + per * r0, (uint32_t)(r1 - r0), &j.opts,
+                                d_lab + r0, d_top ? d_top + r0 * j.opts.top_m : nullptr,
+                                s.stream);
             if (rc != MC_OK) return rc;
-            e = hipMemcpyAsync(s.h_buf + off_labels + r0 * 4, d_lab + r0, (r1 - r0) * 4,
-                               hipMemcpyDeviceToHost, s.stream);
-            if (e == hipSuccess && d_top)
-                e = hipMemcpyAsync(s.h_buf + off_top + r0 * j.opts.top_m * sizeof(mc_tophit),
-                                   d_top + r0 * j.opts.top_m,
-                                   (r1 - r0) * j.opts.top_m * sizeof(mc_tophit),
-                                   hipMemcpyDeviceToHost, s.stream);
-            if (e != hipSuccess) return MC_ERR_HIP;
         }
+        launch.pass();
+        // the results come back once, after the last chunk: a copy to host
+        // memory can hold the calling thread until the stream reaches it
+        // (small copies are done by the host), which between chunks would
+        // hold back the launches of the next chunks
+        e = hipMemcpyAsync(s.h_buf + off_labels, d_lab, (uint64_t)j.n * 4, hipMemcpyDeviceToHost,
+                           s.stream);
+        if (e == hipSuccess && d_top)
+            e = hipMemcpyAsync(s.h_buf + off_top, d_top, top_bytes, hipMemcpyDeviceToHost,
+                               s.stream);
+        if (e != hipSuccess) return MC_ERR_HIP;
         if (hipStreamSynchronize(s.stream) != hipSuccess) return MC_ERR_HIP;
         std::memcpy(j.out_labels, s.h_buf + off_labels, (size_t)j.n * 4);
         if (j.out_top) std::memcpy(j.out_top, s.h_buf + off_top, top_bytes);
@@ -394,6 +410,10 @@ mc_server* mc_server_create(mc_db* db, const mc_server_opts* opts) {
             ok = ok && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
         ok = ok && mc_server::grow(sl, s->staging, initial) == MC_OK;
         sl.d_plan = sl.d_cap;
+        // the slot stream's query workspace, sized for a whole chunk: a
+        // batch that allocated it would wait milliseconds (and hold up the
+        // other slots' launches meanwhile)
+        ok = ok && sl.stream && mc::prepare_workspace(db, sl.stream, kChunkRecords) == MC_OK;
     }
     (void)hipSetDevice(prev);
     if (!ok) {
@@ -530,6 +550,7 @@ int mc_server_destroy(mc_server* srv) {
     (void)hipSetDevice(srv->device);
     for (auto& s : srv->slots) {
         if (s.stream) (void)hipStreamSynchronize(s.stream);
+        if (s.stream) (void)mc::release_workspace(srv->db, s.stream);
         (void)hipFree(s.d_buf);
         (void)hipHostFree(s.h_buf);
         if (s.stream) (void)hipStreamDestroy(s.stream);
