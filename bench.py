@@ -713,6 +713,9 @@ def large_leg(args, g, stream, torch, mc):
                                   "n_buckets", "table_bytes", "load_factor")},
         "query": {"features_per_read": q_feats / (4 * nk), "locations_per_read": q_locs / (4 * nk),
                   "probes_per_feature": q_probes / max(1, q_feats),
+                  "large_pass_records_per_launch":
+                      (st["q_large_records"] - st0["q_large_records"]) / 4,
+                  "hbm_pass_records_per_launch": (st["q_hbm_records"] - st0["q_hbm_records"]) / 4,
                   "classified_frac": float((kernel_labels != mc.MC_UNCLASSIFIED).mean())},
         "oracle_parity": parity,
         "condensed": condensed,
@@ -930,6 +933,8 @@ def main():
                                   "n_cap_candidates")},
         "query": {"features_per_read": q_feats / n, "locations_per_read": q_locs / n,
                   "probes_per_feature": q_probes / max(1, q_feats),
+                  "large_pass_records": st["q_large_records"],
+                  "hbm_pass_records": st["q_hbm_records"],
                   "classified_frac": float((gpu_labels != mc.MC_UNCLASSIFIED).mean())},
         "roofline": roofline,
         "condensed": condensed,

@@ -106,6 +106,10 @@ typedef struct mc_db_stats {
                                   all slots of the table                    */
     uint64_t condensed_bytes;  /* device bytes of the condensed layout (0 if
                                   none, see mc_db_condense)                 */
+    uint64_t q_large_records;  /* records classify handed to its large-list
+                                  pass (list over the launch's capacity)    */
+    uint64_t q_hbm_records;    /* records handed on to the HBM-list pass
+                                  (list over 16384 locations)               */
 } mc_db_stats;
 
 /* Text of the calling thread's last error ("" if none). Never NULL. */

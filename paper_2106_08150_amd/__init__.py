@@ -63,7 +63,8 @@ class DbStats(C.Structure):
         "n_targets", "n_windows", "n_pairs_inserted", "n_pairs_stored", "n_buckets",
         "table_bytes", "n_cap_candidates", "probe_sum", "n_rehash", "q_features",
         "q_locations", "q_probes", "n_features", "n_tombstones")] + [
-        ("load_factor", C.c_double), ("condensed_bytes", C.c_uint64)]
+        ("load_factor", C.c_double), ("condensed_bytes", C.c_uint64),
+        ("q_large_records", C.c_uint64), ("q_hbm_records", C.c_uint64)]
 
     def as_dict(self) -> dict:
         return {n: (float(getattr(self, n)) if t is C.c_double else int(getattr(self, n)))

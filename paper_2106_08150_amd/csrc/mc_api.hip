@@ -1219,6 +1219,8 @@ int mc_db_get_stats(mc_db* db, mc_db_stats* out) {
             out->q_features += q[c * kQsStride + kQsFeatures];
             out->q_locations += q[c * kQsStride + kQsLocations];
             out->q_probes += q[c * kQsStride + kQsProbes];
+            out->q_large_records += q[c * kQsStride + kQsLarge];
+            out->q_hbm_records += q[c * kQsStride + kQsHuge];
         }
     }
     out->n_targets = db->taxa.size();

@@ -166,7 +166,13 @@ struct RouteConfig {
     uint32_t max_windows[kMaxRoutes] = {0, 0, 0, 0};
 };
 
-enum QueryStat { kQsFeatures = 0, kQsLocations = 1, kQsProbes = 2, kNumQueryStats = 4 };
+// Totals kept by the classify passes: sketch elements looked up, locations
+// gathered, bucket lines read, and records handed on to the large-list pass
+// and to the HBM-list pass.
+enum QueryStat {
+    kQsFeatures = 0, kQsLocations = 1, kQsProbes = 2, kQsLarge = 3, kQsHuge = 4,
+    kNumQueryStats = 5
+};
 // The query statistics are kept as kQsCopies partial totals, each on its own
 // 128-byte line: a wave adds its counts to copy (wave id mod kQsCopies), so
 // the waves of a launch do not all queue their atomics on one line (at about

@@ -421,7 +421,7 @@ __device__ __forceinline__ void stage_pair(Word* W, const WinRef& A, const WinRe
 }
 
 struct WaveStats {
-    uint32_t features = 0, locations = 0, probes = 0;
+    uint32_t features = 0, locations = 0, probes = 0, passed_on = 0;
 };
 
 template <uint32_t LCAP, int KPL, bool C>
@@ -491,6 +491,7 @@ __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>
             const uint32_t qi = atomicAdd(&counters[big ? kQHuge : kQOverflow], 1u);
             MC_COLD(queue)[(big ? MC_COLD(n_records) : 0u) + qi] = rec;
         }
+        ws.passed_on += 1;
         return;
     }
     wave_lds_sync();
@@ -657,6 +658,8 @@ void k_classify(QueryArgs a, int big, int cls) {
         if (ws.features) atomicAdd(&q[kQsFeatures], (unsigned long long)ws.features);
         if (ws.locations) atomicAdd(&q[kQsLocations], (unsigned long long)ws.locations);
         if (ws.probes) atomicAdd(&q[kQsProbes], (unsigned long long)ws.probes);
+        if (ws.passed_on)
+            atomicAdd(&q[big ? kQsHuge : kQsLarge], (unsigned long long)ws.passed_on);
     }
 }
 
@@ -1076,14 +1079,26 @@ __global__ __launch_bounds__(256) void k_route_scatter(QueryArgs a, RouteConfig 
     }
 }
 
+// Workgroups of the large-list pass: one a CU at most (its list takes most of
+// a CU's LDS), one per 4,096 records of the launch, 8 to 512. A workgroup of
+// this pass can start only on a CU that every other kernel's groups have
+// left, so a pass launched next to other batches' kernels (a served mix)
+// drains the CUs it is given; the records it takes are rare (none at all in
+// the configured workloads, whose lists stay within the fast path's
+// capacity), so it is kept small.
+inline unsigned large_pass_groups(uint32_t n_records) {
+    return (unsigned)std::min<uint32_t>(512u, std::max<uint32_t>(8u, n_records / 4096u));
+}
+
 template <bool C>
 void launch_large_c(const QueryArgs& a, hipStream_t st) {
+    const dim3 grid(large_pass_groups(a.n_records));
     if (a.S <= 64)
-        hipLaunchKernelGGL((k_classify<kListLarge, 1, 1, C>), dim3(512), dim3(64), 0, st, a, 1, -1);
+        hipLaunchKernelGGL((k_classify<kListLarge, 1, 1, C>), grid, dim3(64), 0, st, a, 1, -1);
     else if (a.S <= 128)
-        hipLaunchKernelGGL((k_classify<kListLarge, 1, 2, C>), dim3(512), dim3(64), 0, st, a, 1, -1);
+        hipLaunchKernelGGL((k_classify<kListLarge, 1, 2, C>), grid, dim3(64), 0, st, a, 1, -1);
     else
-        hipLaunchKernelGGL((k_classify<kListLarge, 1, 4, C>), dim3(512), dim3(64), 0, st, a, 1, -1);
+        hipLaunchKernelGGL((k_classify<kListLarge, 1, 4, C>), grid, dim3(64), 0, st, a, 1, -1);
 }
 
 }  // namespace
