@@ -159,12 +159,24 @@ __device__ __forceinline__ uint64_t next_bucket(uint64_t b, uint64_t nb) {
 
 // ------------------------------------------------------------- encoding --
 // 16 bases packed as 2-bit codes (first base in bits 31..30) plus an invalid
-// mask with the same layout (0b11 in the two bits of every invalid base).
-// A=0 C=1 G=2 T=3, case-insensitive; every other byte is invalid.
+// mask with the same layout (0b11 in the two bits of every invalid base), and
+// the complements of the same bases in the opposite order (base j of the word
+// in bits 2j+1..2j), from which reverse complements are read by a funnel
+// shift. A=0 C=1 G=2 T=3, case-insensitive; every other byte is invalid.
 struct Word {
     uint32_t code;
     uint32_t mask;
+    uint32_t rc;
+    uint32_t pad;
 };
+
+// The complement word of a code word: every 2-bit group complemented and the
+// groups' order reversed (bit reversal, then the two bits of each group
+// swapped back).
+__device__ __forceinline__ uint32_t rc_word(uint32_t code) {
+    const uint32_t r = __builtin_bitreverse32(~code);
+    return ((r >> 1) & 0x55555555u) | ((r & 0x55555555u) << 1);
+}
 
 // Four 2-bit fields held in bits 8i..8i+1 (i = byte) packed into one byte,
 // byte 0's field in bits 7..6: reverse the bytes, then fold pairs twice.
@@ -179,10 +191,15 @@ __device__ __forceinline__ uint32_t pack_fields(uint32_t v) {
 // ((x >> 1) ^ (x >> 2)) & 3 maps A/a C/c G/g T/t to 0 1 2 3; a byte is a base
 // iff it equals "acgt"[code] once lower-cased (v_perm looks the letter up).
 // c8: the 4 codes (those of invalid bases are arbitrary), first base in bits
-// 7..6; m8: 0b11 in the positions of invalid bases. Returns whether a byte
-// inside the sequence is not a base.
-__device__ __forceinline__ bool encode4(uint32_t x, uint32_t ok, uint32_t& c8, uint32_t& m8) {
+// 7..6; m8: 0b11 in the positions of invalid bases; r8: their complements,
+// first base in bits 1..0. Returns whether a byte inside the sequence is not
+// a base.
+__device__ __forceinline__ bool encode4(uint32_t x, uint32_t ok, uint32_t& c8, uint32_t& m8,
+                                        uint32_t& r8) {
     const uint32_t c = ((x >> 1) ^ (x >> 2)) & 0x03030303u;
+    const uint32_t cc = c ^ 0x03030303u;
+    const uint32_t t2 = cc | (cc >> 6);
+    r8 = (t2 | (t2 >> 12)) & 0xFFu;
     const uint32_t expect = __builtin_amdgcn_perm(0u, 0x74676361u, c);
     const uint32_t diff = (x | 0x20202020u) ^ expect;           // zero byte: a base
     const uint32_t t = (diff & 0x7F7F7F7Fu) + 0x7F7F7F7Fu;
@@ -205,57 +222,61 @@ __device__ __forceinline__ uint32_t inside_bytes(uint32_t lo, uint32_t hi) {
 // overlap is not read at all. `bad` is set if a byte inside [vlo, vhi) is not
 // a base.
 __device__ __forceinline__ Word load_word(uintptr_t a, uintptr_t vlo, uintptr_t vhi, bool& bad) {
-    if (a + 16 <= vlo || a >= vhi) return Word{0u, 0xFFFFFFFFu};
+    if (a + 16 <= vlo || a >= vhi) return Word{0u, 0xFFFFFFFFu, 0u, 0u};
     // the address is global memory; saying so gives a global (not flat) load
     typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
     const u32x4 v = *reinterpret_cast<const __attribute__((address_space(1))) u32x4*>(a);
     // bytes [lo, hi) of the word lie inside [vlo, vhi)
     const uint32_t lo = vlo > a ? (uint32_t)(vlo - a) : 0u;
     const uint32_t hi = vhi - a < 16 ? (uint32_t)(vhi - a) : 16u;
-    uint32_t c[4], m[4];
+    uint32_t c[4], m[4], r[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const uint32_t dlo = lo > 4u * i ? min(lo - 4u * i, 4u) : 0u;
         const uint32_t dhi = hi > 4u * i ? min(hi - 4u * i, 4u) : 0u;
         const uint32_t ok = dlo < dhi ? inside_bytes(dlo, dhi) : 0u;
-        bad |= encode4(i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w, ok, c[i], m[i]);
+        bad |= encode4(i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w, ok, c[i], m[i], r[i]);
     }
     Word w;
     w.code = (c[0] << 24) | (c[1] << 16) | (c[2] << 8) | c[3];
     w.mask = (m[0] << 24) | (m[1] << 16) | (m[2] << 8) | m[3];
+    w.rc = rc_word(w.code);
+    w.pad = 0u;
     return w;
 }
 
 // Stage one dword (4 bases) of a word covering [A0, ...), A0 16-byte aligned:
 // dword d of word d >> 2 goes to byte 3 - (d & 3) of that word's code and mask
-// (first base in the top byte). Bytes outside [vlo, vhi) count as invalid; a
+// (first base in the top byte) and to byte d & 3 of its complement word.
+// Bytes outside [vlo, vhi) count as invalid; a
 // dword that does not overlap them is not read. Aligned 4-byte loads never
 // cross a page. Returns whether a byte inside [vlo, vhi) is not a base.
 __device__ __forceinline__ bool stage_dword(Word* W, uintptr_t A0, uint32_t d, uintptr_t vlo,
                                             uintptr_t vhi) {
     const uintptr_t a = A0 + 4u * d;
-    uint32_t c8 = 0u, m8 = 0xFFu;
+    uint32_t c8 = 0u, m8 = 0xFFu, r8 = 0u;
     bool bad = false;
     if (a + 4 > vlo && a < vhi) {
         const uint32_t x = *reinterpret_cast<const __attribute__((address_space(1))) uint32_t*>(a);
         const uint32_t lo = vlo > a ? (uint32_t)(vlo - a) : 0u;
         const uint32_t hi = vhi - a < 4 ? (uint32_t)(vhi - a) : 4u;
-        bad = encode4(x, inside_bytes(lo, hi), c8, m8);
+        bad = encode4(x, inside_bytes(lo, hi), c8, m8, r8);
     }
     uint8_t* w = reinterpret_cast<uint8_t*>(W + (d >> 2));
     w[3 - (d & 3u)] = (uint8_t)c8;
     w[7 - (d & 3u)] = (uint8_t)m8;
+    w[8 + (d & 3u)] = (uint8_t)r8;
     return bad;
 }
 
-// Canonical k-mer (k <= 16) starting o bases into word pair (a, b): the
-// forward k-mer by a funnel shift, the reverse complement by complementing,
-// aligning to the top and reversing the 2-bit groups. Without kCheck the
-// caller knows every base of the k-mer is valid; with it, returns false if
-// one is not.
+// Canonical k-mer (k <= 16) starting o bases into word pair (a, b), both
+// strands by a funnel shift: the forward k-mer from the code words, the
+// reverse complement (its first base the complement of the k-mer's last)
+// from the complement words, kmask = 4^k - 1. Without kCheck the caller knows
+// every base of the k-mer is valid; with it, returns false if one is not.
 template <bool kCheck>
 __device__ __forceinline__ bool kmer_of(const Word& a, const Word& b, uint32_t o, uint32_t k,
-                                        uint32_t& canon) {
+                                        uint32_t kmask, uint32_t& canon) {
     // the top 32 bits of (a:b) << 2o: a funnel shift for o > 0, a itself for 0
     const uint32_t top = o ? __builtin_amdgcn_alignbit(a.code, b.code, 32u - 2u * o) : a.code;
     const uint32_t fwd = top >> (32 - 2 * k);
@@ -264,17 +285,20 @@ __device__ __forceinline__ bool kmer_of(const Word& a, const Word& b, uint32_t o
         const uint32_t mtop = o ? __builtin_amdgcn_alignbit(a.mask, b.mask, 32u - 2u * o) : a.mask;
         bad = (mtop >> (32 - 2 * k)) != 0u;
     }
-    uint32_t r = __builtin_bitreverse32((~fwd) << (32 - 2 * k));
-    r = ((r >> 1) & 0x55555555u) | ((r & 0x55555555u) << 1);
+    const uint32_t r = __builtin_amdgcn_alignbit(b.rc, a.rc, 2u * o) & kmask;
     canon = fwd < r ? fwd : r;
     return !bad;
+}
+
+__device__ __forceinline__ uint32_t kmer_mask(uint32_t k) {
+    return k >= 16 ? 0xFFFFFFFFu : (1u << (2 * k)) - 1u;
 }
 
 // Canonical k-mer starting x bases after the first staged word (k <= 16).
 // Returns false if any of its bases is invalid.
 __device__ __forceinline__ bool kmer_at(const Word* W, uint32_t x, uint32_t k, uint32_t& canon) {
     const uint32_t q = x >> 4, o = x & 15u;
-    return kmer_of<true>(W[q], W[q + 1], o, k, canon);
+    return kmer_of<true>(W[q], W[q + 1], o, k, kmer_mask(k), canon);
 }
 
 // ------------------------------------------------------- bitonic in regs --
@@ -447,6 +471,7 @@ __device__ __forceinline__ bool window_keys_t(const Word* W, uint32_t x0, uint32
     const uint32_t x = x0 + (uint32_t)lane;
     const Word* Wq = W + (x >> 4);
     const uint32_t o = x & 15u;
+    const uint32_t kmask = kmer_mask(k);
     bool top = false;
 #pragma unroll
     for (int r = 0; r < KPL; ++r) {
@@ -454,7 +479,7 @@ __device__ __forceinline__ bool window_keys_t(const Word* W, uint32_t x0, uint32
         key[r] = 0xFFFFFFFFu;
         if (i < nk) {
             uint32_t c;
-            if (kmer_of<kCheck>(Wq[4 * r], Wq[4 * r + 1], o, k, c)) {
+            if (kmer_of<kCheck>(Wq[4 * r], Wq[4 * r + 1], o, k, kmask, c)) {
                 uint32_t h = h1(c);
                 key[r] = h;
                 top |= (h == 0xFFFFFFFFu);
