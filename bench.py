@@ -53,8 +53,11 @@ CEIL_COPY_GBS = 5155.89          # streaming copy, read + write bytes / s (GB/s)
 K, WINDOW, SKETCH, CAP = 16, 128, 16, 254
 
 
+T_START = time.perf_counter()
+
+
 def log(msg: str) -> None:
-    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+    print(f"[bench {time.perf_counter() - T_START:6.1f}s] {msg}", file=sys.stderr, flush=True)
 
 
 def parse():
@@ -94,15 +97,15 @@ def parse():
     ap.add_argument("--large-shape", type=str, default="auto",
                     help="launch shape of the large leg: 'auto' (mc_db_autotune on the first 2M "
                          "reads) or list capacity, waves per workgroup, largest grid")
-    ap.add_argument("--served-parity", type=int, default=0,
+    ap.add_argument("--served-parity", type=int, default=2000,
                     help="records of the served trace checked against the (feature-filtered) "
                          "oracle on the database after all its on-demand additions, plus a "
-                         "table slice (0 = skip: the oracle's scan of 10 Gbp takes about a "
+                         "table slice (0 = skip; the oracle's scan of 10 Gbp takes about a "
                          "minute of host time)")
-    ap.add_argument("--large-parity", type=int, default=0,
+    ap.add_argument("--large-parity", type=int, default=2000,
                     help="reads of the large stream checked against the (feature-filtered) "
-                         "oracle, plus a table slice (0 = skip: the oracle's scan of 30 Gbp "
-                         "takes minutes of host time)")
+                         "oracle, plus a table slice (0 = skip; the oracle's scan of 30 Gbp "
+                         "takes about three minutes of host time)")
     ap.add_argument("--launch-shape", type=str, default="256,4,16384",
                     help="classification launch shape of the main leg: list capacity, waves "
                          "per workgroup, largest grid (the shape mc_db_autotune picks on this "
@@ -256,7 +259,7 @@ def plain_run(torch, mc, db, batches, adds, arrivals):
     return labels, np.array(lat), time.perf_counter() - t0
 
 
-def served_run(torch, mc, db, batches, adds, arrivals, staging, slots=4):
+def served_run(torch, mc, db, batches, adds, arrivals, staging, slots=4, stage_log=None):
     """The served loop on the same arrivals (None: back to back): a feeder
     thread submits each batch at its arrival time; latency = arrival ->
     labels in host memory."""
@@ -282,20 +285,33 @@ def served_run(torch, mc, db, batches, adds, arrivals, staging, slots=4):
 
     th = threading.Thread(target=feeder)
     th.start()
-    labels, lat = [], []
+    labels, lat, stages = [], [], []
     for i in range(nb):
         while tickets[i] is None:
             time.sleep(0.0002)
-        lab, _, ms = srv.wait(tickets[i])
+        lab, _, tm = srv.wait_times(tickets[i])
         labels.append(lab.copy())
         # from arrival, as for plain launches: the server's submit -> labels
         # time plus the time from arrival until submit returned (an upper
         # bound: the submit call itself counts twice)
-        lat.append(ms + late[i])
+        lat.append(tm["total_ms"] + late[i])
+        tm["submit_late_ms"] = late[i]
+        tm["records"] = int(batches[i][1].size - 1)
+        stages.append(tm)
     th.join()
     span = time.perf_counter() - t0
     srv.close()
+    if stage_log is not None:
+        stage_log.extend(stages)
     return labels, np.array(lat), span
+
+
+def slowest_stages(stages, lat, n=3):
+    """Stage split of the n slowest batches (ms), slowest first."""
+    order = np.argsort(lat)[::-1][:n]
+    keys = ("records", "submit_late_ms", "admit_ms", "copy_ms", "launch_ms", "finish_ms")
+    return [{k: (round(stages[i][k], 3) if k != "records" else stages[i][k]) for k in keys}
+            for i in order]
 
 
 def summary(lat, span, n_reads):
@@ -418,9 +434,9 @@ def served_leg(args, g, gtext, torch, mc, synth):
         db.close()
         return out
 
-    def served(arrivals):
+    def served(arrivals, stage_log=None):
         db = fresh_db()
-        out = served_run(torch, mc, db, batches, adds, arrivals, staging)
+        out = served_run(torch, mc, db, batches, adds, arrivals, staging, stage_log=stage_log)
         db.close()
         return out
 
@@ -432,12 +448,18 @@ def served_leg(args, g, gtext, torch, mc, synth):
         rate = load * plain_tput / float(sizes.mean())
         arrivals = unit_t / rate
         p_lab, p_lat, p_span = plain(arrivals)
-        s_lab, s_lat, s_span = served(arrivals)
+        stages = []
+        s_lab, s_lat, s_span = served(arrivals, stages)
         same = all(np.array_equal(a, b) for a, b in zip(s_lab, p_lab))
         same_all &= same
+        slow_plain = np.argsort(p_lat)[::-1][:3]
         results.append({"offered_load": load, "batches_per_s": rate,
                         "served": summary(s_lat, s_span, reads.n_records),
                         "plain": summary(p_lat, p_span, reads.n_records),
+                        "served_slowest": slowest_stages(stages, s_lat),
+                        "plain_slowest": [{"records": int(batches[i][1].size - 1),
+                                           "ms": round(float(p_lat[i]), 3)}
+                                          for i in slow_plain],
                         "labels_identical": bool(same)})
         log(f"load {load:.2f}: served p50 {pct(s_lat, 50):.2f} p99 {pct(s_lat, 99):.2f} ms, "
             f"plain p50 {pct(p_lat, 50):.2f} p99 {pct(p_lat, 99):.2f} ms, identical {same}")

@@ -438,6 +438,23 @@ int mc_server_add_targets(mc_server* srv, const char* genomes, const uint64_t* l
  * second wait on it returns MC_ERR_INVALID_ARG at once. */
 int mc_server_wait(mc_server* srv, uint64_t ticket, double* latency_ms);
 
+/* Where a batch's latency went, from the host's clock (milliseconds). The
+ * stages follow one another, so they add up to total_ms. For an addition only
+ * total_ms is set; for a failed batch only total_ms. */
+typedef struct mc_batch_times {
+    double admit_ms;    /* submit -> given a slot (waiting for a free slot and memory
+                           budget, or for an earlier addition)                       */
+    double copy_ms;     /* -> its last read chunk on the device (earlier batches'
+                           copies go first: one copy stream, admission order)        */
+    double launch_ms;   /* -> its last chunk's kernels queued (earlier batches queue
+                           theirs first)                                             */
+    double finish_ms;   /* -> results in the caller's buffers (kernels, copy back)   */
+    double total_ms;    /* submit -> results: the latency mc_server_wait reports     */
+} mc_batch_times;
+
+/* mc_server_wait with the batch's latency split by stage (times may be NULL). */
+int mc_server_wait_times(mc_server* srv, uint64_t ticket, mc_batch_times* times);
+
 int mc_server_get_stats(mc_server* srv, mc_server_stats* out);
 
 /* Finish every queued job, stop the dispatcher and free the server's

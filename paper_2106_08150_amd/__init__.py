@@ -38,6 +38,7 @@ EXPORTS = [
     "mc_db_query_status", "mc_db_get_stats", "mc_db_dump", "mc_db_sketch",
     "mc_db_set_profiling", "mc_db_kernel_times",
     "mc_server_create", "mc_server_submit", "mc_server_add_targets", "mc_server_wait",
+    "mc_server_wait_times",
     "mc_server_get_stats", "mc_server_destroy",
     "mc_db_set_launch_config", "mc_db_get_launch_config", "mc_db_autotune",
     "mc_classify_graph_create", "mc_classify_graph_launch", "mc_classify_graph_destroy",
@@ -95,6 +96,14 @@ class RouteConfig(C.Structure):
 class ServerOpts(C.Structure):
     _fields_ = [("slots", C.c_uint32), ("memory_budget", C.c_uint64),
                 ("staging_bytes", C.c_uint64)]
+
+
+class BatchTimes(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("admit_ms", "copy_ms", "launch_ms", "finish_ms",
+                                          "total_ms")]
+
+    def as_dict(self) -> dict:
+        return {n: getattr(self, n) for n, _ in self._fields_}
 
 
 class ServerStats(C.Structure):
@@ -172,6 +181,8 @@ def lib():
         L.mc_server_add_targets.argtypes = [vp, vp, vp, vp, u32, vp, u32, C.POINTER(u64)]
         L.mc_server_wait.restype = i32
         L.mc_server_wait.argtypes = [vp, u64, C.POINTER(C.c_double)]
+        L.mc_server_wait_times.restype = i32
+        L.mc_server_wait_times.argtypes = [vp, u64, C.POINTER(BatchTimes)]
         L.mc_server_get_stats.restype = i32
         L.mc_server_get_stats.argtypes = [vp, C.POINTER(ServerStats)]
         L.mc_server_destroy.restype, L.mc_server_destroy.argtypes = i32, [vp]
@@ -543,14 +554,20 @@ class Server:
         return t.value
 
     def wait(self, ticket: int):
-        ms = C.c_double(0)
-        rc = lib().mc_server_wait(self.h, ticket, C.byref(ms))
+        """(labels, top hits, latency ms) of a batch; (None, None, ms) for an addition."""
+        labels, top, times = self.wait_times(ticket)
+        return labels, top, times["total_ms"]
+
+    def wait_times(self, ticket: int):
+        """As wait, with the latency split by stage (mc_batch_times) as a dict."""
+        t = BatchTimes()
+        rc = lib().mc_server_wait_times(self.h, ticket, C.byref(t))
         job = self._jobs.pop(ticket, None)
         _check(rc)
         if job is None or isinstance(job[0], str):   # an addition
-            return None, None, ms.value
+            return None, None, t.as_dict()
         _, _, labels, top, n = job
-        return labels[:n], (top[:n] if top is not None else None), ms.value
+        return labels[:n], (top[:n] if top is not None else None), t.as_dict()
 
     def stats(self) -> dict:
         return mc_server_get_stats(self.h)

@@ -774,13 +774,10 @@ int check_classify(mc_db* db, const char* reads, const uint64_t* offsets, uint32
     return MC_OK;
 }
 
-// Queue the classification launches on st with workspace w (no allocation, no
-// synchronisation: usable under stream capture).
-int classify_launch(mc_db* db, const char* reads, const uint64_t* offsets, uint32_t n_records,
-                    const mc_query_opts& opts, uint32_t* out_labels, mc_tophit* out_top,
-                    Workspace& w, const LaunchPlan& plan, hipStream_t st, bool profile) {
-    static_assert(kQOverflow == 0 && kQHuge == 1, "the per-launch queue counters lead");
-    HIP_TRY(launch_fill_u32(w.counters, 2, 0u, st));
+// Kernel arguments of a classification of n_records records with workspace w.
+QueryArgs query_args(mc_db* db, const char* reads, const uint64_t* offsets, uint32_t n_records,
+                     const mc_query_opts& opts, uint32_t* out_labels, mc_tophit* out_top,
+                     Workspace& w) {
     QueryArgs a{};
     if (db->cidx) {   // condensed layout
         a.table = reinterpret_cast<const unsigned long long*>(db->cidx);
@@ -795,6 +792,7 @@ int classify_launch(mc_db* db, const char* reads, const uint64_t* offsets, uint3
     a.n_records = n_records;
     a.paired = opts.paired;
     a.k = db->k; a.w = db->w; a.S = db->S; a.s = db->s;
+    a.divS = make_divu32(db->S);
     a.top_m = opts.top_m;
     a.min_hits = opts.min_hits;
     a.hit_diff = opts.hit_diff;
@@ -811,6 +809,13 @@ int classify_launch(mc_db* db, const char* reads, const uint64_t* offsets, uint3
     a.huge_groups = w.huge_groups;
     a.route_queue = w.queue + 2 * w.queue_cap;
     a.route_meta = w.route_meta;
+    return a;
+}
+
+// The fast pass of a classification: one launch, or the routing launches and
+// one launch per size class.
+int launch_fast_phase(mc_db* db, const QueryArgs& a, Workspace& w, const LaunchPlan& plan,
+                      hipStream_t st, bool profile) {
     auto fast = [&]() -> hipError_t {
         if (plan.route.n <= 1) return launch_classify_fast(a, plan.shape[0], st);
         hipError_t e = launch_fill_u32(w.route_meta, kRouteMetaWords, 0u, st);
@@ -824,7 +829,19 @@ int classify_launch(mc_db* db, const char* reads, const uint64_t* offsets, uint3
     } else {
         HIP_TRY(fast());
     }
-    HIP_TRY(launch_classify_large(a, st));
+    return MC_OK;
+}
+
+// Queue the classification launches on st with workspace w (no allocation, no
+// synchronisation: usable under stream capture).
+int classify_launch(mc_db* db, const char* reads, const uint64_t* offsets, uint32_t n_records,
+                    const mc_query_opts& opts, uint32_t* out_labels, mc_tophit* out_top,
+                    Workspace& w, const LaunchPlan& plan, hipStream_t st, bool profile) {
+    static_assert(kQOverflow == 0 && kQHuge == 1, "the per-launch queue counters lead");
+    HIP_TRY(launch_fill_u32(w.counters, 2, 0u, st));
+    const QueryArgs a = query_args(db, reads, offsets, n_records, opts, out_labels, out_top, w);
+    if (int rc = launch_fast_phase(db, a, w, plan, st, profile)) return rc;
+    HIP_TRY(launch_classify_large(a, st, 0));
     HIP_TRY(launch_classify_huge(a, st));
     return MC_OK;
 }
@@ -952,6 +969,35 @@ int classify_into(struct ::mc_db* db, const char* reads, const uint64_t* offsets
     return classify_launch(db, reads, offsets, n_records, *opts, out_labels, out_top, w, db->plan,
                            st, false);
 }
+int served_classify(struct ::mc_db* db, int phase, const char* reads, const uint64_t* offsets,
+                    uint32_t r0, uint32_t r1, const mc_query_opts& opts, uint32_t* out_labels,
+                    mc_tophit* out_top, uint32_t* counters, uint32_t n_queued, hipStream_t st) {
+    if (phase == 0) {
+        if (int rc = check_classify(db, reads, offsets, r1 - r0, &opts, out_labels)) return rc;
+    }
+    if (r1 <= r0) return MC_OK;
+    DeviceGuard dg(db->device);
+    auto it = db->ws.find(st);
+    if (it == db->ws.end() || it->second.queue_cap < r1)
+        return fail(MC_ERR_STATE, "the stream's workspace holds fewer than %u records", r1);
+    Workspace& w = it->second;
+    const uint64_t per = opts.paired ? 2 : 1;
+    QueryArgs a = query_args(db, reads, offsets + per * r0, r1 - r0, opts, out_labels + r0,
+                             out_top ? out_top + (uint64_t)r0 * opts.top_m : nullptr, w);
+    a.counters = counters;
+    a.queue = w.queue + 2ull * r0;   // ids [0, 2 (r1 - r0)) of the range's records
+    if (phase == 0) {
+        HIP_TRY(launch_fill_u32(counters, kNumQueryCounters, 0u, st));
+        return launch_fast_phase(db, a, w, db->plan, st, db->profiling);
+    }
+    if (phase == 1) {
+        HIP_TRY(launch_classify_large(a, st, n_queued));
+        return MC_OK;
+    }
+    HIP_TRY(launch_classify_huge(a, st));
+    return MC_OK;
+}
+
 int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
 }  // namespace mc
 
@@ -1312,8 +1358,7 @@ int mc_db_condense(mc_db* db, int release_table) {
         if (dev_alloc(&cnt, 1) == MC_OK) {
             unsigned long long n = 0;
             if (launch_fill_u64(cnt, 1, 0ull, nullptr) == hipSuccess &&
-                launch_condense_dump(db->cidx, db->nbc, db->cval, 0u, 0xFFFFFFFFu, nullptr, 0,
-                                     cnt, nullptr) == hipSuccess &&
+                launch_condense_pairs(db->cidx, db->nbc, cnt, nullptr) == hipSuccess &&
                 hipMemcpy(&n, cnt, 8, hipMemcpyDeviceToHost) == hipSuccess)
                 db->c_pairs = n;
             (void)dev_free(cnt);

@@ -285,6 +285,23 @@ __global__ __launch_bounds__(256) void k_condense_dump(const unsigned int* idx, 
     }
 }
 
+// Pairs held by the condensed layout: the sum of its entries' counts, one
+// atomic per wave.
+__global__ __launch_bounds__(256) void k_condense_pairs(const unsigned int* idx, uint64_t nbc,
+                                                        unsigned long long* total) {
+    const uint64_t n = nbc * kCondEntries;
+    unsigned long long sum = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        sum += reinterpret_cast<const uint4*>(idx)[i].y;
+#pragma unroll
+    for (int m = 1; m < kWave; m <<= 1) {
+        const uint32_t lo = shfl_xor((uint32_t)sum, m), hi = shfl_xor((uint32_t)(sum >> 32), m);
+        sum += ((unsigned long long)hi << 32) | lo;
+    }
+    if (lane_id() == 0 && sum) atomicAdd(total, sum);
+}
+
 inline unsigned grid_cap(uint64_t items, unsigned max_blocks) {
     return (unsigned)(items < 1 ? 1 : items > max_blocks ? max_blocks : items);
 }
@@ -306,6 +323,15 @@ hipError_t launch_condense_scan(const CondArgs& c, unsigned long long* total_fea
 hipError_t launch_condense_write(const CondArgs& c, hipStream_t st) {
     hipLaunchKernelGGL(k_condense_write, dim3(grid_cap(c.n_slices, 8192)), dim3(kCondThreads), 0,
                        st, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_condense_pairs(const unsigned int* idx, uint64_t nbc, unsigned long long* total,
+                                 hipStream_t st) {
+    if (nbc == 0) return hipSuccess;
+    const uint64_t n = nbc * kCondEntries;
+    hipLaunchKernelGGL(k_condense_pairs, dim3(grid_cap((n + 255) / 256, 16384)), dim3(256), 0, st,
+                       idx, nbc, total);
     return hipGetLastError();
 }
 

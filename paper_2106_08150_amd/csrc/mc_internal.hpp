@@ -126,6 +126,25 @@ constexpr uint64_t kHugeRegionBytes =
     4ull * (kHugeFeats + kHugeLocs + 2ull * kHugeSlots) + 8ull * kHugeTargets + 4ull * kHugeTargets;
 constexpr uint64_t kHugeBytes = kHugeRegionBytes * kHugeGroups;
 
+// Unsigned 32-bit division by a divisor fixed per database (the window
+// stride) as a multiply-high and two shifts: with L = ceil(log2 d) and
+// m = floor(2^32 (2^L - d) / d) + 1, floor(n / d) = (t + ((n - t) >> min(L, 1)))
+// >> max(L - 1, 0) where t = floor(m n / 2^32), for every 32-bit n (Granlund
+// and Montgomery, PLDI 1994). Uniform operands keep it in scalar registers.
+struct DivU32 {
+    uint32_t m = 1, sh1 = 0, sh2 = 0;
+};
+
+inline DivU32 make_divu32(uint32_t d) {
+    uint32_t L = 0;
+    while ((1ull << L) < d) ++L;
+    DivU32 r;
+    r.m = (uint32_t)(((1ull << 32) * ((1ull << L) - d)) / d + 1);
+    r.sh1 = L ? 1u : 0u;
+    r.sh2 = L ? L - 1u : 0u;
+    return r;
+}
+
 struct QueryArgs {
     const unsigned long long* table;
     uint64_t nb;
@@ -134,6 +153,7 @@ struct QueryArgs {
     uint32_t n_records;
     uint32_t paired;
     uint32_t k, w, S, s;
+    DivU32 divS;                  // division by S
     uint32_t top_m, min_hits, hit_diff, insert_size;
     const uint32_t* target_taxon;
     const uint32_t* parents;
@@ -253,7 +273,8 @@ bool classify_config_valid(const ClassifyConfig& c);
 // Fast path (one wave per record, small LDS list) and the large-list pass
 // over the records the fast path queued.
 hipError_t launch_classify_fast(const QueryArgs& a, const ClassifyConfig& c, hipStream_t st);
-hipError_t launch_classify_large(const QueryArgs& a, hipStream_t st);
+// groups: workgroups of the large-list pass (0: sized by the launch's records).
+hipError_t launch_classify_large(const QueryArgs& a, hipStream_t st, uint32_t groups);
 // Routing: the records' size classes into route_queue / route_meta, then one
 // fast-path launch per class with that class's shape.
 hipError_t launch_route(const QueryArgs& a, const RouteConfig& r, hipStream_t st);
@@ -266,6 +287,9 @@ hipError_t launch_condense_count(const CondArgs& c, hipStream_t st);
 hipError_t launch_condense_scan(const CondArgs& c, unsigned long long* total_feats,
                                 hipStream_t st);
 hipError_t launch_condense_write(const CondArgs& c, hipStream_t st);
+// Sum of the condensed entries' location counts into *total (which the caller zeroes).
+hipError_t launch_condense_pairs(const unsigned int* idx, uint64_t nbc, unsigned long long* total,
+                                 hipStream_t st);
 hipError_t launch_condense_dump(const unsigned int* idx, uint64_t nbc, const uint32_t* val,
                                 uint32_t lo, uint32_t hi, unsigned long long* out, uint64_t cap,
                                 unsigned long long* count, hipStream_t st);
@@ -300,6 +324,22 @@ struct ScratchView {
 int classify_into(struct ::mc_db* db, const char* reads, const uint64_t* offsets,
                   uint32_t n_records, const struct mc_query_opts* opts, uint32_t* out_labels,
                   struct mc_tophit* out_top, const ScratchView& scratch, hipStream_t st);
+
+// Classification of the records [r0, r1) of a served batch (offsets: the
+// batch's offsets array) in three phases, each queued on st: phase 0 clears
+// `counters` (kNumQueryCounters u32 of device memory owned by the caller) and
+// queues the fast pass; phase 1 the large-list pass over the n_queued records
+// the fast pass passed on (counters[kQOverflow]); phase 2 the HBM-list pass
+// over those the large-list pass passed on (counters[kQHuge]). The caller
+// reads the counters back and queues phases 1 and 2 only when they hold
+// records: a large-list workgroup needs a CU of its own, which a busy device
+// frees only when its other kernels drain. The records' queue ids sit at
+// 2 r0 .. 2 r1 of st's workspace queue, which prepare_workspace must have
+// sized for r1 records.
+int served_classify(struct ::mc_db* db, int phase, const char* reads, const uint64_t* offsets,
+                    uint32_t r0, uint32_t r1, const struct mc_query_opts& opts,
+                    uint32_t* out_labels, struct mc_tophit* out_top, uint32_t* counters,
+                    uint32_t n_queued, hipStream_t st);
 
 // Set the calling thread's mc_last_error text; returns code.
 int set_error(int code, const char* msg);

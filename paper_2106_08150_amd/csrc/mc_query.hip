@@ -244,12 +244,7 @@ __device__ bool lookup_cond(const QueryArgs& a, const uint32_t* F, uint32_t nf, 
             // lane r holds run r; an inclusive scan of the counts gives every
             // run's first list position
             wave_lds_sync();
-            uint32_t cnt = 0, off_lo = 0, off_hi = 0;
-            if (lane < nrun) {
-                cnt = runs[3 * lane + 0];
-                off_lo = runs[3 * lane + 1];
-                off_hi = runs[3 * lane + 2];
-            }
+            const uint32_t cnt = lane < nrun ? runs[3 * lane + 0] : 0u;
             uint32_t incl = cnt;
 #pragma unroll
             for (int d = 1; d < 32; d <<= 1) {
@@ -369,6 +364,25 @@ __device__ __forceinline__ void write_result(const QueryArgs& a, uint32_t rec, u
     }
 }
 
+// floor(n / S): a multiply-high for the counts of any real record, a 64-bit
+// division only past 2^32.
+__device__ __forceinline__ uint64_t div_by_S(const QueryArgs& a, uint64_t n) {
+    if ((n >> 32) == 0) {
+        const uint32_t x = (uint32_t)n, t = __umulhi(a.divS.m, x);
+        return (t + ((x - t) >> a.divS.sh1)) >> a.divS.sh2;
+    }
+    return n / a.S;
+}
+
+// Windows of a mate of len bases, and the windows of reference a fragment of
+// F bases can touch (sws).
+__device__ __forceinline__ uint64_t mate_windows(const QueryArgs& a, uint64_t len) {
+    return len < a.k ? 0 : div_by_S(a, len - a.k + a.S);
+}
+__device__ __forceinline__ uint32_t fragment_sws(const QueryArgs& a, uint64_t F) {
+    return F < a.k ? 1u : (uint32_t)(div_by_S(a, F - a.k + a.S - 1) + 1);
+}
+
 // One window of a record: its bytes [lo, hi) inside the mate [vlo, vhi), its
 // number of k-mer starts and the offset of its first base in the staged words.
 struct WinRef {
@@ -442,12 +456,12 @@ __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>
     const uint64_t len[2] = {o1 - o0, o2 - o1};
     uint64_t F = len[0] + len[1];
     if (len[0] > 0 && len[1] > 0 && a.insert_size > F) F = a.insert_size;
-    const uint32_t sws = F < a.k ? 1u : (uint32_t)((F - a.k + a.S - 1) / a.S + 1);
+    const uint32_t sws = fragment_sws(a, F);
 
     // windows of the record, mate 1's then mate 2's, sketched two at a time
     uint64_t nws[2];
     for (int sg = 0; sg < 2; ++sg)
-        nws[sg] = len[sg] < a.k ? 0 : (len[sg] - a.k + 1 + a.S - 1) / a.S;
+        nws[sg] = mate_windows(a, len[sg]);
     const uint64_t nwt = nws[0] + nws[1];
     uint32_t nlist = 0, nf = 0;
     bool fits = true;
@@ -754,10 +768,10 @@ __device__ void classify_huge_record(const QueryArgs& a, uint32_t rec, const Hug
     const uint64_t len[2] = {o1 - o0, o2 - o1};
     uint64_t F = len[0] + len[1];
     if (len[0] > 0 && len[1] > 0 && a.insert_size > F) F = a.insert_size;
-    const uint32_t sws = F < a.k ? 1u : (uint32_t)((F - a.k + a.S - 1) / a.S + 1);
+    const uint32_t sws = fragment_sws(a, F);
     uint64_t nws[2];
     for (int sg = 0; sg < 2; ++sg)
-        nws[sg] = len[sg] < a.k ? 0 : (len[sg] - a.k + 1 + a.S - 1) / a.S;
+        nws[sg] = mate_windows(a, len[sg]);
     const uint64_t nwt = nws[0] + nws[1];
     if (tid == 0) {
         L.nfeat = 0;
@@ -1026,7 +1040,7 @@ __device__ __forceinline__ uint64_t record_windows(const QueryArgs& a, uint32_t 
     uint64_t nw = 0;
     const uint64_t len[2] = {o1 - o0, o2 - o1};
     for (int sg = 0; sg < 2; ++sg)
-        nw += len[sg] < a.k ? 0 : (len[sg] - a.k + 1 + a.S - 1) / a.S;
+        nw += mate_windows(a, len[sg]);
     return nw;
 }
 
@@ -1091,8 +1105,8 @@ inline unsigned large_pass_groups(uint32_t n_records) {
 }
 
 template <bool C>
-void launch_large_c(const QueryArgs& a, hipStream_t st) {
-    const dim3 grid(large_pass_groups(a.n_records));
+void launch_large_c(const QueryArgs& a, uint32_t groups, hipStream_t st) {
+    const dim3 grid(groups ? std::min<uint32_t>(groups, 512u) : large_pass_groups(a.n_records));
     if (a.S <= 64)
         hipLaunchKernelGGL((k_classify<kListLarge, 1, 1, C>), grid, dim3(64), 0, st, a, 1, -1);
     else if (a.S <= 128)
@@ -1142,10 +1156,10 @@ hipError_t launch_classify_huge(const QueryArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_classify_large(const QueryArgs& a, hipStream_t st) {
+hipError_t launch_classify_large(const QueryArgs& a, hipStream_t st, uint32_t groups) {
     if (a.n_records == 0) return hipSuccess;
-    if (a.cval) launch_large_c<true>(a, st);
-    else launch_large_c<false>(a, st);
+    if (a.cval) launch_large_c<true>(a, groups, st);
+    else launch_large_c<false>(a, groups, st);
     return hipGetLastError();
 }
 

@@ -44,12 +44,19 @@ struct Job {
     const uint32_t* parents = nullptr;
     uint32_t n_nodes = 0;
     Clock::time_point t_submit;
+    // stages of a classification batch (set by the dispatcher and its worker)
+    Clock::time_point t_admit, t_copied, t_launched;
 };
 
 struct Done {
     int status = MC_OK;
     double ms = 0.0;
+    mc_batch_times times{};
 };
+
+double ms_between(Clock::time_point a, Clock::time_point b) {
+    return std::chrono::duration<double, std::milli>(b - a).count();
+}
 
 // One in-flight slot: a worker thread with its own stream, device buffers and
 // pinned staging. The dispatcher hands it one batch at a time.
@@ -119,10 +126,18 @@ struct mc_server {
 
     // Record a finished job (caller holds mu).
     void finish_locked(const Job& j, int status) {
-        const double ms =
-            std::chrono::duration<double, std::milli>(Clock::now() - j.t_submit).count();
-        done[j.ticket] = Done{status, ms};
-        t_last = Clock::now();
+        const Clock::time_point now = Clock::now();
+        const double ms = ms_between(j.t_submit, now);
+        Done d{status, ms, {}};
+        if (!j.is_add && status == MC_OK) {
+            d.times.admit_ms = ms_between(j.t_submit, j.t_admit);
+            d.times.copy_ms = ms_between(j.t_admit, j.t_copied);
+            d.times.launch_ms = ms_between(j.t_copied, j.t_launched);
+            d.times.finish_ms = ms_between(j.t_launched, now);
+        }
+        d.times.total_ms = ms;
+        done[j.ticket] = d;
+        t_last = now;
         if (j.is_add) {
             additions += status == MC_OK;
         } else {
@@ -199,6 +214,14 @@ struct mc_server {
     // The reads keep their offsets: the classification's reads pointer is
     // the device buffer shifted by the batch's first offset, so the caller's
     // offsets are copied unchanged.
+    //
+    // Each chunk's fast pass counts the records it passes on in counters of
+    // its own; they come back with the results, and only chunks that passed
+    // records on get the large-list pass (then, the same way, the HBM-list
+    // pass). A large-list workgroup takes most of a CU's LDS and starts only
+    // on a CU that every other kernel has left: queued unconditionally next
+    // to other batches' kernels, it would hold up every batch until the
+    // device drains.
     int process(Slot& s, Job& j) {
         Turn turn{copy_mu, copy_cv, copy_turn, j.order};
         Turn launch{launch_turn_mu, launch_cv, launch_turn, j.order};
@@ -210,13 +233,21 @@ struct mc_server {
         const uint64_t off_labels = off_offsets + align256((seg + 1) * 8);
         const uint64_t off_top = off_labels + align256((uint64_t)j.n * 4);
         const uint64_t top_bytes = (uint64_t)j.n * j.opts.top_m * sizeof(mc_tophit);
-        const uint64_t total = off_top + (j.out_top ? align256(top_bytes) : 0);
+        const uint64_t off_cnt = off_top + (j.out_top ? align256(top_bytes) : 0);
+        const uint64_t total = off_cnt + align256(4ull * mc::kNumQueryCounters * kMaxChunks);
         uint64_t plan;
         {
             std::lock_guard<std::mutex> lk(mu);
             plan = s.d_plan;
         }
         int rc = grow(s, total, std::max(plan, total));
+        if (rc != MC_OK) return rc;
+        {
+            // the stream's record queues hold the whole batch (chunks queue
+            // their records at ids of their own)
+            std::lock_guard<std::mutex> lk(launch_mu);
+            rc = mc::prepare_workspace(db, s.stream, j.n);
+        }
         if (rc != MC_OK) return rc;
         std::memcpy(s.h_buf + off_offsets, j.offsets, (seg + 1) * 8);
         if (!j.pinned) std::memcpy(s.h_buf, j.reads + base, rb);
@@ -241,31 +272,60 @@ struct mc_server {
         const uint64_t* d_off = reinterpret_cast<const uint64_t*>(s.d_buf + off_offsets);
         uint32_t* d_lab = reinterpret_cast<uint32_t*>(s.d_buf + off_labels);
         mc_tophit* d_top = j.out_top ? reinterpret_cast<mc_tophit*>(s.d_buf + off_top) : nullptr;
-        for (uint32_t c = 0; c < n_chunks; ++c) {
+        uint32_t* d_cnt = reinterpret_cast<uint32_t*>(s.d_buf + off_cnt);
+        const uint32_t* h_cnt = reinterpret_cast<const uint32_t*>(s.h_buf + off_cnt);
+        auto chunk_cnt = [&](uint32_t c, int which) { return h_cnt[c * mc::kNumQueryCounters + which]; };
+        // phase p of chunk c (records [c chunk, (c + 1) chunk))
+        auto classify = [&](int phase, uint32_t c, uint32_t n_queued) {
             const uint64_t r0 = c * chunk, r1 = std::min<uint64_t>(j.n, r0 + chunk);
+            std::lock_guard<std::mutex> lk(launch_mu);
+            return mc::served_classify(db, phase, reads, d_off, (uint32_t)r0, (uint32_t)r1, j.opts,
+                                       d_lab, d_top, d_cnt + c * mc::kNumQueryCounters, n_queued,
+                                       s.stream);
+        };
+        for (uint32_t c = 0; c < n_chunks; ++c) {
             // the worker waits for the chunk's copy itself: a wait queued on
             // the slot's stream would sit in a hardware queue that streams
             // share (more streams than hardware queues) and hold up the work
             // of other slots queued behind it until this batch's copy is done
             if (hipEventSynchronize(s.copied[c]) != hipSuccess) return MC_ERR_HIP;
-            std::lock_guard<std::mutex> lk(launch_mu);
-            rc = mc_classify_ex(db, reads, d_off + per * r0, (uint32_t)(r1 - r0), &j.opts,
-                                d_lab + r0, d_top ? d_top + r0 * j.opts.top_m : nullptr,
-                                s.stream);
-            if (rc != MC_OK) return rc;
+            if (c + 1 == n_chunks) j.t_copied = Clock::now();
+            if ((rc = classify(0, c, 0)) != MC_OK) return rc;
         }
+        if (n_chunks == 0) j.t_copied = Clock::now();
+        j.t_launched = Clock::now();
         launch.pass();
-        // the results come back once, after the last chunk: a copy to host
-        // memory can hold the calling thread until the stream reaches it
-        // (small copies are done by the host), which between chunks would
-        // hold back the launches of the next chunks
-        e = hipMemcpyAsync(s.h_buf + off_labels, d_lab, (uint64_t)j.n * 4, hipMemcpyDeviceToHost,
-                           s.stream);
-        if (e == hipSuccess && d_top)
-            e = hipMemcpyAsync(s.h_buf + off_top, d_top, top_bytes, hipMemcpyDeviceToHost,
-                               s.stream);
-        if (e != hipSuccess) return MC_ERR_HIP;
-        if (hipStreamSynchronize(s.stream) != hipSuccess) return MC_ERR_HIP;
+        // counters and results come back together, once after the last
+        // chunk: a copy to host memory can hold the calling thread until the
+        // stream reaches it (small copies are done by the host), which
+        // between chunks would hold back the launches of the next chunks
+        auto copy_back = [&]() -> int {
+            hipError_t e2 = hipMemcpyAsync(s.h_buf + off_cnt, d_cnt,
+                                           4ull * mc::kNumQueryCounters * n_chunks,
+                                           hipMemcpyDeviceToHost, s.stream);
+            if (e2 == hipSuccess)
+                e2 = hipMemcpyAsync(s.h_buf + off_labels, d_lab, (uint64_t)j.n * 4,
+                                    hipMemcpyDeviceToHost, s.stream);
+            if (e2 == hipSuccess && d_top)
+                e2 = hipMemcpyAsync(s.h_buf + off_top, d_top, top_bytes, hipMemcpyDeviceToHost,
+                                    s.stream);
+            if (e2 != hipSuccess) return MC_ERR_HIP;
+            return hipStreamSynchronize(s.stream) == hipSuccess ? MC_OK : MC_ERR_HIP;
+        };
+        if (n_chunks && (rc = copy_back()) != MC_OK) return rc;
+        // the passes for records with long candidate lists, where there are any
+        for (int phase = 1; phase <= 2; ++phase) {
+            const int which = phase == 1 ? mc::kQOverflow : mc::kQHuge;
+            bool any = false;
+            for (uint32_t c = 0; c < n_chunks; ++c) {
+                const uint32_t q = chunk_cnt(c, which);
+                if (!q) continue;
+                any = true;
+                if ((rc = classify(phase, c, q)) != MC_OK) return rc;
+            }
+            if (!any) break;
+            if ((rc = copy_back()) != MC_OK) return rc;
+        }
         std::memcpy(j.out_labels, s.h_buf + off_labels, (size_t)j.n * 4);
         if (j.out_top) std::memcpy(j.out_top, s.h_buf + off_top, top_bytes);
         return MC_OK;
@@ -368,6 +428,7 @@ struct mc_server {
                 return free_slot != nullptr;
             });
             j.order = next_order++;
+            j.t_admit = Clock::now();
             free_slot->busy = true;
             free_slot->has_job = true;
             busy_slots += 1;
@@ -447,7 +508,8 @@ int mc_server_submit(mc_server* srv, const char* reads, const uint64_t* offsets,
             return mc::set_error(MC_ERR_INVALID_ARG, "offsets decrease");
     j.bytes = offsets[seg] - offsets[0];
     j.dev_need = align256(j.bytes) + align256((seg + 1) * 8) + align256((uint64_t)n_records * 4) +
-                 (out_top ? align256((uint64_t)n_records * opts->top_m * sizeof(mc_tophit)) : 0);
+                 (out_top ? align256((uint64_t)n_records * opts->top_m * sizeof(mc_tophit)) : 0) +
+                 align256(4ull * mc::kNumQueryCounters * kMaxChunks);
     if (j.dev_need > srv->budget)
         return mc::set_error(MC_ERR_INVALID_ARG, "batch larger than the memory budget");
     j.t_submit = Clock::now();
@@ -489,6 +551,13 @@ int mc_server_add_targets(mc_server* srv, const char* genomes, const uint64_t* l
 }
 
 int mc_server_wait(mc_server* srv, uint64_t ticket, double* latency_ms) {
+    mc_batch_times t{};
+    const int rc = mc_server_wait_times(srv, ticket, &t);
+    if (latency_ms) *latency_ms = t.total_ms;
+    return rc;
+}
+
+int mc_server_wait_times(mc_server* srv, uint64_t ticket, mc_batch_times* times) {
     if (!srv) return mc::set_error(MC_ERR_INVALID_ARG, "server is NULL");
     std::unique_lock<std::mutex> lk(srv->mu);
     if (ticket == 0 || ticket >= srv->next_ticket)
@@ -499,7 +568,7 @@ int mc_server_wait(mc_server* srv, uint64_t ticket, double* latency_ms) {
     srv->cv_done.wait(lk, [&] { return srv->done.count(ticket) != 0; });
     Done d = srv->done[ticket];
     srv->done.erase(ticket);
-    if (latency_ms) *latency_ms = d.ms;
+    if (times) *times = d.times;
     return d.status;
 }
 

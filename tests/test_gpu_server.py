@@ -156,3 +156,49 @@ def test_budget_shared_by_slots(torch):
         lab, top, _ = srv.wait(t)
         assert np.array_equal(lab, lab0) and np.array_equal(top, top0)
     srv.close()
+
+
+def test_long_records_through_the_server(torch):
+    """Records whose candidate lists outgrow the fast pass, in a batch of two
+    chunks (more than 131,072 records) and in small batches: the server runs
+    the large-list and HBM-list passes only for the chunks whose fast pass
+    queued records, and every label and top-hit list equals the plain
+    launch's; the long records also equal the oracle's. The reference set is
+    the tiny set plus 300 identical copies of another genome, whose features
+    each hold 254 locations: a 100 bp read of those copies gathers 4,064
+    locations (large-list pass), a 600 bp read 24,384 (HBM-list pass)."""
+    tiny = synth.tiny_genomes(length=20_000)
+    rep = synth.repeated_genome(300, 20_000, seed=21)
+    g = synth.Genomes(np.concatenate([tiny.text, rep.text]),
+                      np.concatenate([tiny.lengths, rep.lengths]),
+                      np.concatenate([tiny.taxa, np.full(rep.lengths.size, 10, np.uint32)]),
+                      tiny.parents)
+    db = mc.Database()
+    db.add_targets(torch.from_numpy(g.text.copy()).cuda(), g.lengths, g.taxa)
+    db.set_taxonomy(g.parents)
+    short = synth.sample_reads(tiny, 140_000, 100, seed=31)
+    r0 = rep.genome(0)
+    long_at = {7: r0[0:100], 70_001: r0[1000:1600], 131_080: r0[2000:2100],
+               139_990: synth.reverse_complement_text(r0[5000:5600])}
+    pieces = [long_at.get(i, short.text[int(short.offsets[i]):int(short.offsets[i + 1])])
+              for i in range(short.n_records)]
+    off = np.zeros(len(pieces) + 1, np.uint64)
+    off[1:] = np.cumsum([p.size for p in pieces])
+    big = synth.Reads(np.concatenate(pieces), off, False)
+    batches = [big, sub_batch(big, 0, 10), sub_batch(big, 70_000, 70_003),
+               sub_batch(big, 131_070, 131_100)]
+    alone = [plain(torch, db, r, False, min_hits=1) for r in batches]
+    srv = mc.Server(db, slots=3)
+    tickets = [srv.submit(r.text, r.offsets, with_top=True, min_hits=1) for r in batches]
+    for (lab0, top0), t in zip(alone, tickets):
+        lab, top, _ = srv.wait(t)
+        assert np.array_equal(lab, lab0) and np.array_equal(top, top0)
+    srv.close()
+    odb = orc.OracleDB()
+    odb.add_targets(g.text, g.lengths, g.taxa)
+    odb.set_taxonomy(g.parents)
+    lab0, top0 = alone[0]
+    for i in sorted(long_at):
+        ol, ot = odb.classify(big.text, big.offsets, first=i, count=1, min_hits=1)
+        assert ol[0] == lab0[i] and np.array_equal(ot[0], top0[i]), i
+        assert lab0[i] != 0xFFFFFFFF
