@@ -35,6 +35,15 @@ __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 // going through an int would materialise it in a VGPR first).
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
+// Whether the calling lane's bit of a wave-uniform mask is set (the mask is
+// used as the lane predicate as it is, without a per-lane shift and test).
+// Combining the ballots of single compares with scalar ANDs, then taking
+// lanes from the result, avoids the select-and-compare a ballot of a compound
+// predicate compiles to.
+__device__ __forceinline__ bool lane_in(uint64_t mask) {
+    return __builtin_amdgcn_inverse_ballot_w64(mask);
+}
+
 // Number of set bits of `mask` in lanes below the calling lane, plus `base`.
 __device__ __forceinline__ uint32_t rank_below(uint64_t mask, uint32_t base = 0u) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
@@ -660,8 +669,10 @@ __device__ __forceinline__ void sketch_pair(const Word* WA, uint32_t xA, uint32_
     wave_sort_halves(v);
     // previous lane's key (whole-wave shift right by one lane)
     const uint32_t prev = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x138, 0xF, 0xF, false);
-    const bool first = v != 0xFFFFFFFFu && (hl == 0 || v != prev);
-    const uint64_t bal = ballot(first);
+    // first of its value in its half: not the padding key, and lane 0 of the
+    // half or unlike the lane before
+    const uint64_t bal = ballot(v != 0xFFFFFFFFu) & (ballot(v != prev) | 0x0000000100000001ull);
+    const bool first = lane_in(bal);
     const uint32_t dA = popc64(bal & 0xFFFFFFFFull), dB = popc64(bal >> 32);
     const bool okA = modeA == 0 || (modeA == 1 && dA >= s);
     const bool okB = modeB == 0 || (modeB == 1 && dB >= s);

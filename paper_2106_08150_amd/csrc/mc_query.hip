@@ -56,6 +56,16 @@ struct QueryLds {
     uint32_t sel_t[kMaxTopM], sel_s[kMaxTopM], sel_b[kMaxTopM];   // top-m list
 };
 
+// Lanes below m (any m), computed in scalar registers.
+__device__ __forceinline__ uint64_t lanes_below(uint32_t m) {
+    return m >= 64u ? ~0ull : (1ull << m) - 1ull;
+}
+
+// Lanes of the first n 8-lane groups (n <= 8), computed in scalar registers.
+__device__ __forceinline__ uint64_t group_lanes(uint32_t n) {
+    return n >= 8u ? ~0ull : (1ull << (8u * n)) - 1ull;
+}
+
 // s_waitcnt immediate for vmcnt(0) with the other counters left alone (gfx9
 // encoding: vmcnt bits 3..0 and 15..14, expcnt 6..4, lgkmcnt 11..8).
 constexpr int kWaitVmem0 = 0x0F70;
@@ -84,7 +94,6 @@ __device__ bool lookup(const QueryArgs& a, const uint32_t* F, uint32_t nf, uint2
     constexpr uint32_t G = 8;            // groups of 8 lanes, one bucket line each
     const uint32_t lane = (uint32_t)lane_id();
     const uint32_t g = lane >> 3;
-    const uint32_t nb = (uint32_t)a.nb;
     for (uint32_t i = lane; i < nf; i += kWave) {
         const uint2 it = make_uint2(F[i], (uint32_t)home_bucket(F[i], a.nb));
         ring[i] = it;
@@ -111,8 +120,8 @@ __device__ bool lookup(const QueryArgs& a, const uint32_t* F, uint32_t nf, uint2
             b[q] = it.y;
         }
         // groups past the batch's last item load nothing (their lines would
-        // be fetched only to be ignored); `valid` below keeps their
-        // unloaded values out of every result
+        // be fetched only to be ignored); the mask of the groups holding an
+        // item keeps their unloaded values out of every result
 #pragma unroll
         for (int q = 0; q < NB; ++q)
             if (G * q + g < c) sl[q] = slot2[(uint64_t)b[q] * (kSlots / 2)];
@@ -122,29 +131,31 @@ __device__ bool lookup(const QueryArgs& a, const uint32_t* F, uint32_t nf, uint2
             if (G * q >= c) break;
             const uint32_t nv = min(c - G * q, G);   // groups holding an item
             probes += nv;
-            const bool valid = g < nv;
+            const uint64_t held = group_lanes(nv);
             const unsigned long long s0 = sl[q].x, s1 = sl[q].y;
-            const bool mine0 = valid && (uint32_t)(s0 >> 32) == f[q] && (uint32_t)s0 < kTombLoc;
-            const bool mine1 = valid && (uint32_t)(s1 >> 32) == f[q] && (uint32_t)s1 < kTombLoc;
-            const uint64_t hit0 = ballot(mine0), hit1 = ballot(mine1);
+            // a slot is the item's if it holds the item's feature and a
+            // stored location (not a tombstone); the last slot of a bucket is
+            // occupied unless its location word is all ones (empty)
+            const uint64_t hit0 = held & ballot((uint32_t)(s0 >> 32) == f[q]) &
+                                  ballot((uint32_t)s0 < kTombLoc);
+            const uint64_t hit1 = held & ballot((uint32_t)(s1 >> 32) == f[q]) &
+                                  ballot((uint32_t)s1 < kTombLoc);
             if (hit0 | hit1) {
                 const uint32_t n0 = popc64(hit0);
-                if (mine0) {
-                    const uint32_t i = rank_below(hit0, nlist);
-                    if (i < LCAP + kWave) list[i] = (uint32_t)s0;
-                }
-                if (mine1) {
+                // nlist <= LCAP here, so hit0's entries stay below LCAP + 64
+                if (lane_in(hit0)) list[rank_below(hit0, nlist)] = (uint32_t)s0;
+                if (lane_in(hit1)) {
                     const uint32_t i = rank_below(hit1, nlist + n0);
                     if (i < LCAP + kWave) list[i] = (uint32_t)s1;
                 }
                 nlist += n0 + popc64(hit1);
                 if (nlist > LCAP) return false;
             }
-            const bool occupied = valid && s1 != kEmpty;
-            const uint64_t full = ballot(occupied) & kLastSlots;
+            const uint64_t full = held & kLastSlots & ballot((uint32_t)s1 != 0xFFFFFFFFu);
             if (full) {
-                if (occupied && (lane & 7u) == 7u) {
-                    const uint32_t nxt = b[q] + 1u == nb ? 0u : b[q] + 1u;
+                if (lane_in(full)) {
+                    // the bucket count is read here, not held across the loop
+                    const uint32_t nxt = b[q] + 1u == (uint32_t)MC_COLD(nb) ? 0u : b[q] + 1u;
                     const uint32_t pos = (tail + rank_below(full)) & (kRing - 1u);
                     ring[pos] = make_uint2(f[q], nxt);
                     if (pos < kRingMirror) ring[pos + kRing] = make_uint2(f[q], nxt);
@@ -172,7 +183,6 @@ __device__ bool lookup_cond(const QueryArgs& a, const uint32_t* F, uint32_t nf, 
     constexpr uint32_t G = 8;
     const uint32_t lane = (uint32_t)lane_id();
     const uint32_t g = lane >> 3;
-    const uint32_t nb = (uint32_t)a.nb;
     for (uint32_t i = lane; i < nf; i += kWave) {
         const uint2 it = make_uint2(F[i], (uint32_t)home_bucket(F[i], a.nb));
         ring[i] = it;
@@ -203,21 +213,18 @@ __device__ bool lookup_cond(const QueryArgs& a, const uint32_t* F, uint32_t nf, 
             if (G * q >= c) break;
             const uint32_t nv = min(c - G * q, G);
             probes += nv;
-            const bool valid = g < nv;
-            const bool mine = valid && e[q].x == f[q] && e[q].y != 0u;
-            const bool inl = mine && e[q].y <= kCondInline;
-            const bool run = mine && e[q].y > kCondInline;
-            const uint64_t hitA = ballot(inl), hitB = ballot(inl && e[q].y == 2u);
-            const uint64_t hitR = ballot(run);
+            const uint64_t used = group_lanes(nv) & ballot(e[q].y != 0u);   // occupied entries
+            const uint64_t mine = used & ballot(e[q].x == f[q]);
+            const uint64_t small = ballot(e[q].y <= kCondInline);
+            const uint64_t hitA = mine & small, hitR = mine & ~small;
+            const uint64_t hitB = hitA & ballot(e[q].y == 2u);
             if (hitA | hitR) {
                 const uint32_t nA = popc64(hitA);
                 if (nlist + nA + popc64(hitB) > LCAP) return false;
-                if (inl) {
-                    list[rank_below(hitA, nlist)] = e[q].z;
-                    if (e[q].y == 2u) list[rank_below(hitB, nlist + nA)] = e[q].w;
-                }
+                if (lane_in(hitA)) list[rank_below(hitA, nlist)] = e[q].z;
+                if (lane_in(hitB)) list[rank_below(hitB, nlist + nA)] = e[q].w;
                 nlist += nA + popc64(hitB);
-                if (run) {
+                if (lane_in(hitR)) {
                     const uint32_t r = nrun + rank_below(hitR);
                     runs[3 * r + 0] = e[q].y;
                     runs[3 * r + 1] = e[q].z;
@@ -225,14 +232,18 @@ __device__ bool lookup_cond(const QueryArgs& a, const uint32_t* F, uint32_t nf, 
                 }
                 nrun += popc64(hitR);
             }
-            // a group that did not find its feature in a full line goes on
-            const uint64_t found = ballot(mine);
-            const bool gfound = ((found >> (lane & ~7u)) & 0xFFull) != 0;
-            const bool open = valid && e[q].y != 0u && !gfound;
-            const uint64_t full = ballot(open) & kLastSlots;
+            // a group that did not find its feature in a full line goes on:
+            // spread each group's found bits to its lowest lane, move that to
+            // its last lane, and keep the full lines' last lanes without one
+            uint64_t gf = mine;
+            gf |= gf >> 1;
+            gf |= gf >> 2;
+            gf |= gf >> 4;
+            const uint64_t full = used & kLastSlots & ~((gf & 0x0101010101010101ull) << 7);
             if (full) {
-                if (open && (lane & 7u) == 7u) {
-                    const uint32_t nxt = b[q] + 1u == nb ? 0u : b[q] + 1u;
+                if (lane_in(full)) {
+                    // the bucket count is read here, not held across the loop
+                    const uint32_t nxt = b[q] + 1u == (uint32_t)MC_COLD(nb) ? 0u : b[q] + 1u;
                     const uint32_t pos = (tail + rank_below(full)) & (kRing - 1u);
                     ring[pos] = make_uint2(f[q], nxt);
                     if (pos < kRingMirror) ring[pos + kRing] = make_uint2(f[q], nxt);
@@ -516,11 +527,11 @@ __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>
     // run-length encoding: uidx[u] = first index of the u-th distinct location
     uint32_t U = 0;
     for (uint32_t c = 0; c < n; c += kWave) {
-        uint32_t i = c + (uint32_t)lane;
-        bool first = false;
-        if (i < n) first = (i == 0) || (L.list[i] != L.list[i - 1]);
-        uint64_t mb = ballot(first);
-        if (first) L.rk.uidx[U + rank_below(mb)] = (uint16_t)i;
+        // i < n + 63 < LCAP + 64: every lane reads inside the list
+        const uint32_t i = c + (uint32_t)lane;
+        const uint32_t cur = L.list[i], prev = L.list[i ? i - 1u : 0u];
+        const uint64_t mb = lanes_below(n - c) & (ballot(cur != prev) | (c == 0 ? 1ull : 0ull));
+        if (lane_in(mb)) L.rk.uidx[U + rank_below(mb)] = (uint16_t)i;
         U += popc64(mb);
     }
     if (lane == 0) L.rk.uidx[U] = (uint16_t)n;
