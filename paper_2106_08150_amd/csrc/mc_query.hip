@@ -449,17 +449,130 @@ struct WaveStats {
     uint32_t features = 0, locations = 0, probes = 0, passed_on = 0;
 };
 
+// Label of a record from its top-m list (sel_* in LDS, nsel entries): the
+// best target's taxon on a clear lead, else the LCA of the taxa of the listed
+// targets within hit_diff of the best score.
+// The taxonomy arrays are read by scalar loads (every index is wave-uniform;
+// the arrays are small and do not change during a launch).
+typedef const __attribute__((address_space(4))) uint32_t ConstU32;
+__device__ __forceinline__ ConstU32* scalar_ptr(const uint32_t* p) {
+    return (ConstU32*)(uintptr_t)p;
+}
+
+__device__ __forceinline__ uint32_t lca_uniform(uint32_t a, uint32_t b, ConstU32* parent,
+                                                ConstU32* depth) {
+    uint32_t da = depth[a], db = depth[b];
+    while (da > db) { a = parent[a]; --da; }
+    while (db > da) { b = parent[b]; --db; }
+    while (a != b) { a = parent[a]; b = parent[b]; }
+    return a;
+}
+
+template <typename Lds>
+__device__ __forceinline__ uint32_t label_of(const QueryArgs& a, const Lds& L, uint32_t nsel) {
+    const uint32_t min_hits = MC_COLD(min_hits), hit_diff = MC_COLD(hit_diff);
+    uint32_t label = kNone;
+    const uint32_t c1 = uniform(L.sel_s[0]);
+    if (nsel > 0 && c1 >= min_hits) {
+        const uint32_t c2 = nsel > 1 ? uniform(L.sel_s[1]) : 0u;
+        ConstU32* const taxon = scalar_ptr(MC_COLD(target_taxon));
+        label = taxon[uniform(L.sel_t[0])];
+        if (c1 - c2 <= hit_diff) {
+            ConstU32* const parents = scalar_ptr(MC_COLD(parents));
+            ConstU32* const depth = scalar_ptr(MC_COLD(depth));
+            for (uint32_t x = 1; x < nsel; ++x)
+                if ((uint64_t)uniform(L.sel_s[x]) + hit_diff >= c1)
+                    label = lca_uniform(label, taxon[uniform(L.sel_t[x])], parents, depth);
+        }
+    }
+    return label;
+}
+
+// Whether the top-m rounds can stop after round m (score: its score): only
+// when no top-hit list is written; then after the first round if the best
+// score is below min_hits (unclassified), else at the first score more than
+// hit_diff below the best (later, lower entries take no part in the label).
+struct TopStop {
+    bool whole_list;
+    uint32_t min_hits, hit_diff, c_best = 0;
+    __device__ __forceinline__ bool operator()(uint32_t m, uint32_t score) {
+        if (whole_list) return false;
+        if (m == 0) {
+            c_best = score;
+            return score < min_hits;
+        }
+        return (uint64_t)score + hit_diff < c_best;
+    }
+};
+
+// Steps Q5-Q8 for a list of at most 64 locations (most records), held one a
+// lane: sorted in registers; the runs of equal locations (window counts) are
+// found with one ballot; distinct location u moves to lane u with its first
+// list index P(u) (the number of smaller locations), so that a range's score
+// is P(end) - P(u), end being the first distinct location past the range
+// (at most sws windows of one target); top-m by wave maxima as below.
+template <typename Lds>
+__device__ __forceinline__ void label_short_list(const QueryArgs& a, uint32_t rec, Lds& L,
+                                                 uint32_t n, uint32_t sws) {
+    const uint32_t lane = (uint32_t)lane_id();
+    uint32_t v[1] = {lane < n ? L.list[lane] : 0xFFFFFFFFu};
+    wave_sort<1>(v);
+    const uint32_t prev = (uint32_t)__builtin_amdgcn_mov_dpp((int)v[0], 0x138, 0xF, 0xF, false);
+    const uint64_t firsts = lanes_below(n) & (ballot(v[0] != prev) | 1ull);
+    const uint32_t U = popc64(firsts);
+    uint32_t* const first_of = L.sk.scratch;          // lane of distinct location u
+    if (lane_in(firsts)) first_of[rank_below(firsts)] = lane;
+    wave_lds_sync();
+    const uint32_t P = lane < U ? first_of[lane] : n;    // P(U) = n
+    const uint32_t loc = shfl_idx(v[0], (int)(P & 63u));
+    wave_lds_sync();
+    // end of the range of sws windows starting at loc (not past its target)
+    const uint32_t w = loc & kWindowMask, base = loc - w;
+    const uint32_t lim = base + min(w + sws, 1u << kWindowBits);
+    uint32_t end = lane + 1u;
+    const uint32_t steps = min(sws, U);
+    for (uint32_t j = 1; j < steps; ++j) {
+        const uint32_t l2 = shfl_idx(loc, (int)min(lane + j, 63u));
+        end += (lane + j < U && l2 < lim) ? 1u : 0u;
+    }
+    const uint32_t Pend = shfl_idx(P, (int)min(end, 63u));
+    const uint32_t score = (end >= U ? n : Pend) - P;
+    uint32_t key = lane < U ? (score << 16) | (0xFFFFu - lane) : 0u;
+    const uint32_t t = loc >> kWindowBits;
+    TopStop stop{MC_COLD(out_top) != nullptr, MC_COLD(min_hits), MC_COLD(hit_diff)};
+    const uint32_t top_m = MC_COLD(top_m);
+    uint32_t nsel = 0;
+    for (uint32_t m = 0; m < top_m; ++m) {
+        const uint32_t k = wave_max_u32(key);
+        if (k == 0) break;
+        const uint32_t sl = (uint32_t)__builtin_amdgcn_readlane((int)loc, (int)(0xFFFFu - (k & 0xFFFFu)));
+        if (lane == 0) {
+            L.sel_t[m] = sl >> kWindowBits;
+            L.sel_s[m] = k >> 16;
+            L.sel_b[m] = sl & kWindowMask;
+        }
+        nsel = m + 1;
+        if (stop(m, k >> 16)) break;
+        if (t == sl >> kWindowBits) key = 0;
+    }
+    wave_lds_sync();
+    write_result(a, rec, label_of(a, L, nsel), L, nsel);
+}
+
 template <uint32_t LCAP, int KPL, bool C>
 __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>& L, bool big,
                                 const Threshold& th, WaveStats& ws) {
     const int lane = lane_id();
+    // the record's offsets by scalar loads (rec is wave-uniform; the array
+    // does not change during the launch)
+    typedef const __attribute__((address_space(4))) uint64_t ConstU64;
+    ConstU64* const off = (ConstU64*)(uintptr_t)a.offsets;
     uint64_t o0, o1, o2;
     if (a.paired) {
-        o0 = a.offsets[2ull * rec]; o1 = a.offsets[2ull * rec + 1]; o2 = a.offsets[2ull * rec + 2];
+        o0 = off[2ull * rec]; o1 = off[2ull * rec + 1]; o2 = off[2ull * rec + 2];
     } else {
-        o0 = a.offsets[rec]; o1 = a.offsets[rec + 1ull]; o2 = o1;
+        o0 = off[rec]; o1 = off[rec + 1ull]; o2 = o1;
     }
-    o0 = uniform64(o0); o1 = uniform64(o1); o2 = uniform64(o2);
     if (o1 < o0 || o2 < o1) {           // malformed record: nothing to classify
         write_result(a, rec, kNone, L, 0);
         return;
@@ -522,6 +635,10 @@ __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>
     wave_lds_sync();
     const uint32_t n = nlist;
     ws.locations += n;
+    if (n <= (uint32_t)kWave) {
+        label_short_list(a, rec, L, n, sws);
+        return;
+    }
     sort_list<LCAP>(L.list, n);
 
     // run-length encoding: uidx[u] = first index of the u-th distinct location
@@ -565,17 +682,7 @@ __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>
     // with lower scores take no part in the LCA).
     uint32_t nsel = 0;
     const uint32_t top_m = MC_COLD(top_m);
-    const bool whole_list = MC_COLD(out_top) != nullptr;
-    const uint32_t min_hits = MC_COLD(min_hits), hit_diff = MC_COLD(hit_diff);
-    uint32_t c_best = 0;
-    auto decided = [&](uint32_t m, uint32_t score) {
-        if (whole_list) return false;
-        if (m == 0) {
-            c_best = score;
-            return score < min_hits;
-        }
-        return (uint64_t)score + hit_diff < c_best;
-    };
+    TopStop decided{MC_COLD(out_top) != nullptr, MC_COLD(min_hits), MC_COLD(hit_diff)};
     if (U <= (uint32_t)kWave) {          // one distinct location per lane
         uint32_t key = 0, t = kNone;
         if ((uint32_t)lane < U) {
@@ -620,20 +727,7 @@ __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>
         }
     }
 
-    // label: the best target's taxon on a clear lead, else the LCA of the
-    // taxa of the listed targets within hit_diff of the best score
-    uint32_t label = kNone;
-    if (nsel > 0 && L.sel_s[0] >= min_hits) {
-        const uint32_t c1 = L.sel_s[0], c2 = nsel > 1 ? L.sel_s[1] : 0u;
-        const uint32_t* const taxon = MC_COLD(target_taxon);
-        label = uniform(taxon[L.sel_t[0]]);
-        if (c1 - c2 <= hit_diff) {
-            for (uint32_t x = 1; x < nsel; ++x)
-                if ((uint64_t)L.sel_s[x] + hit_diff >= c1)
-                    label = uniform(lca(label, taxon[L.sel_t[x]], MC_COLD(parents), MC_COLD(depth)));
-        }
-    }
-    write_result(a, rec, label, L, nsel);
+    write_result(a, rec, label_of(a, L, nsel), L, nsel);
 }
 
 // Occupancy: the lookups' memory latency is hidden by other waves' work, so
