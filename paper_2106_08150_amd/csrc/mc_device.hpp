@@ -254,21 +254,23 @@ __device__ __forceinline__ Word load_word(uintptr_t a, uintptr_t vlo, uintptr_t 
     return w;
 }
 
-// Stage one dword (4 bases) of a word covering [A0, ...), A0 16-byte aligned:
-// dword d of word d >> 2 goes to byte 3 - (d & 3) of that word's code and mask
-// (first base in the top byte) and to byte d & 3 of its complement word.
-// Bytes outside [vlo, vhi) count as invalid; a
-// dword that does not overlap them is not read. Aligned 4-byte loads never
-// cross a page. Returns whether a byte inside [vlo, vhi) is not a base.
-__device__ __forceinline__ bool stage_dword(Word* W, uintptr_t A0, uint32_t d, uintptr_t vlo,
-                                            uintptr_t vhi) {
-    const uintptr_t a = A0 + 4u * d;
+// Stage one dword (4 bases) of a word covering [A0, ...): dword d of word
+// d >> 2 goes to byte 3 - (d & 3) of that word's code and mask (first base in
+// the top byte) and to byte d & 3 of its complement word. Positions are
+// 32-bit offsets from `base` (16-byte aligned), A0 a multiple of 16. Bytes
+// outside [vlo, vhi) count as invalid; a dword that does not overlap them is
+// not read. Aligned 4-byte loads never cross a page. Returns whether a byte
+// inside [vlo, vhi) is not a base.
+__device__ __forceinline__ bool stage_dword(Word* W, uintptr_t base, uint32_t A0, uint32_t d,
+                                            uint32_t vlo, uint32_t vhi) {
+    const uint32_t a = A0 + 4u * d;
     uint32_t c8 = 0u, m8 = 0xFFu, r8 = 0u;
     bool bad = false;
-    if (a + 4 > vlo && a < vhi) {
-        const uint32_t x = *reinterpret_cast<const __attribute__((address_space(1))) uint32_t*>(a);
-        const uint32_t lo = vlo > a ? (uint32_t)(vlo - a) : 0u;
-        const uint32_t hi = vhi - a < 4 ? (uint32_t)(vhi - a) : 4u;
+    if (a + 4u > vlo && a < vhi) {
+        const uint32_t x =
+            *reinterpret_cast<const __attribute__((address_space(1))) uint32_t*>(base + a);
+        const uint32_t lo = vlo > a ? vlo - a : 0u;
+        const uint32_t hi = vhi - a < 4u ? vhi - a : 4u;
         bad = encode4(x, inside_bytes(lo, hi), c8, m8, r8);
     }
     uint8_t* w = reinterpret_cast<uint8_t*>(W + (d >> 2));

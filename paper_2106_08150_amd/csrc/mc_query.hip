@@ -394,55 +394,74 @@ __device__ __forceinline__ uint32_t fragment_sws(const QueryArgs& a, uint64_t F)
     return F < a.k ? 1u : (uint32_t)(div_by_S(a, F - a.k + a.S - 1) + 1);
 }
 
-// One window of a record: its bytes [lo, hi) inside the mate [vlo, vhi), its
-// number of k-mer starts and the offset of its first base in the staged words.
+// One window of a record: its bytes [lo, hi) inside the mate [vlo, vhi), as
+// 32-bit offsets from the record's first byte rounded down to 16 bytes (the
+// staging base; records are shorter than 2^31 bytes), its number of k-mer
+// starts and the offset of its first base in the staged words.
 struct WinRef {
-    uintptr_t lo, hi, vlo, vhi;
-    uint32_t nk, x0;
+    uint32_t lo, hi, vlo, vhi, nk, x0;
 };
 
-// Window i of the record (mate 1's windows first); i >= nwt gives an empty one.
-__device__ __forceinline__ WinRef window_ref(const QueryArgs& a, uint64_t i, uint64_t nwt,
-                                             uint64_t nw0, uint64_t o0, uint64_t o1,
-                                             const uint64_t (&len)[2]) {
-    WinRef r{0, 0, 0, 0, 0u, 0u};
+// Window i of the record (mate 1's windows first; mate 2 follows mate 1);
+// i >= nwt gives an empty one. r0: the record's first byte from the base.
+__device__ __forceinline__ WinRef window_ref(const QueryArgs& a, uint32_t i, uint32_t nwt,
+                                             uint32_t nw0, uint32_t r0, const uint32_t (&len)[2]) {
+    WinRef r{0u, 0u, 0u, 0u, 0u, 0u};
     if (i >= nwt) return r;
     const int sg = i < nw0 ? 0 : 1;
-    const uint64_t j = sg ? i - nw0 : i;
-    r.vlo = (uintptr_t)(a.reads + (sg ? o1 : o0));
+    const uint32_t j = sg ? i - nw0 : i;
+    r.vlo = r0 + (sg ? len[0] : 0u);
     r.vhi = r.vlo + len[sg];
     r.lo = r.vlo + j * a.S;
-    r.hi = r.lo + a.w < r.vhi ? r.lo + a.w : r.vhi;
-    const uint64_t n_starts = len[sg] - a.k + 1;
-    r.nk = (uint32_t)min((uint64_t)a.S, n_starts - j * a.S);
-    r.x0 = (uint32_t)(r.lo & 15u);
+    r.hi = min(r.lo + a.w, r.vhi);
+    r.nk = min(a.S, len[sg] - a.k + 1u - j * a.S);
+    r.x0 = r.lo & 15u;
     return r;
 }
 
 // Words staged for a window: its bytes from the 16-byte boundary below it, plus
 // one look-ahead word.
 __device__ __forceinline__ uint32_t staged_words(const WinRef& r) {
-    return r.nk ? (uint32_t)((r.hi - (r.lo & ~(uintptr_t)15) + 15) / 16) + 1u : 0u;
+    return r.nk ? (r.hi - (r.lo & ~15u) + 15u) / 16u + 1u : 0u;
 }
 
 // Stage two windows at once, A's words into W[0..) and B's into
 // W[kStageWords..), one dword (4 bases) per lane: a 150-base read's two
 // windows take a single pass of the wave. dirtyA / dirtyB (wave-uniform): a
 // staged byte of that window's mate is not a base.
-__device__ __forceinline__ void stage_pair(Word* W, const WinRef& A, const WinRef& B, int lane,
-                                           bool& dirtyA, bool& dirtyB) {
+__device__ __forceinline__ void stage_pair(Word* W, uintptr_t base, const WinRef& A,
+                                           const WinRef& B, int lane, bool& dirtyA,
+                                           bool& dirtyB) {
     const uint32_t ndA = 4u * staged_words(A), nd = ndA + 4u * staged_words(B);
     bool badA = false, badB = false;
     for (uint32_t q = (uint32_t)lane; q < nd; q += kWave) {
         const bool second = q >= ndA;
-        const WinRef& r = second ? B : A;
-        const bool bad = stage_dword(W + (second ? kStageWords : 0), r.lo & ~(uintptr_t)15,
-                                     second ? q - ndA : q, r.vlo, r.vhi);
+        const bool bad = stage_dword(W + (second ? kStageWords : 0), base,
+                                     (second ? B.lo : A.lo) & ~15u, second ? q - ndA : q,
+                                     second ? B.vlo : A.vlo, second ? B.vhi : A.vhi);
         badA |= bad && !second;
         badB |= bad && second;
     }
     dirtyA = ballot(badA) != 0;
     dirtyB = ballot(badB) != 0;
+}
+
+// A record's staging base and lengths, or false for a record of 2^31 bytes or
+// more (beyond every pass: left unclassified and counted as too long).
+struct RecordSpan {
+    uintptr_t base;
+    uint32_t r0;
+    uint32_t len[2];
+};
+__device__ __forceinline__ bool record_span(const QueryArgs& a, uint64_t o0, uint64_t o1,
+                                            uint64_t o2, RecordSpan& rs) {
+    if (o2 - o0 >= (1ull << 31)) return false;
+    const uintptr_t first = (uintptr_t)(a.reads + o0);
+    rs.base = first & ~(uintptr_t)15;
+    rs.r0 = (uint32_t)(first - rs.base);
+    rs.len[0] = (uint32_t)(o1 - o0);
+    rs.len[1] = (uint32_t)(o2 - o1);
+    return true;
 }
 
 struct WaveStats {
@@ -577,24 +596,29 @@ __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>
         write_result(a, rec, kNone, L, 0);
         return;
     }
-    const uint64_t len[2] = {o1 - o0, o2 - o1};
-    uint64_t F = len[0] + len[1];
-    if (len[0] > 0 && len[1] > 0 && a.insert_size > F) F = a.insert_size;
+    RecordSpan rs;
+    if (!record_span(a, o0, o1, o2, rs)) {
+        if (lane == 0) atomicAdd(&MC_COLD(counters)[kQTooLong], 1u);
+        write_result(a, rec, kNone, L, 0);
+        return;
+    }
+    uint64_t F = (uint64_t)rs.len[0] + rs.len[1];
+    if (rs.len[0] > 0 && rs.len[1] > 0 && a.insert_size > F) F = a.insert_size;
     const uint32_t sws = fragment_sws(a, F);
 
     // windows of the record, mate 1's then mate 2's, sketched two at a time
-    uint64_t nws[2];
+    uint32_t nws[2];
     for (int sg = 0; sg < 2; ++sg)
-        nws[sg] = mate_windows(a, len[sg]);
-    const uint64_t nwt = nws[0] + nws[1];
+        nws[sg] = (uint32_t)mate_windows(a, rs.len[sg]);
+    const uint32_t nwt = nws[0] + nws[1];
     uint32_t nlist = 0, nf = 0;
     bool fits = true;
-    for (uint64_t p = 0; p < nwt && fits; p += 2) {
+    for (uint32_t p = 0; p < nwt && fits; p += 2) {
         WinRef wr[2];
-        for (int h = 0; h < 2; ++h) wr[h] = window_ref(a, p + h, nwt, nws[0], o0, o1, len);
+        for (int h = 0; h < 2; ++h) wr[h] = window_ref(a, p + h, nwt, nws[0], rs.r0, rs.len);
         wave_lds_sync();
         bool dirtyA, dirtyB;
-        stage_pair(L.sk.stage, wr[0], wr[1], lane, dirtyA, dirtyB);
+        stage_pair(L.sk.stage, rs.base, wr[0], wr[1], lane, dirtyA, dirtyB);
         wave_lds_sync();
         uint32_t nA, nB;
         sketch_pair<KPL>(L.sk.stage, wr[0].x0, wr[0].nk, L.sk.stage + kStageWords, wr[1].x0, wr[1].nk,
@@ -870,29 +894,33 @@ __device__ void classify_huge_record(const QueryArgs& a, uint32_t rec, const Hug
     } else {
         o0 = a.offsets[rec]; o1 = a.offsets[rec + 1ull]; o2 = o1;
     }
-    const uint64_t len[2] = {o1 - o0, o2 - o1};
-    uint64_t F = len[0] + len[1];
-    if (len[0] > 0 && len[1] > 0 && a.insert_size > F) F = a.insert_size;
+    // a record of 2^31 bytes or more never comes here (the fast pass counts
+    // it as too long); were it to, it is counted the same way (overflow)
+    RecordSpan rs;
+    const bool spans = record_span(a, o0, o1, o2, rs);
+    if (!spans) rs = RecordSpan{0, 0u, {0u, 0u}};
+    uint64_t F = (uint64_t)rs.len[0] + rs.len[1];
+    if (rs.len[0] > 0 && rs.len[1] > 0 && a.insert_size > F) F = a.insert_size;
     const uint32_t sws = fragment_sws(a, F);
-    uint64_t nws[2];
+    uint32_t nws[2];
     for (int sg = 0; sg < 2; ++sg)
-        nws[sg] = mate_windows(a, len[sg]);
-    const uint64_t nwt = nws[0] + nws[1];
+        nws[sg] = (uint32_t)mate_windows(a, rs.len[sg]);
+    const uint32_t nwt = nws[0] + nws[1];
     if (tid == 0) {
         L.nfeat = 0;
         L.nloc = 0;
         L.ntarget = 0;
-        L.overflow = 0;
+        L.overflow = spans ? 0u : 1u;
     }
     __syncthreads();
 
     // sketches of all windows: each wave takes pairs of windows
-    for (uint64_t p = 2ull * wave; p < nwt; p += 2ull * kHugeWaves) {
+    for (uint32_t p = 2u * wave; p < nwt; p += 2u * kHugeWaves) {
         WinRef wr[2];
-        for (int x = 0; x < 2; ++x) wr[x] = window_ref(a, p + x, nwt, nws[0], o0, o1, len);
+        for (int x = 0; x < 2; ++x) wr[x] = window_ref(a, p + x, nwt, nws[0], rs.r0, rs.len);
         wave_lds_sync();
         bool dirtyA, dirtyB;
-        stage_pair(L.stage[wave], wr[0], wr[1], (int)lane, dirtyA, dirtyB);
+        stage_pair(L.stage[wave], rs.base, wr[0], wr[1], (int)lane, dirtyA, dirtyB);
         wave_lds_sync();
         uint32_t nA, nB;
         sketch_pair<KPL>(L.stage[wave], wr[0].x0, wr[0].nk, L.stage[wave] + kStageWords, wr[1].x0,
