@@ -415,6 +415,10 @@ def served_leg(args, g, gtext, torch, mc, synth):
     adds, base = {}, g
     for i in range(50, nb, 50):
         add, parents = synth.addition_genomes(base, 2, 10, 8e7, seed=4000 + i)
+        # the new genomes in pinned host memory, as a loader would leave them
+        # (both forms copy them from there)
+        text = torch.from_numpy(add.text).pin_memory()
+        add = synth.Genomes(text.numpy(), add.lengths, add.taxa, add.parents)
         adds[i] = (add, parents)
         base = synth.Genomes(base.text[:0], base.lengths[:0], base.taxa[:0], parents)
     log(f"served trace: {nb} batches, {int(sizes.sum())} reads, {len(adds)} additions")
