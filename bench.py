@@ -309,7 +309,8 @@ def served_run(torch, mc, db, batches, adds, arrivals, staging, slots=4, stage_l
 def slowest_stages(stages, lat, n=3):
     """Stage split of the n slowest batches (ms), slowest first."""
     order = np.argsort(lat)[::-1][:n]
-    keys = ("records", "submit_late_ms", "admit_ms", "copy_ms", "launch_ms", "finish_ms")
+    keys = ("records", "submit_late_ms", "admit_ms", "copy_ms", "launch_ms", "finish_ms",
+            "gpu_kernels_ms", "gpu_copy_back_ms")
     return [{k: (round(stages[i][k], 3) if k != "records" else stages[i][k]) for k in keys}
             for i in order]
 

@@ -450,6 +450,12 @@ typedef struct mc_batch_times {
                            theirs first)                                             */
     double finish_ms;   /* -> results in the caller's buffers (kernels, copy back)   */
     double total_ms;    /* submit -> results: the latency mc_server_wait reports     */
+    /* On the device's clock (events on the slot's stream), inside finish_ms and
+       the launches before it: from the stream reaching the batch's first
+       kernels to its last fast-pass kernel done, and from there to the copies
+       of its results back done. */
+    double gpu_kernels_ms;
+    double gpu_copy_back_ms;
 } mc_batch_times;
 
 /* mc_server_wait with the batch's latency split by stage (times may be NULL). */

@@ -100,7 +100,7 @@ class ServerOpts(C.Structure):
 
 class BatchTimes(C.Structure):
     _fields_ = [(n, C.c_double) for n in ("admit_ms", "copy_ms", "launch_ms", "finish_ms",
-                                          "total_ms")]
+                                          "total_ms", "gpu_kernels_ms", "gpu_copy_back_ms")]
 
     def as_dict(self) -> dict:
         return {n: getattr(self, n) for n, _ in self._fields_}

@@ -61,11 +61,6 @@ __device__ __forceinline__ uint64_t lanes_below(uint32_t m) {
     return m >= 64u ? ~0ull : (1ull << m) - 1ull;
 }
 
-// Lanes of the first n 8-lane groups (n <= 8), computed in scalar registers.
-__device__ __forceinline__ uint64_t group_lanes(uint32_t n) {
-    return n >= 8u ? ~0ull : (1ull << (8u * n)) - 1ull;
-}
-
 // s_waitcnt immediate for vmcnt(0) with the other counters left alone (gfx9
 // encoding: vmcnt bits 3..0 and 15..14, expcnt 6..4, lgkmcnt 11..8).
 constexpr int kWaitVmem0 = 0x0F70;
@@ -131,7 +126,9 @@ __device__ bool lookup(const QueryArgs& a, const uint32_t* F, uint32_t nf, uint2
             if (G * q >= c) break;
             const uint32_t nv = min(c - G * q, G);   // groups holding an item
             probes += nv;
-            const uint64_t held = group_lanes(nv);
+            // lanes of the groups holding an item: one vector compare (scalar
+            // issue, not vector issue, limits this kernel)
+            const uint64_t held = ballot(g < nv);
             const unsigned long long s0 = sl[q].x, s1 = sl[q].y;
             // a slot is the item's if it holds the item's feature and a
             // stored location (not a tombstone); the last slot of a bucket is
@@ -213,7 +210,7 @@ __device__ bool lookup_cond(const QueryArgs& a, const uint32_t* F, uint32_t nf, 
             if (G * q >= c) break;
             const uint32_t nv = min(c - G * q, G);
             probes += nv;
-            const uint64_t used = group_lanes(nv) & ballot(e[q].y != 0u);   // occupied entries
+            const uint64_t used = ballot(g < nv) & ballot(e[q].y != 0u);   // occupied entries
             const uint64_t mine = used & ballot(e[q].x == f[q]);
             const uint64_t small = ballot(e[q].y <= kCondInline);
             const uint64_t hitA = mine & small, hitR = mine & ~small;

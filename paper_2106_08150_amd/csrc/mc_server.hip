@@ -46,6 +46,7 @@ struct Job {
     Clock::time_point t_submit;
     // stages of a classification batch (set by the dispatcher and its worker)
     Clock::time_point t_admit, t_copied, t_launched;
+    float gpu_kernels_ms = 0.f, gpu_copy_back_ms = 0.f;
 };
 
 struct Done {
@@ -67,11 +68,13 @@ constexpr uint32_t kMaxChunks = 16;
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t copied[kMaxChunks] = {};   // chunk c of its batch is on the device
+    hipEvent_t t_kernels = nullptr, t_kernels_done = nullptr, t_back = nullptr;   // timing
     char* d_buf = nullptr;
     uint64_t d_cap = 0;
     uint64_t d_plan = 0;         // device bytes granted by admission (guarded by the
                                  // server mutex); the worker grows d_buf to it
     char* h_buf = nullptr;       // pinned
+    char* h_dev = nullptr;       // h_buf as the device addresses it
     uint64_t h_cap = 0;
     bool busy = false;           // owned by a batch (guarded by the server mutex)
     bool has_job = false;
@@ -81,6 +84,18 @@ struct Slot {
 };
 
 uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
+
+// A batch's results (labels, top hits, pass counters: one contiguous, 16-byte
+// aligned region of the slot's device buffer) stored by the device straight
+// into the slot's pinned host buffer. A copy-engine transfer back would queue
+// behind other batches' large host-to-device copies; these stores take the
+// other direction of the host link and finish with the kernel.
+__global__ __launch_bounds__(256) void k_publish(const uint4* __restrict__ src,
+                                                 uint4* __restrict__ dst, uint64_t n16) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
 
 // Slot buffers grow in steps of this size (not by doubling, so that the
 // capacity admission counts stays close to what batches need).
@@ -134,6 +149,8 @@ struct mc_server {
             d.times.copy_ms = ms_between(j.t_admit, j.t_copied);
             d.times.launch_ms = ms_between(j.t_copied, j.t_launched);
             d.times.finish_ms = ms_between(j.t_launched, now);
+            d.times.gpu_kernels_ms = j.gpu_kernels_ms;
+            d.times.gpu_copy_back_ms = j.gpu_copy_back_ms;
         }
         d.times.total_ms = ms;
         done[j.ticket] = d;
@@ -166,6 +183,11 @@ struct mc_server {
             s.h_cap = 0;
             if (hipHostMalloc((void**)&s.h_buf, cap, hipHostMallocDefault) != hipSuccess)
                 return MC_ERR_OOM;
+            if (hipHostGetDevicePointer((void**)&s.h_dev, s.h_buf, 0) != hipSuccess) {
+                (void)hipHostFree(s.h_buf);
+                s.h_buf = nullptr;
+                return MC_ERR_HIP;
+            }
             // touch every page now: a page's first write otherwise faults in the
             // batch that reaches it (about 1.5 us a 4-KiB page, milliseconds a batch)
             std::memset(s.h_buf, 0, cap);
@@ -290,8 +312,10 @@ struct mc_server {
             // of other slots queued behind it until this batch's copy is done
             if (hipEventSynchronize(s.copied[c]) != hipSuccess) return MC_ERR_HIP;
             if (c + 1 == n_chunks) j.t_copied = Clock::now();
+            if (c == 0 && hipEventRecord(s.t_kernels, s.stream) != hipSuccess) return MC_ERR_HIP;
             if ((rc = classify(0, c, 0)) != MC_OK) return rc;
         }
+        if (n_chunks && hipEventRecord(s.t_kernels_done, s.stream) != hipSuccess) return MC_ERR_HIP;
         if (n_chunks == 0) j.t_copied = Clock::now();
         j.t_launched = Clock::now();
         launch.pass();
@@ -299,20 +323,23 @@ struct mc_server {
         // chunk: a copy to host memory can hold the calling thread until the
         // stream reaches it (small copies are done by the host), which
         // between chunks would hold back the launches of the next chunks
+        // [off_labels, off_cnt + the counters): labels, top hits, counters
+        const uint64_t n16 = (off_cnt + 4ull * mc::kNumQueryCounters * n_chunks - off_labels + 15) / 16;
         auto copy_back = [&]() -> int {
-            hipError_t e2 = hipMemcpyAsync(s.h_buf + off_cnt, d_cnt,
-                                           4ull * mc::kNumQueryCounters * n_chunks,
-                                           hipMemcpyDeviceToHost, s.stream);
-            if (e2 == hipSuccess)
-                e2 = hipMemcpyAsync(s.h_buf + off_labels, d_lab, (uint64_t)j.n * 4,
-                                    hipMemcpyDeviceToHost, s.stream);
-            if (e2 == hipSuccess && d_top)
-                e2 = hipMemcpyAsync(s.h_buf + off_top, d_top, top_bytes, hipMemcpyDeviceToHost,
-                                    s.stream);
+            const unsigned grid = (unsigned)std::min<uint64_t>(1024, (n16 + 255) / 256);
+            hipLaunchKernelGGL(k_publish, dim3(grid), dim3(256), 0, s.stream,
+                               reinterpret_cast<const uint4*>(s.d_buf + off_labels),
+                               reinterpret_cast<uint4*>(s.h_dev + off_labels), n16);
+            hipError_t e2 = hipGetLastError();
+            if (e2 == hipSuccess) e2 = hipEventRecord(s.t_back, s.stream);
             if (e2 != hipSuccess) return MC_ERR_HIP;
             return hipStreamSynchronize(s.stream) == hipSuccess ? MC_OK : MC_ERR_HIP;
         };
-        if (n_chunks && (rc = copy_back()) != MC_OK) return rc;
+        if (n_chunks) {
+            if ((rc = copy_back()) != MC_OK) return rc;
+            (void)hipEventElapsedTime(&j.gpu_kernels_ms, s.t_kernels, s.t_kernels_done);
+            (void)hipEventElapsedTime(&j.gpu_copy_back_ms, s.t_kernels_done, s.t_back);
+        }
         // the passes for records with long candidate lists, where there are any
         for (int phase = 1; phase <= 2; ++phase) {
             const int which = phase == 1 ? mc::kQOverflow : mc::kQHuge;
@@ -469,6 +496,8 @@ mc_server* mc_server_create(mc_db* db, const mc_server_opts* opts) {
         ok = ok && hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess;
         for (auto& ev : sl.copied)
             ok = ok && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
+        for (hipEvent_t* ev : {&sl.t_kernels, &sl.t_kernels_done, &sl.t_back})
+            ok = ok && hipEventCreate(ev) == hipSuccess;
         ok = ok && mc_server::grow(sl, s->staging, initial) == MC_OK;
         sl.d_plan = sl.d_cap;
         // the slot stream's query workspace, sized for a whole chunk: a
@@ -624,6 +653,8 @@ int mc_server_destroy(mc_server* srv) {
         (void)hipHostFree(s.h_buf);
         if (s.stream) (void)hipStreamDestroy(s.stream);
         for (auto& ev : s.copied)
+            if (ev) (void)hipEventDestroy(ev);
+        for (hipEvent_t ev : {s.t_kernels, s.t_kernels_done, s.t_back})
             if (ev) (void)hipEventDestroy(ev);
     }
     if (srv->copy_stream) {

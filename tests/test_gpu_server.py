@@ -51,8 +51,14 @@ def test_results_identical_alone_and_in_the_mix(torch):
     srv = mc.Server(db, slots=3)
     tickets = [srv.submit(r.text, r.offsets, paired=p, with_top=True,
                           insert_size=400 if p else 0) for r, p in batches]
-    for (lab0, top0), t in zip(alone, tickets):
-        lab, top, ms = srv.wait(t)
+    for i, ((lab0, top0), t) in enumerate(zip(alone, tickets)):
+        if i % 2:
+            lab, top, ms = srv.wait(t)
+        else:   # the stage split of a batch's latency adds up to it
+            lab, top, tm = srv.wait_times(t)
+            ms = tm["total_ms"]
+            stages = tm["admit_ms"] + tm["copy_ms"] + tm["launch_ms"] + tm["finish_ms"]
+            assert abs(stages - ms) < 1e-3 and min(tm.values()) >= 0
         assert ms >= 0
         assert np.array_equal(lab, lab0) and np.array_equal(top, top0)
     st = srv.stats()
