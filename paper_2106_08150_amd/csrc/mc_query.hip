@@ -81,10 +81,11 @@ constexpr uint64_t kLastSlots = 0x8080808080808080ull;
 // to bucket 0 when a wave starts), so groups past a batch's last item may read
 // any entry and their lines are simply ignored. Returns false once the list
 // outgrew LCAP (locations past LCAP + 64 are then not stored: the record goes
-// to the large-list pass).
+// to the large-list pass). junk holds one word per lane that lanes without a
+// hit store into.
 template <uint32_t LCAP>
 __device__ bool lookup(const QueryArgs& a, const uint32_t* F, uint32_t nf, uint2* ring,
-                       uint32_t* list, uint32_t& nlist, uint32_t& probes) {
+                       uint32_t* list, uint32_t* junk, uint32_t& nlist, uint32_t& probes) {
     constexpr int NB = 4;
     constexpr uint32_t G = 8;            // groups of 8 lanes, one bucket line each
     const uint32_t lane = (uint32_t)lane_id();
@@ -138,13 +139,15 @@ __device__ bool lookup(const QueryArgs& a, const uint32_t* F, uint32_t nf, uint2
             const uint64_t hit1 = held & ballot((uint32_t)(s1 >> 32) == f[q]) &
                                   ballot((uint32_t)s1 < kTombLoc);
             if (hit0 | hit1) {
+                // every lane stores both slots, those without a hit into a
+                // word of their own (no branch around the stores); nlist <=
+                // LCAP here, so hit0's entries stay below LCAP + 64
                 const uint32_t n0 = popc64(hit0);
-                // nlist <= LCAP here, so hit0's entries stay below LCAP + 64
-                if (lane_in(hit0)) list[rank_below(hit0, nlist)] = (uint32_t)s0;
-                if (lane_in(hit1)) {
-                    const uint32_t i = rank_below(hit1, nlist + n0);
-                    if (i < LCAP + kWave) list[i] = (uint32_t)s1;
-                }
+                const uint32_t i1 = rank_below(hit1, nlist + n0);
+                uint32_t* const d0 = lane_in(hit0) ? list + rank_below(hit0, nlist) : junk + lane;
+                uint32_t* const d1 = lane_in(hit1) && i1 < LCAP + kWave ? list + i1 : junk + lane;
+                *d0 = (uint32_t)s0;
+                *d1 = (uint32_t)s1;
                 nlist += n0 + popc64(hit1);
                 if (nlist > LCAP) return false;
             }
@@ -638,7 +641,8 @@ __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>
                                          reinterpret_cast<uint32_t*>(L.sk.stage), nlist,
                                          ws.probes);
             else
-                fits = lookup<LCAP>(a, L.sk.feats, nf, L.ring, L.list, nlist, ws.probes);
+                fits = lookup<LCAP>(a, L.sk.feats, nf, L.ring, L.list, L.sk.scratch, nlist,
+                                    ws.probes);
             nf = 0;
         }
     }
