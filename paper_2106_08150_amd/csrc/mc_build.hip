@@ -42,7 +42,9 @@ template <int KPL, bool kPairs>
 __global__ __launch_bounds__(kBuildThreads) void k_sketch(BuildArgs a) {
     __shared__ SketchLds L;
     const int tid = threadIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
+    // the wave index in a scalar register: the window loop and its bounds
+    // are then wave-uniform
+    const int wave = (int)uniform((uint32_t)tid >> 6), lane = tid & 63;
     const Threshold th(a.S, a.s);
     if (kPairs) {
         for (uint32_t p = tid; p < kScatGroups * kMaxParts; p += kBuildThreads) L.hist[p] = 0;
@@ -87,7 +89,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_sketch(BuildArgs a) {
             }
             uint32_t* sk = L.feats[wave];
             uint32_t n[2];
-            sketch_pair<KPL>(L.words, x0[0], nk[0], L.words, x0[1], nk[1], a.k, a.s, th, sk,
+            sketch_pair<KPL, true>(L.words, x0[0], nk[0], L.words, x0[1], nk[1], a.k, a.s, th, sk,
                              sk + kMaxSketch, L.scratch[wave], n[0], n[1], dirty, dirty);
             wave_lds_sync();
             // entry e of the pair: window e / s, sketch slot e % s

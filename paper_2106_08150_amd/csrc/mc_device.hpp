@@ -67,11 +67,11 @@ __device__ __forceinline__ uint32_t shfl_xor(uint32_t v, int m) {
 template <int M>
 __device__ __forceinline__ uint32_t xor_lanes(uint32_t v) {
     if constexpr (M == 1) {
-        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, true);
     } else if constexpr (M == 2) {
-        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, true);
     } else if constexpr (M == 8) {
-        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, false);
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xF, 0xF, true);
     } else if constexpr (M == 4 || M == 16) {
         return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, (M << 10) | 0x1F);
     } else {
@@ -195,24 +195,31 @@ __device__ __forceinline__ uint32_t pack_fields(uint32_t v) {
     return (t | (t >> 12)) & 0xFFu;
 }
 
-// Encode 4 ASCII bytes x (byte 0 = first base); ok: 0x80 in each byte that
-// lies inside the sequence. Bits 1..2 of a letter give its code,
-// ((x >> 1) ^ (x >> 2)) & 3 maps A/a C/c G/g T/t to 0 1 2 3; a byte is a base
-// iff it equals "acgt"[code] once lower-cased (v_perm looks the letter up).
-// c8: the 4 codes (those of invalid bases are arbitrary), first base in bits
-// 7..6; m8: 0b11 in the positions of invalid bases; r8: their complements,
-// first base in bits 1..0. Returns whether a byte inside the sequence is not
-// a base.
-__device__ __forceinline__ bool encode4(uint32_t x, uint32_t ok, uint32_t& c8, uint32_t& m8,
-                                        uint32_t& r8) {
-    const uint32_t c = ((x >> 1) ^ (x >> 2)) & 0x03030303u;
-    const uint32_t cc = c ^ 0x03030303u;
-    const uint32_t t2 = cc | (cc >> 6);
-    r8 = (t2 | (t2 >> 12)) & 0xFFu;
+// Codes of 4 ASCII bytes x (byte 0 = first base). Bits 1..2 of a letter give
+// its code, ((x >> 1) ^ (x >> 2)) & 3 maps A/a C/c G/g T/t to 0 1 2 3; a byte
+// is a base iff it equals "acgt"[code] once lower-cased (v_perm looks the
+// letter up). c: the 4 codes, one per byte (those of non-bases are
+// arbitrary). Returns 0x80 in each byte that is not a base.
+__device__ __forceinline__ uint32_t codes4(uint32_t x, uint32_t& c) {
+    c = ((x >> 1) ^ (x >> 2)) & 0x03030303u;
     const uint32_t expect = __builtin_amdgcn_perm(0u, 0x74676361u, c);
     const uint32_t diff = (x | 0x20202020u) ^ expect;           // zero byte: a base
     const uint32_t t = (diff & 0x7F7F7F7Fu) + 0x7F7F7F7Fu;
-    const uint32_t bad = (t | diff) & ok & 0x80808080u;          // 0x80 per non-base inside
+    return (t | diff) & 0x80808080u;
+}
+
+// Encode 4 ASCII bytes x; ok: 0x80 in each byte that lies inside the
+// sequence. c8: the 4 codes (those of invalid bases are arbitrary), first base
+// in bits 7..6; m8: 0b11 in the positions of invalid bases; r8: their
+// complements, first base in bits 1..0. Returns whether a byte inside the
+// sequence is not a base.
+__device__ __forceinline__ bool encode4(uint32_t x, uint32_t ok, uint32_t& c8, uint32_t& m8,
+                                        uint32_t& r8) {
+    uint32_t c;
+    const uint32_t bad = codes4(x, c) & ok;                      // 0x80 per non-base inside
+    const uint32_t cc = c ^ 0x03030303u;
+    const uint32_t t2 = cc | (cc >> 6);
+    r8 = (t2 | (t2 >> 12)) & 0xFFu;
     const uint32_t inv = bad | (~ok & 0x80808080u);               // 0x80 per invalid base
     c8 = pack_fields(c);
     m8 = pack_fields((inv >> 6) | (inv >> 7));
@@ -229,26 +236,41 @@ __device__ __forceinline__ uint32_t inside_bytes(uint32_t lo, uint32_t hi) {
 // one 16-byte load: an aligned 16-byte block never crosses a page, so it lies
 // in the same mapped page as the valid byte it contains. A word that does not
 // overlap is not read at all. `bad` is set if a byte inside [vlo, vhi) is not
-// a base.
+// a base. Words wholly inside [vlo, vhi) (nearly all) need no per-byte range
+// test, and words without an invalid base no mask packing.
 __device__ __forceinline__ Word load_word(uintptr_t a, uintptr_t vlo, uintptr_t vhi, bool& bad) {
     if (a + 16 <= vlo || a >= vhi) return Word{0u, 0xFFFFFFFFu, 0u, 0u};
     // the address is global memory; saying so gives a global (not flat) load
     typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
     const u32x4 v = *reinterpret_cast<const __attribute__((address_space(1))) u32x4*>(a);
-    // bytes [lo, hi) of the word lie inside [vlo, vhi)
-    const uint32_t lo = vlo > a ? (uint32_t)(vlo - a) : 0u;
-    const uint32_t hi = vhi - a < 16 ? (uint32_t)(vhi - a) : 16u;
-    uint32_t c[4], m[4], r[4];
+    uint32_t c[4], inv[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const uint32_t dlo = lo > 4u * i ? min(lo - 4u * i, 4u) : 0u;
-        const uint32_t dhi = hi > 4u * i ? min(hi - 4u * i, 4u) : 0u;
-        const uint32_t ok = dlo < dhi ? inside_bytes(dlo, dhi) : 0u;
-        bad |= encode4(i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w, ok, c[i], m[i], r[i]);
+    for (int i = 0; i < 4; ++i) inv[i] = codes4(i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w, c[i]);
+    if (a < vlo || a + 16 > vhi) {
+        // bytes [lo, hi) of the word lie inside [vlo, vhi)
+        const uint32_t lo = vlo > a ? (uint32_t)(vlo - a) : 0u;
+        const uint32_t hi = vhi - a < 16 ? (uint32_t)(vhi - a) : 16u;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t dlo = lo > 4u * i ? min(lo - 4u * i, 4u) : 0u;
+            const uint32_t dhi = hi > 4u * i ? min(hi - 4u * i, 4u) : 0u;
+            const uint32_t ok = dlo < dhi ? inside_bytes(dlo, dhi) : 0u;
+            bad |= (inv[i] & ok) != 0u;
+            inv[i] = (inv[i] & ok) | (~ok & 0x80808080u);
+        }
+    } else {
+        bad |= (inv[0] | inv[1] | inv[2] | inv[3]) != 0u;
     }
     Word w;
-    w.code = (c[0] << 24) | (c[1] << 16) | (c[2] << 8) | c[3];
-    w.mask = (m[0] << 24) | (m[1] << 16) | (m[2] << 8) | m[3];
+    w.code = (pack_fields(c[0]) << 24) | (pack_fields(c[1]) << 16) | (pack_fields(c[2]) << 8) |
+             pack_fields(c[3]);
+    w.mask = 0u;
+    if ((inv[0] | inv[1] | inv[2] | inv[3]) != 0u) {
+        uint32_t m = 0u;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) m = (m << 8) | pack_fields((inv[i] >> 6) | (inv[i] >> 7));
+        w.mask = m;
+    }
     w.rc = rc_word(w.code);
     w.pad = 0u;
     return w;
@@ -281,19 +303,21 @@ __device__ __forceinline__ bool stage_dword(Word* W, uintptr_t base, uint32_t A0
 }
 
 // Canonical k-mer (k <= 16) starting o bases into word pair (a, b), both
-// strands by a funnel shift: the forward k-mer from the code words, the
-// reverse complement (its first base the complement of the k-mer's last)
-// from the complement words, kmask = 4^k - 1. Without kCheck the caller knows
-// every base of the k-mer is valid; with it, returns false if one is not.
+// strands by a funnel shift: the forward k-mer is the top 2k bits of
+// (a:b) << 2o, the reverse complement (its first base the complement of the
+// k-mer's last) comes from the complement words, kmask = 4^k - 1. lo is b for
+// o > 0 and a itself for o = 0: the forward funnel shift by 32 - 2o (taken mod
+// 32) then needs no select between its two cases. Without kCheck the caller
+// knows every base of the k-mer is valid; with it, returns false if one is
+// not.
 template <bool kCheck>
-__device__ __forceinline__ bool kmer_of(const Word& a, const Word& b, uint32_t o, uint32_t k,
-                                        uint32_t kmask, uint32_t& canon) {
-    // the top 32 bits of (a:b) << 2o: a funnel shift for o > 0, a itself for 0
-    const uint32_t top = o ? __builtin_amdgcn_alignbit(a.code, b.code, 32u - 2u * o) : a.code;
+__device__ __forceinline__ bool kmer_of(const Word& a, const Word& lo, const Word& b, uint32_t o,
+                                        uint32_t k, uint32_t kmask, uint32_t& canon) {
+    const uint32_t top = __builtin_amdgcn_alignbit(a.code, lo.code, 32u - 2u * o);
     const uint32_t fwd = top >> (32 - 2 * k);
     bool bad = false;
     if constexpr (kCheck) {
-        const uint32_t mtop = o ? __builtin_amdgcn_alignbit(a.mask, b.mask, 32u - 2u * o) : a.mask;
+        const uint32_t mtop = __builtin_amdgcn_alignbit(a.mask, lo.mask, 32u - 2u * o);
         bad = (mtop >> (32 - 2 * k)) != 0u;
     }
     const uint32_t r = __builtin_amdgcn_alignbit(b.rc, a.rc, 2u * o) & kmask;
@@ -309,7 +333,7 @@ __device__ __forceinline__ uint32_t kmer_mask(uint32_t k) {
 // Returns false if any of its bases is invalid.
 __device__ __forceinline__ bool kmer_at(const Word* W, uint32_t x, uint32_t k, uint32_t& canon) {
     const uint32_t q = x >> 4, o = x & 15u;
-    return kmer_of<true>(W[q], W[q + 1], o, k, kmer_mask(k), canon);
+    return kmer_of<true>(W[q], W[q + (o != 0u)], W[q + 1], o, k, kmer_mask(k), canon);
 }
 
 // ------------------------------------------------------- bitonic in regs --
@@ -475,29 +499,50 @@ struct Threshold {
 // hashed to 0xFFFFFFFF (that value then still counts as a distinct feature).
 // kCheck = false: the caller knows the window holds no invalid base. K-mer
 // r*64 + lane starts 4r words after k-mer lane, at the same offset in its word.
-template <int KPL, bool kCheck>
+// kAll: every lane hashes, with no branch around lanes past nk (they read
+// staged words beyond the window and drop them; W must then hold 4 * KPL + 2
+// words from the window's first word on, x0 < 16). That saves the scalar
+// branch work per key where vector issue has room (the build); without it,
+// lanes past nk skip the hash.
+template <int KPL, bool kCheck, bool kAll = false>
 __device__ __forceinline__ bool window_keys_t(const Word* W, uint32_t x0, uint32_t nk, uint32_t k,
                                               uint32_t (&key)[KPL]) {
     const int lane = lane_id();
     const uint32_t x = x0 + (uint32_t)lane;
     const Word* Wq = W + (x >> 4);
     const uint32_t o = x & 15u;
+    const Word* Wl = Wq + (o != 0u);
     const uint32_t kmask = kmer_mask(k);
-    bool top = false;
+    if constexpr (kAll) {
+        uint32_t top = 0u;
 #pragma unroll
-    for (int r = 0; r < KPL; ++r) {
-        uint32_t i = (uint32_t)(r * kWave + lane);
-        key[r] = 0xFFFFFFFFu;
-        if (i < nk) {
+        for (int r = 0; r < KPL; ++r) {
+            const uint32_t i = (uint32_t)(r * kWave + lane);
             uint32_t c;
-            if (kmer_of<kCheck>(Wq[4 * r], Wq[4 * r + 1], o, k, kmask, c)) {
-                uint32_t h = h1(c);
-                key[r] = h;
-                top |= (h == 0xFFFFFFFFu);
+            const bool ok = kmer_of<kCheck>(Wq[4 * r], Wl[4 * r], Wq[4 * r + 1], o, k, kmask, c);
+            const uint32_t h = h1(c);
+            const bool use = i < nk && ok;
+            key[r] = use ? h : 0xFFFFFFFFu;
+            top |= use && h == 0xFFFFFFFFu ? 1u : 0u;
+        }
+        return ballot(top != 0u) != 0;
+    } else {
+        bool top = false;
+#pragma unroll
+        for (int r = 0; r < KPL; ++r) {
+            const uint32_t i = (uint32_t)(r * kWave + lane);
+            key[r] = 0xFFFFFFFFu;
+            if (i < nk) {
+                uint32_t c;
+                if (kmer_of<kCheck>(Wq[4 * r], Wl[4 * r], Wq[4 * r + 1], o, k, kmask, c)) {
+                    const uint32_t h = h1(c);
+                    key[r] = h;
+                    top |= (h == 0xFFFFFFFFu);
+                }
             }
         }
+        return ballot(top) != 0;
     }
-    return ballot(top) != 0;
 }
 
 template <int KPL>
@@ -643,8 +688,8 @@ __device__ __forceinline__ uint32_t half_candidates(const uint32_t (&key)[KPL], 
 // staged words must still be in place). All pointers are to LDS. Writes
 // skA[0..nA) and skB[0..nB). scratch: 64 words of LDS owned by the wave.
 // dirtyA / dirtyB (wave-uniform): the window may hold an invalid base; when
-// false its k-mers skip the validity test.
-template <int KPL>
+// false its k-mers skip the validity test. kAll: as for window_keys_t.
+template <int KPL, bool kAll = false>
 __device__ __forceinline__ void sketch_pair(const Word* WA, uint32_t xA, uint32_t nkA,
                                             const Word* WB, uint32_t xB, uint32_t nkB,
                                             uint32_t k, uint32_t s, const Threshold& th,
@@ -657,11 +702,11 @@ __device__ __forceinline__ void sketch_pair(const Word* WA, uint32_t xA, uint32_
     bool topA, topB;
     {
         uint32_t key[KPL];
-        topA = dirtyA ? window_keys_t<KPL, true>(WA, xA, nkA, k, key)
-                      : window_keys_t<KPL, false>(WA, xA, nkA, k, key);
+        topA = dirtyA ? window_keys_t<KPL, true, kAll>(WA, xA, nkA, k, key)
+                      : window_keys_t<KPL, false, kAll>(WA, xA, nkA, k, key);
         cA = half_candidates<KPL>(key, nkA, s, th, scratch, modeA);
-        topB = dirtyB ? window_keys_t<KPL, true>(WB, xB, nkB, k, key)
-                      : window_keys_t<KPL, false>(WB, xB, nkB, k, key);
+        topB = dirtyB ? window_keys_t<KPL, true, kAll>(WB, xB, nkB, k, key)
+                      : window_keys_t<KPL, false, kAll>(WB, xB, nkB, k, key);
         cB = half_candidates<KPL>(key, nkB, s, th, scratch + 32, modeB);
     }
     wave_lds_sync();
