@@ -283,23 +283,23 @@ __device__ __forceinline__ Word load_word(uintptr_t a, uintptr_t vlo, uintptr_t 
 // outside [vlo, vhi) count as invalid; a dword that does not overlap them is
 // not read. Aligned 4-byte loads never cross a page. Returns whether a byte
 // inside [vlo, vhi) is not a base.
-__device__ __forceinline__ bool stage_dword(Word* W, uintptr_t base, uint32_t A0, uint32_t d,
-                                            uint32_t vlo, uint32_t vhi) {
+__device__ __forceinline__ uint32_t stage_dword(Word* W, uintptr_t base, uint32_t A0, uint32_t d,
+                                                uint32_t vlo, uint32_t vhi) {
     const uint32_t a = A0 + 4u * d;
-    uint32_t c8 = 0u, m8 = 0xFFu, r8 = 0u;
-    bool bad = false;
-    if (a + 4u > vlo && a < vhi) {
-        const uint32_t x =
-            *reinterpret_cast<const __attribute__((address_space(1))) uint32_t*>(base + a);
-        const uint32_t lo = vlo > a ? vlo - a : 0u;
-        const uint32_t hi = vhi - a < 4u ? vhi - a : 4u;
-        bad = encode4(x, inside_bytes(lo, hi), c8, m8, r8);
-    }
+    // every lane loads (no branch): a dword outside [vlo, vhi) reads the
+    // nearest dword that overlaps it (vlo < vhi) and marks all its bytes
+    // invalid; its codes are then arbitrary
+    const uint32_t ac = min(max(a, vlo & ~3u), (vhi - 1u) & ~3u);
+    const uint32_t x = *reinterpret_cast<const __attribute__((address_space(1))) uint32_t*>(base + ac);
+    const uint32_t lo = vlo > a ? min(vlo - a, 4u) : 0u;
+    const uint32_t hi = vhi > a ? min(vhi - a, 4u) : 0u;
+    uint32_t c8, m8, r8;
+    const bool bad = encode4(x, lo < hi ? inside_bytes(lo, hi) : 0u, c8, m8, r8);
     uint8_t* w = reinterpret_cast<uint8_t*>(W + (d >> 2));
     w[3 - (d & 3u)] = (uint8_t)c8;
     w[7 - (d & 3u)] = (uint8_t)m8;
     w[8 + (d & 3u)] = (uint8_t)r8;
-    return bad;
+    return bad ? 1u : 0u;
 }
 
 // Canonical k-mer (k <= 16) starting o bases into word pair (a, b), both

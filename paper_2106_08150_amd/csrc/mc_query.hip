@@ -390,6 +390,13 @@ __device__ __forceinline__ uint64_t div_by_S(const QueryArgs& a, uint64_t n) {
 __device__ __forceinline__ uint64_t mate_windows(const QueryArgs& a, uint64_t len) {
     return len < a.k ? 0 : div_by_S(a, len - a.k + a.S);
 }
+// The same for a mate of a record shorter than 2^31 bytes: len - k + S then
+// fits 32 bits, so the division needs no 64-bit fallback.
+__device__ __forceinline__ uint32_t mate_windows32(const QueryArgs& a, uint32_t len) {
+    if (len < a.k) return 0u;
+    const uint32_t x = len - a.k + a.S, t = __umulhi(a.divS.m, x);
+    return (t + ((x - t) >> a.divS.sh1)) >> a.divS.sh2;
+}
 __device__ __forceinline__ uint32_t fragment_sws(const QueryArgs& a, uint64_t F) {
     return F < a.k ? 1u : (uint32_t)(div_by_S(a, F - a.k + a.S - 1) + 1);
 }
@@ -433,17 +440,19 @@ __device__ __forceinline__ void stage_pair(Word* W, uintptr_t base, const WinRef
                                            const WinRef& B, int lane, bool& dirtyA,
                                            bool& dirtyB) {
     const uint32_t ndA = 4u * staged_words(A), nd = ndA + 4u * staged_words(B);
-    bool badA = false, badB = false;
+    // the flags are vector words, not lane masks: merging lane masks across
+    // the loop took scalar instructions (scalar issue limits this kernel)
+    uint32_t badA = 0u, badB = 0u;
     for (uint32_t q = (uint32_t)lane; q < nd; q += kWave) {
         const bool second = q >= ndA;
-        const bool bad = stage_dword(W + (second ? kStageWords : 0), base,
-                                     (second ? B.lo : A.lo) & ~15u, second ? q - ndA : q,
-                                     second ? B.vlo : A.vlo, second ? B.vhi : A.vhi);
-        badA |= bad && !second;
-        badB |= bad && second;
+        const uint32_t bad = stage_dword(W + (second ? kStageWords : 0), base,
+                                         (second ? B.lo : A.lo) & ~15u, second ? q - ndA : q,
+                                         second ? B.vlo : A.vlo, second ? B.vhi : A.vhi);
+        badA |= second ? 0u : bad;
+        badB |= second ? bad : 0u;
     }
-    dirtyA = ballot(badA) != 0;
-    dirtyB = ballot(badB) != 0;
+    dirtyA = ballot(badA != 0u) != 0;
+    dirtyB = ballot(badB != 0u) != 0;
 }
 
 // A record's staging base and lengths, or false for a record of 2^31 bytes or
@@ -609,7 +618,7 @@ __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>
     // windows of the record, mate 1's then mate 2's, sketched two at a time
     uint32_t nws[2];
     for (int sg = 0; sg < 2; ++sg)
-        nws[sg] = (uint32_t)mate_windows(a, rs.len[sg]);
+        nws[sg] = mate_windows32(a, rs.len[sg]);
     const uint32_t nwt = nws[0] + nws[1];
     uint32_t nlist = 0, nf = 0;
     bool fits = true;
@@ -905,7 +914,7 @@ __device__ void classify_huge_record(const QueryArgs& a, uint32_t rec, const Hug
     const uint32_t sws = fragment_sws(a, F);
     uint32_t nws[2];
     for (int sg = 0; sg < 2; ++sg)
-        nws[sg] = (uint32_t)mate_windows(a, rs.len[sg]);
+        nws[sg] = mate_windows32(a, rs.len[sg]);
     const uint32_t nwt = nws[0] + nws[1];
     if (tid == 0) {
         L.nfeat = 0;
