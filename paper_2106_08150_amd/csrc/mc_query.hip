@@ -122,11 +122,11 @@ __device__ bool lookup(const QueryArgs& a, const uint32_t* F, uint32_t nf, uint2
         for (int q = 0; q < NB; ++q)
             if (G * q + g < c) sl[q] = slot2[(uint64_t)b[q] * (kSlots / 2)];
         head += c;
+        probes += c;
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
             if (G * q >= c) break;
             const uint32_t nv = min(c - G * q, G);   // groups holding an item
-            probes += nv;
             // lanes of the groups holding an item: one vector compare (scalar
             // issue, not vector issue, limits this kernel)
             const uint64_t held = ballot(g < nv);
@@ -400,6 +400,14 @@ __device__ __forceinline__ uint32_t mate_windows32(const QueryArgs& a, uint32_t 
 __device__ __forceinline__ uint32_t fragment_sws(const QueryArgs& a, uint64_t F) {
     return F < a.k ? 1u : (uint32_t)(div_by_S(a, F - a.k + a.S - 1) + 1);
 }
+// The same for a fragment below 2^32 bases: F - k + S - 1 fits 32 bits unless
+// F lies within 512 of 2^32 (S is at most 271).
+__device__ __forceinline__ uint32_t fragment_sws32(const QueryArgs& a, uint32_t F) {
+    if (F < a.k) return 1u;
+    if (F > 0xFFFFFE00u) return fragment_sws(a, F);
+    const uint32_t x = F - a.k + a.S - 1u, t = __umulhi(a.divS.m, x);
+    return ((t + ((x - t) >> a.divS.sh1)) >> a.divS.sh2) + 1u;
+}
 
 // One window of a record: its bytes [lo, hi) inside the mate [vlo, vhi), as
 // 32-bit offsets from the record's first byte rounded down to 16 bytes (the
@@ -611,9 +619,11 @@ __device__ void classify_record(const QueryArgs& a, uint32_t rec, QueryLds<LCAP>
         write_result(a, rec, kNone, L, 0);
         return;
     }
-    uint64_t F = (uint64_t)rs.len[0] + rs.len[1];
-    if (rs.len[0] > 0 && rs.len[1] > 0 && a.insert_size > F) F = a.insert_size;
-    const uint32_t sws = fragment_sws(a, F);
+    // the fragment: the record's length (below 2^31), or the insert size
+    // when that is longer and both mates are present
+    const uint32_t len = rs.len[0] + rs.len[1];
+    const uint32_t F = rs.len[0] > 0 && rs.len[1] > 0 && a.insert_size > len ? a.insert_size : len;
+    const uint32_t sws = fragment_sws32(a, F);
 
     // windows of the record, mate 1's then mate 2's, sketched two at a time
     uint32_t nws[2];
