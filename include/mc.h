@@ -123,14 +123,14 @@ mc_db* mc_db_create(uint32_t k, uint32_t window, uint32_t sketch_size,
                     uint32_t max_locations);
 
 /* Free every device and host resource of the handle. NULL is accepted.
- * Device blocks of 256 MiB or more (the table, build scratch) are freed, or
- * kept mapped for reuse if mc_set_cached_memory_limit allows it. */
+ * Device blocks of 1 MiB or more (the table, build scratch, query workspaces)
+ * are freed, or kept mapped for reuse if mc_set_cached_memory_limit allows it. */
 int mc_db_destroy(mc_db* db);
 
 /* Reuse of large device blocks (process-wide, every device). Mapping and
  * unmapping tens of GB costs far more than a build (hundreds of milliseconds
  * to seconds), so a process that rebuilds databases may keep released blocks
- * of 256 MiB or more mapped, idle, for later allocations of the library on the
+ * of 1 MiB or more mapped, idle, for later allocations of the library on the
  * same device (a block serves a request up to 25% smaller than itself), while
  * the idle blocks of a device stay within `bytes_per_device`. Default 0:
  * nothing is kept, every release frees at once. Idle blocks are memory the

@@ -164,18 +164,20 @@ uint64_t num_windows(uint64_t len, uint32_t k, uint32_t S) {
     return (len - k + 1 + S - 1) / S;
 }
 
-// Large device blocks can be kept for reuse after they are released: hipMalloc
-// and hipFree of tens of GB cost hundreds of milliseconds to seconds once the
+// Device blocks can be kept for reuse after they are released: hipMalloc and
+// hipFree of tens of GB cost hundreds of milliseconds to seconds once the
 // runtime stops deferring them (about 28 ms per GB to free and 4 ms per GB to
 // map), far more than the build that uses them, so a process that rebuilds
-// databases would pay that on every build. Keeping is opt-in
+// databases would pay that on every build; a new handle's query workspace
+// (record queues and HBM-list scratch, a few hundred MB) took about 0.4 ms
+// to map on its first classification. Keeping is opt-in
 // (mc_set_cached_memory_limit): a released block of at least kCacheMinBytes
 // stays mapped (idle) while the idle blocks of its device stay within the
 // limit; otherwise it is freed at once. An allocation takes an idle block of
 // its device whose size is within 25% above the request. An allocation that
 // fails releases every idle block of the device and tries once more.
 // mc_release_cached_memory() gives all idle blocks back.
-constexpr size_t kCacheMinBytes = size_t(256) << 20;
+constexpr size_t kCacheMinBytes = size_t(1) << 20;
 
 struct BlockCache {
     std::mutex mu;

@@ -1,8 +1,9 @@
 """Rebuilds on device blocks the library kept for reuse.
 
-Large blocks (the table here) released by one handle are handed to the next
-handle's allocations with the previous contents still in them; every result
-must be the same as on freshly mapped memory.
+Blocks released by one handle (the table, build scratch, the query workspace's
+record queues and HBM-list scratch) are handed to the next handle's
+allocations with the previous contents still in them; every result must be
+the same as on freshly mapped memory.
 """
 import numpy as np
 import pytest
