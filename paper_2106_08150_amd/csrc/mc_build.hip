@@ -38,8 +38,13 @@ __device__ __forceinline__ uint32_t part_of(uint32_t f, uint64_t nb, uint32_t sh
 //                   empty for n <= i < s, plus a histogram of the pairs' table
 //                   partitions per scatter group (the group of a tile's pairs
 //                   is that of the level-1 scatter chunk holding the tile).
+//
+// Eight waves a SIMD: with the 106 scalar registers it takes unbounded fewer
+// waves fit; the scalar spills that the 8-wave budget costs are cheaper than
+// the lost latency hiding (10.6 -> 9.9 ms on a 4 Gbp build).
 template <int KPL, bool kPairs>
-__global__ __launch_bounds__(kBuildThreads) void k_sketch(BuildArgs a) {
+__global__ __launch_bounds__(kBuildThreads) __attribute__((amdgpu_waves_per_eu(8)))
+void k_sketch(BuildArgs a) {
     __shared__ SketchLds L;
     const int tid = threadIdx.x;
     // the wave index in a scalar register: the window loop and its bounds
