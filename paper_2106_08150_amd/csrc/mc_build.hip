@@ -39,9 +39,9 @@ __device__ __forceinline__ uint32_t part_of(uint32_t f, uint64_t nb, uint32_t sh
 //                   partitions per scatter group (the group of a tile's pairs
 //                   is that of the level-1 scatter chunk holding the tile).
 //
-// Eight waves a SIMD: with the 106 scalar registers it takes unbounded fewer
-// waves fit; the scalar spills that the 8-wave budget costs are cheaper than
-// the lost latency hiding (10.6 -> 9.9 ms on a 4 Gbp build).
+// Eight waves a SIMD: left unbounded, the kernel takes 106 scalar registers
+// and fewer waves fit; the scalar spills that the 8-wave budget costs are
+// cheaper than the lost latency hiding (10.6 -> 9.9 ms on a 4 Gbp build).
 template <int KPL, bool kPairs>
 __global__ __launch_bounds__(kBuildThreads) __attribute__((amdgpu_waves_per_eu(8)))
 void k_sketch(BuildArgs a) {

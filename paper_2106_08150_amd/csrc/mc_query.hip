@@ -401,7 +401,7 @@ __device__ __forceinline__ uint32_t fragment_sws(const QueryArgs& a, uint64_t F)
     return F < a.k ? 1u : (uint32_t)(div_by_S(a, F - a.k + a.S - 1) + 1);
 }
 // The same for a fragment below 2^32 bases: F - k + S - 1 fits 32 bits unless
-// F lies within 512 of 2^32 (S is at most 271).
+// F lies within 512 of 2^32 (S is at most 256).
 __device__ __forceinline__ uint32_t fragment_sws32(const QueryArgs& a, uint32_t F) {
     if (F < a.k) return 1u;
     if (F > 0xFFFFFE00u) return fragment_sws(a, F);
